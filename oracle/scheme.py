@@ -1,0 +1,146 @@
+"""The fully discrete AP IMEX Runge-Kutta step (Algorithm 1 with the space
+discretisation of Section 3.2 and its high-order extension).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+State: (u1, u2, theta, v1, v2, q), each (ny, nx) float64.  One call advances one time
+step dt.  For each stage i, in the order of Algorithm 1:
+  1. v(i) = [tau eps^2 v^n - dt sum_{j<i} at_ij E(j) - dt sum_{j<i} a_ij v(j)] / kappa_i,
+     E(j) = (tau/4) D0_LF.B(u(j)) + tau eps^2 D_LF q(j) - F(u(j)),
+     kappa_i = tau eps^2 + dt a_ii;
+  2. (D_Delta - sigma_i) theta(i) = -sigma_i theta^n
+        + 1/(dt a_ii^2) sum_{j<i} a_ij D0.u(j) + 1/(dt a_ii) D0.u^n
+        - 1/a_ii sum_{j<=i} a_ij D0^2:B(v(j)) - 1/a_ii sum_{j<i} a_ij D_Delta theta(j),
+     sigma_i = 2 eps^2 / (dt a_ii)^2;
+  3. u(i) = u^n - dt sum_{j<=i} a_ij [D_LF.B(v(j)) + D0 theta(j)];
+  4. q(i) = [tau eps^2 q^n - dt sum_{j<=i} a_ij (tau/2) D0_LF.v(j)
+            - dt sum_{j<i} a_ij q(j)] / kappa_i.
+Steps 1 and 4 are the stage equations multiplied by tau eps^2, so they hold for
+tau = 0 and eps = 0.  If a_11 = 0 (types CK and ARS) the first stage is the state at
+time n.  The scheme must be globally stiffly accurate, so the new state is the last
+stage.
+
+Readings (each listed with its pin in the design notes):
+  * Sign of the last right-hand-side term of step 2: minus.  The printed algorithm
+    and fully discrete scheme show plus, but substituting step 3 into the theta
+    stage equation gives minus, and the proof of Theorem 3.4 uses minus.  Pinned by
+    the consistent-operator invariant (tests/test_scheme.py).
+  * Dissipation partner of D_LF.B(v(j)) in step 3: u(j-1) (u(0) := u^n for the first
+    solved stage).  The printed flux needs jumps of the unknown u, but u(j) is not
+    known when its own flux is formed; using the previous stage keeps step 3
+    explicit.  Parity unpinned beyond self-consistency (convergence tests).
+  * Helmholtz (0,0) mode set to mean(theta^n) (see helmholtz.py).
+"""
+
+import numpy as np
+
+from . import helmholtz
+from .d2q6 import flux_F
+
+
+class Params:
+    def __init__(self, eps, tau, dt):
+        if eps < 0 or tau < 0 or dt <= 0:
+            raise ValueError("need eps >= 0, tau >= 0, dt > 0")
+        self.eps, self.tau, self.dt = float(eps), float(tau), float(dt)
+
+
+def step(state, p, tab, ops, trace=None, _last_sign=-1.0):
+    """Advance state by one time step.  trace, if a list, receives one dict per stage
+    (used by the invariant tests).  _last_sign exists only so that tests can plant
+    the printed sign of step 2 and watch the invariant fail."""
+    if not tab.is_gsa():
+        raise ValueError("tableau must be globally stiffly accurate")
+    u1n, u2n, thn, v1n, v2n, qn = [np.asarray(x, dtype=np.float64) for x in state]
+    ny, nx = thn.shape
+    eps, tau, dt = p.eps, p.tau, p.dt
+    te2 = tau * eps * eps
+    A, At, s = tab.A, tab.At, tab.s
+    lam_x, lam_y = ops.lap_symbol(nx, ny)
+    th_mean = float(np.mean(thn))
+    div_un = ops.div_c(u1n, u2n)
+
+    st = []  # per stage: dict of the stage values and derived terms
+
+    def explicit_terms(S):
+        # E(j) = (tau/4) D0_LF.B(u) + tau eps^2 D_LF q [v] - F(u)
+        b1, b2 = ops.div0_B(S["u1"], S["u2"])
+        g1, g2 = ops.grad_lf(S["q"], S["v1"], S["v2"])
+        F1, F2 = flux_F(S["u1"], S["u2"])
+        return (0.25 * tau * b1 + te2 * g1 - F1,
+                0.25 * tau * b2 + te2 * g2 - F2)
+
+    def implicit_u_term(S, partner):
+        # D_LF.B(v(j)) [dissipation on the partner u] + D0 theta(j)
+        b1, b2 = ops.div_lf_B(S["v1"], S["v2"], partner[0], partner[1])
+        t1, t2 = ops.grad_c(S["th"])
+        return b1 + t1, b2 + t2
+
+    first = 0
+    if A[0, 0] == 0.0:
+        S = dict(u1=u1n, u2=u2n, th=thn, v1=v1n, v2=v2n, q=qn)
+        S["Hu"] = implicit_u_term(S, (u1n, u2n))
+        S["Hq"] = 0.5 * tau * ops.div0(v1n, v2n)
+        st.append(S)
+        first = 1
+
+    for i in range(first, s):
+        aii = A[i, i]
+        kap = te2 + dt * aii
+        sig = 2.0 * eps * eps / (dt * aii) ** 2
+        # step 1
+        r1 = te2 * v1n
+        r2 = te2 * v2n
+        for j in range(i):
+            if At[i, j] != 0.0:
+                if "E" not in st[j]:
+                    st[j]["E"] = explicit_terms(st[j])
+                r1 = r1 - dt * At[i, j] * st[j]["E"][0]
+                r2 = r2 - dt * At[i, j] * st[j]["E"][1]
+            if A[i, j] != 0.0:
+                r1 = r1 - dt * A[i, j] * st[j]["v1"]
+                r2 = r2 - dt * A[i, j] * st[j]["v2"]
+        v1 = r1 / kap
+        v2 = r2 / kap
+        # step 2
+        ddb_i = ops.divdivB(v1, v2)
+        R = -sig * thn + div_un / (dt * aii)
+        R = R - ddb_i
+        for j in range(i):
+            if A[i, j] != 0.0:
+                S = st[j]
+                R = R + A[i, j] / (dt * aii * aii) * ops.div_c(S["u1"], S["u2"])
+                R = R - A[i, j] / aii * ops.divdivB(S["v1"], S["v2"])
+                R = R + _last_sign * A[i, j] / aii * ops.lap(S["th"])
+        th = helmholtz.solve(R, sig, th_mean, lam_x, lam_y)
+        # step 3
+        S = dict(v1=v1, v2=v2, th=th)
+        partner = (st[i - 1]["u1"], st[i - 1]["u2"]) if i > 0 else (u1n, u2n)
+        S["Hu"] = implicit_u_term(S, partner)
+        u1 = u1n - dt * aii * S["Hu"][0]
+        u2 = u2n - dt * aii * S["Hu"][1]
+        for j in range(i):
+            if A[i, j] != 0.0:
+                u1 = u1 - dt * A[i, j] * st[j]["Hu"][0]
+                u2 = u2 - dt * A[i, j] * st[j]["Hu"][1]
+        # step 4
+        S["Hq"] = 0.5 * tau * ops.div0(v1, v2)
+        rq = te2 * qn - dt * aii * S["Hq"]
+        for j in range(i):
+            if A[i, j] != 0.0:
+                rq = rq - dt * A[i, j] * (st[j]["Hq"] + st[j]["q"])
+        q = rq / kap
+        S.update(u1=u1, u2=u2, q=q)
+        st.append(S)
+        if trace is not None:
+            trace.append(dict(i=i, sigma=sig, kappa=kap, R=R, **{k: S[k] for k in
+                                                                  ("u1", "u2", "th", "v1", "v2", "q")}))
+
+    L = st[-1]
+    return L["u1"], L["u2"], L["th"], L["v1"], L["v2"], L["q"]
+
+
+def run(state, p, tab, ops, nsteps):
+    for _ in range(nsteps):
+        state = step(state, p, tab, ops)
+    return state
