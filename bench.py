@@ -1,0 +1,167 @@
+"""Throughput benchmark of the AP IMEX-RK D2Q6 stepper on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  A step is one IMEX Runge-Kutta time step of every instance of
+the workload (all implicit stages: step-1 relaxation, Helmholtz right-hand side, FFT
+Helmholtz solve, u/q update, stage terms).  Inputs are resident in HBM before the
+timed region; the timed region is bracketed by torch.cuda.synchronize().
+
+value = 6 * sum(nx * ny) * K / seconds   (cell-population updates/s, Q = 6)
+
+roofline: the kernel class with the largest share of step time is bracketed by HIP
+events on the library's stream during the timed region; achieved = its algorithmic
+bytes per launch (every plane it must read or write, once) / its mean duration.
+cpu_baseline: the FP64 NumPy oracle on a bounded sample of the same workload, on the
+host (one core: NumPy's elementwise kernels and pocketfft are single-threaded).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IMEX-RK cell-pop updates/s + %HBM roofline; FP32-split/batched vs FP64"
+UNIT = "cell-population updates/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_2512_19847_amd import workloads as wl
+
+    if name == "shear512":
+        cases = [wl.shear_layer_512(e) for e in (1.0, 1e-2, 1e-6)]
+        cfg = {"workload": "shear_layer_512x512_eps_1_1e-2_1e-6_ars443", "grid": [512, 512],
+               "instances": 3, "eps": [1.0, 1e-2, 1e-6], "mach": 0.05,
+               "tableau": "ARS(4,4,3)", "space": "WENO5 + 4th-order central",
+               "cfl": wl.CFL_ARS, "steps_stated": 2000}
+        return cases, "ars443", cfg
+    if name == "taylor_green64":
+        cases = [wl.taylor_green_64("paper2")]
+        cfg = {"workload": "taylor_green_64x64_eps1_ma0.1_paper2", "grid": [64, 64],
+               "instances": 1, "tableau": "paper second order (c = 9/4)",
+               "steps_stated": 100}
+        return cases, "paper2", cfg
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(cases, tab, budget_s=20.0):
+    """Oracle steps on the host, as many whole instance-steps as fit the budget."""
+    from oracle import scheme, tableau as otab
+    from oracle.operators import Production
+
+    t0 = time.perf_counter()
+    done_cells = 0
+    k = 0
+    while True:
+        c = cases[k % len(cases)]
+        ops = Production(c.lx / c.nx, c.ly / c.ny)
+        scheme.step(c.state, scheme.Params(c.eps, c.tau, c.dt), otab.preset(tab), ops)
+        done_cells += c.nx * c.ny
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or k >= 3 * len(cases):
+            break
+    return {"value": 6.0 * done_cells / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{k} instance-steps of the same workload ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="shear512")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32split"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_19847_amd import apdvm
+
+    cases, tab, cfg = workload(args.workload)
+    prec = apdvm.FP32_SPLIT if args.precision == "fp32split" else apdvm.FP64
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    sim = apdvm.Simulation([dict(nx=c.nx, ny=c.ny, eps=c.eps, tau=c.tau, dt=c.dt,
+                                 lx=c.lx, ly=c.ly) for c in cases],
+                           tableau=tab, precision=prec, stream=stream)
+    for k, c in enumerate(cases):
+        sim.set_fields(k, *c.state)
+    cells = sum(c.nx * c.ny for c in cases)
+
+    # warm-up, then find the kernel class with the largest share of a step
+    sim.step(args.warmup)
+    share = []
+    for cls in range(len(apdvm.KERNEL_CLASSES)):
+        sim.timing_enable(cls)
+        sim.step(4)
+        n, ms = sim.timing_read()
+        share.append(ms)
+    sim.timing_enable(-1)
+    dom = int(np.argmax(share))
+
+    # timed region: every launch of the dominant class bracketed by HIP events
+    sim.timing_enable(dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_dom, ms_dom = sim.timing_read()
+    sim.timing_enable(-1)
+    sec = t1 - t0
+
+    bytes_step, launches = sim.traffic(dom)
+    per_launch = bytes_step / launches
+    mean_s = ms_dom / n_dom / 1e3
+    achieved = per_launch / mean_s / 1e9
+    diag = [sim.diagnostics(k) for k in range(len(cases))]
+    finite = all(d[7] == 1.0 for d in diag)
+    total_bytes, nl = sim.traffic(-1)
+    print(f"[bench] {args.workload} {args.precision}: {sec / args.steps * 1e3:.3f} ms/step, "
+          f"{nl} launches/step, algorithmic {total_bytes / 1e6:.1f} MB/step "
+          f"({total_bytes / (sec / args.steps) / 1e9:.0f} GB/s whole step); class shares ms "
+          f"{dict(zip(apdvm.KERNEL_CLASSES, [round(x, 3) for x in share]))}; finite={finite}",
+          file=sys.stderr)
+
+    out = {
+        "metric": METRIC,
+        "value": 6.0 * cells * args.steps / sec,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == apdvm.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": dict(cfg, precision=args.precision),
+        "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": per_launch, "mean_launch_us": mean_s * 1e6,
+                     "launches_timed": n_dom},
+        "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cases, tab)
+    sim.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * apdvm -- asymptotic-preserving IMEX Runge-Kutta stepper for the six-velocity
+ * (D2Q6) lattice-Boltzmann-type discrete velocity model in the low-Mach diffusive
+ * scaling (Dimarco, Klar, Koefler, Pareschi, arXiv 2512.19847), on MI355X (gfx950).
+ *
+ * The library evolves the six scaled moments (u1, u2, theta, v1, v2, q) of the
+ * populations (Section 2.1: the populations and these moments are in one-to-one
+ * correspondence) on a doubly periodic, cell-centred nx x ny grid.  One call of
+ * apdvm_step advances every simulation of a context by one time step of a globally
+ * stiffly accurate IMEX Runge-Kutta method: for each implicit stage, the local
+ * implicit relaxation of v (Algorithm 1, step 1), the periodic Helmholtz equation
+ * for theta (step 2, solved exactly by a 2D FFT), the velocity update (step 3) and
+ * the local implicit relaxation of q (step 4), with the space discretisation of
+ * Section 3.2 in its high-order form (WENO5 Lax-Friedrichs fluxes and fourth-order
+ * central differences).
+ *
+ * Conventions for every entry point:
+ *  - Host arrays are float64, row-major [ny][nx] (x fastest), owned by the caller and
+ *    copied in or out; device arrays follow the same layout and are caller-owned.
+ *  - Every call returns an apdvm_status.  A call that fails validation changes
+ *    nothing.  No entry point throws or aborts.
+ *  - Work is enqueued on the stream given at creation.  apdvm_step only enqueues;
+ *    the get_* calls synchronise that stream before returning.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef APDVM_H
+#define APDVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  APDVM_OK = 0,
+  APDVM_ERR_ARG = 1,       /* a size, pointer or parameter is out of range        */
+  APDVM_ERR_VELSET = 2,    /* the velocity set is not the paper's six velocities   */
+  APDVM_ERR_TABLEAU = 3,   /* tableau not GSA / not ARS-type / malformed           */
+  APDVM_ERR_NOMEM = 4,     /* device allocation failed or workspace too small      */
+  APDVM_ERR_HIP = 5,       /* a HIP runtime call failed                            */
+  APDVM_ERR_NONFINITE = 6, /* input or state holds NaN or Inf                      */
+  APDVM_ERR_STATE = 7      /* call out of order (e.g. step before set_fields)      */
+} apdvm_status;
+
+typedef enum {
+  APDVM_FP64 = 0,       /* every plane and every operation in float64             */
+  APDVM_FP32_SPLIT = 1  /* u, v, q and stage terms stored and transported in
+                           float32; history sums feeding the implicit relaxations
+                           and the Helmholtz right-hand side accumulated in float64;
+                           theta and the whole Helmholtz solve in float64          */
+} apdvm_precision;
+
+/*
+ * One simulation.  Grid: periodic box [0, lx) x [0, ly), cell centres
+ * ((i + 1/2) lx/nx, (j + 1/2) ly/ny) (Section 3.2).  nx, ny must be even, >= 8, and
+ * of the form 2^a 3^b; each at most 8192.
+ *
+ * Velocity set: q must be 6.  cx, cy may be NULL (the paper's set
+ * c_i = (cos(pi(i-1)/3), sin(pi(i-1)/3)), Section 2.1) or point to 6 values each,
+ * which must equal that set to 1e-12, else APDVM_ERR_VELSET.
+ *
+ * eps >= 0 is the Knudsen number (eps = 0 runs the exact limit scheme); mach > 0.
+ * tau < 0 derives tau = 4 eps / mach (eps = Ma/Re and the limit Reynolds number is
+ * 4/tau, Section 2); tau >= 0 is used as given (the paper's tests use 0 and 0.05).
+ *
+ * Tableau: s stages (2 <= s <= 8), a_ex and a_im s x s row-major, b_ex and b_im of
+ * length s (Section 3.1).  Must be globally stiffly accurate and of ARS type
+ * (a_im[0][0] = 0 and a_im[i][0] = 0), a_ex strictly lower triangular, a_im lower
+ * triangular with nonzero diagonal after the first stage; else APDVM_ERR_TABLEAU.
+ *
+ * dt > 0 is used as given.  dt <= 0 derives the largest dt with
+ *   ct dt max(umax, 1, tau eps / (tau eps^2 + ct dt)) <= cfl h  and
+ *   ct dt (tau/4) ct dt / (tau eps^2 + ct dt) <= c_visc h^2,
+ * h = min(lx/nx, ly/ny), ct the largest explicit stage abscissa, umax the largest
+ * |u| of the fields given to apdvm_set_fields (the derivation happens there), and 1
+ * the Lax-Friedrichs dissipation speed (alpha = 1, Section 3.2), whose jump term acts
+ * explicitly.
+ */
+typedef struct {
+  int32_t nx, ny;
+  double lx, ly;
+  int32_t q;
+  const double *cx, *cy;
+  double eps, mach, tau;
+  int32_t s;
+  const double *a_ex, *b_ex, *a_im, *b_im;
+  double dt, cfl, c_visc;
+  int32_t precision; /* apdvm_precision; must be the same for every instance */
+} apdvm_config;
+
+typedef struct apdvm_ctx apdvm_ctx;
+
+/* Bytes of device workspace that apdvm_create needs for these configurations
+ * (n >= 1 instances sharing one tableau and precision).  Host-only; no GPU call. */
+apdvm_status apdvm_workspace_bytes(int32_t n, const apdvm_config *cfgs, size_t *bytes);
+
+/* Create a context holding n >= 1 independent simulations, all advanced together by
+ * apdvm_step.  All instances must share s, the tableau and the precision.
+ * dev_ws: device workspace of ws_bytes >= apdvm_workspace_bytes, owned by the caller
+ * and outliving the context; NULL makes the library allocate (and free) its own.
+ * hip_stream: a hipStream_t cast to void*, or NULL for the default stream.
+ * On success *out receives the context. */
+apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws,
+                          size_t ws_bytes, void *hip_stream, apdvm_ctx **out);
+
+/* Initial fields of instance k from host arrays.  v1 and v2 may both be NULL (then
+ * v = F(u) = (1/2 (u2^2 - u1^2), u1 u2), local equilibrium); q may be NULL (then 0).
+ * Rejects NaN/Inf (APDVM_ERR_NONFINITE).  Resets the step counter of the context
+ * only when called for every instance before the next step. */
+apdvm_status apdvm_set_fields(apdvm_ctx *ctx, int32_t k, const double *u1,
+                              const double *u2, const double *theta, const double *v1,
+                              const double *v2, const double *q);
+
+/* Same from six device arrays of nx*ny float64 each (no NULLs).  The caller
+ * guarantees the values are finite. */
+apdvm_status apdvm_set_fields_device(apdvm_ctx *ctx, int32_t k, const double *const dev[6]);
+
+/* Initial fields of instance k from populations F[6][ny][nx] (host, float64), mapped
+ * to scaled moments by R = 1 + 2 eps^2 theta, U = eps u, V = eps^2 v, Q = eps^3 q with
+ * (R, U, V, Q) the moments of F for the basis 1, c, 1/2 - c_x^2, c_x c_y,
+ * c_x (c_y^2 - 1/4).  Needs eps > 0. */
+apdvm_status apdvm_set_populations(apdvm_ctx *ctx, int32_t k, const double *F);
+
+/* Enqueue nsteps >= 0 time steps of every instance on the context's stream. */
+apdvm_status apdvm_step(apdvm_ctx *ctx, int64_t nsteps);
+
+/* Copy the six fields of instance k to host arrays (any pointer may be NULL to skip
+ * that field).  Synchronises the stream. */
+apdvm_status apdvm_get_fields(apdvm_ctx *ctx, int32_t k, double *u1, double *u2,
+                              double *theta, double *v1, double *v2, double *q);
+
+/* Same into six device arrays of nx*ny float64 each (enqueued, not synchronised). */
+apdvm_status apdvm_get_fields_device(apdvm_ctx *ctx, int32_t k, double *const dev[6]);
+
+/* Physical moments of instance k (host): rho = 1 + 2 eps^2 theta, u, and the pressure
+ * p = theta - |u|^2 / 2 (Section 2.1).  Synchronises the stream. */
+apdvm_status apdvm_get_moments(apdvm_ctx *ctx, int32_t k, double *rho, double *u1,
+                               double *u2, double *p);
+
+/* Populations F[6][ny][nx] of instance k (host), the inverse of the map of
+ * apdvm_set_populations.  Needs eps > 0.  Synchronises the stream. */
+apdvm_status apdvm_get_populations(apdvm_ctx *ctx, int32_t k, double *F);
+
+/* Time step, tau and the number of steps taken, for instance k. */
+apdvm_status apdvm_get_info(apdvm_ctx *ctx, int32_t k, double *dt, double *tau,
+                            int64_t *step);
+
+/* Set the step counter (checkpoint restore: set_fields + set_step). */
+apdvm_status apdvm_set_step(apdvm_ctx *ctx, int64_t step);
+
+/* Diagnostics of instance k, computed on the device and synchronised:
+ * out[0] sum theta h_x h_y, out[1] sum u1 h_x h_y, out[2] sum u2 h_x h_y,
+ * out[3] max |D0.u| (fourth-order central divergence, the divergence diagnostic of
+ * Section 4), out[4] min vorticity, out[5] max vorticity (fourth-order central
+ * D_x u2 - D_y u1), out[6] kinetic energy 1/2 sum |u|^2 h_x h_y, out[7] 1 if every
+ * value of the six fields is finite else 0. */
+apdvm_status apdvm_diagnostics(apdvm_ctx *ctx, int32_t k, double out[8]);
+
+/* Number of kernel launches one apdvm_step(ctx, 1) enqueues (for profiling). */
+apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
+
+/* Launch mode.  on = 0 (default): every kernel of a step is launched on its own.
+ * on = 1: each step replays a HIP graph of the step's launches, captured on first use;
+ * needs a created (non-NULL) stream at apdvm_create, else APDVM_ERR_ARG. */
+apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
+
+/* Kernel classes of a step, used by the two profiling calls below:
+ * 0 step-1 relaxation of v, 1 step-2 right-hand side, 2 Helmholtz rows forward FFT,
+ * 3 Helmholtz columns (FFT, symbol divide, inverse FFT), 4 Helmholtz rows inverse FFT,
+ * 5 steps 3 and 4 (u and q updates), 6 stage terms reused by later stages. */
+#define APDVM_NUM_KERNEL_CLASSES 7
+
+/* From now on bracket every launch of kernel class cls with a pair of HIP events on
+ * the context's stream (cls = -1 stops); graph replay is bypassed while a class is
+ * timed.  Synchronises the stream and clears earlier timings. */
+apdvm_status apdvm_timing_enable(apdvm_ctx *ctx, int32_t cls);
+
+/* Synchronise, then return the number of timed launches since apdvm_timing_enable and
+ * the sum of their durations in milliseconds. */
+apdvm_status apdvm_timing_read(apdvm_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* Algorithmic bytes that one step moves through the kernels of class cls (-1: every
+ * class): each plane a launch must read or write counted once, summed over the
+ * instances; and the number of such launches per step.  Host-only. */
+apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
+                           int32_t *launches_per_step);
+
+/* Release the context (and the workspace if the library allocated it).  NULL ok. */
+void apdvm_destroy(apdvm_ctx *ctx);
+
+/* Static text for a status code. */
+const char *apdvm_status_string(apdvm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APDVM_H */

@@ -1,0 +1,135 @@
+// Internal data structures shared by the HIP kernels and the host runtime.
+//
+// Every context holds one or more independent simulations ("instances").  Each
+// phase of a stage is one kernel launch over a work table that lists, for every
+// workgroup, the instance and the tile (or FFT row block / column strip) it owns,
+// so a single launch advances every instance.  Per-instance scalars, FFT plans,
+// symbols and plane base pointers live in a device array of Inst; per-stage slot
+// numbers and tableau coefficients are identical for all instances and travel as
+// kernel arguments.
+//
+// Planes: an instance owns two arenas, one of "transport" planes (T = double in the
+// FP64 form, float in the FP32-split form) and one of float64 planes (theta, the
+// Helmholtz right-hand side, the spectrum).  A slot number k addresses the plane at
+// base + k * nx * ny.  Layout of a plane: row-major [ny][nx], x fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace apdvm {
+
+constexpr int kMaxStages = 8;
+constexpr int kMaxPasses = 16;
+constexpr int kNoSlot = -1;
+
+// Stencil tiles: TX x TY interior cells, halo kHalo (WENO5 needs 3 on each side).
+constexpr int kTileX = 64;
+constexpr int kHalo = 3;
+constexpr int kStencilThreads = 256;
+
+// FFT workgroups: capacity in complex float64 values held in LDS, and threads.
+constexpr int kFftCap = 8192;
+constexpr int kFftThreads = 1024;
+
+struct FftPlan {
+  int n;                  // transform length
+  int npass;              // number of Stockham passes
+  int radix[kMaxPasses];  // radices (2, 3, 4 or 8), first pass first
+  const double2 *tw;      // tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device)
+};
+
+struct Inst {
+  int nx, ny;
+  long long plane;           // nx * ny
+  double ihx, ihy;           // 1 / h
+  double eps, tau, dt, te2;  // te2 = tau * eps^2
+  double theta_mean;         // value imposed on the (0,0) Helmholtz mode
+  double kinv[kMaxStages];   // 1 / (tau eps^2 + dt a_ii)
+  double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
+  double inv_nxny;           // 1 / (nx ny)
+  FftPlan fx, fy;
+  const double *lam_x;       // nx/2 + 1 values of the x symbol of D_Delta
+  const double *lam_y;       // ny values of the y symbol
+  void *tbase;               // transport arena
+  double *dbase;             // float64 arena
+  int row_pairs_per_block;   // FFT row kernels: row pairs per workgroup
+  int cols_per_block;        // FFT column kernel: complex columns per workgroup
+};
+
+// Work table entry: instance and the first cell / row pair / column of the block.
+struct Work {
+  int inst;
+  int a;  // stencil: x0;  FFT rows: first row pair;  FFT columns: first column
+  int b;  // stencil: y0
+  int c;  // unused
+};
+
+// ---------------------------------------------------------------- kernel arguments
+
+// Step 1 of a stage: v(i) = [te2 v^n - dt sum_j cE_j E(j) - dt sum_j cV_j v(j)] kinv.
+struct ArgsV {
+  int stage;
+  int vn[2];
+  int nE, E[kMaxStages][2];
+  double cE[kMaxStages];
+  int nV, V[kMaxStages][2];
+  double cV[kMaxStages];
+  int out[2];
+};
+
+// Step 2 right-hand side:
+// R = -sigma theta^n + 1/(dt a_ii^2) sum_j cD_j D0.u(j) + 1/(dt a_ii) D0.u^n
+//     - D0^2:B(v(i)) - 1/a_ii sum_j cL_j Ltheta(j),
+// with Ltheta(j) = D0^2:B(v(j)) + D_Delta theta(j).  Also stores D0^2:B(v(i)).
+struct ArgsR {
+  int stage;
+  double aii;
+  int v[2];       // v(i), read with a halo of 2 (corners included)
+  int thn;        // theta^n (float64 slot)
+  int du0;        // D0.u^n
+  int nD, D[kMaxStages];
+  double cD[kMaxStages];
+  int nL, L[kMaxStages];
+  double cL[kMaxStages];
+  int out_r;      // R (float64 slot)
+  int out_ddb;    // D0^2:B(v(i))
+};
+
+// Steps 3 and 4:
+// Hu = D_W.B(v(i))[dissipation on u(i-1)] + D0 theta(i)
+// u(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii Hu
+// Hq = (tau/2) D0_W.v(i)
+// q(i) = [te2 q^n - dt a_ii Hq - dt sum_j cG_j Gq(j)] kinv,   Gq(j) = Hq(j) + q(j)
+struct ArgsUQ {
+  int stage;
+  double aii;
+  int v[2];       // v(i), halo 3
+  int partner[2]; // u(i-1), halo 3
+  int th;         // theta(i) (float64 slot), halo 2
+  int un[2], qn;  // state at time n
+  int nH, H[kMaxStages][2];
+  double cH[kMaxStages];
+  int nG, G[kMaxStages];
+  double cG[kMaxStages];
+  int out_u[2], out_q;
+  int out_hu[2], out_gq;  // kNoSlot when no later stage needs them
+};
+
+// Terms of a known stage that later stages reuse:
+// E = (tau/4) D0_W.B(u) + te2 D_W q[dissipation on v] - F(u), D0.u,
+// Ltheta = D0^2:B(v) + D_Delta theta.
+struct ArgsE {
+  int u[2], q, v[2];  // halo 3
+  int th;             // float64 slot, halo 2 (only when out_lt != kNoSlot)
+  int ddb;            // D0^2:B(v) of this stage (only when out_lt != kNoSlot)
+  int out_e[2], out_du, out_lt;
+};
+
+// Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec.
+struct ArgsSolve {
+  int stage;
+  int r, spec, out;
+};
+
+}  // namespace apdvm

@@ -1,0 +1,1122 @@
+// Host runtime behind the C ABI of include/apdvm.h: configuration checks, the
+// per-instance parameter table, the plane layout, FFT plans, work tables and the
+// launch sequence of one IMEX step (Algorithm 1 for every implicit stage).
+#include "apdvm.h"
+#include "common.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace apdvm {
+
+template <typename T>
+int tile_rows();
+template <typename T>
+hipError_t launch_relax_v(const Inst *, const Work *, int, const ArgsV &, hipStream_t);
+template <typename T>
+hipError_t launch_helmholtz_rhs(const Inst *, const Work *, int, const ArgsR &, hipStream_t);
+template <typename T>
+hipError_t launch_update_uq(const Inst *, const Work *, int, const ArgsUQ &, hipStream_t);
+template <typename T>
+hipError_t launch_stage_terms(const Inst *, const Work *, int, const ArgsE &, hipStream_t);
+hipError_t launch_solve_part(int part, const Inst *, const Work *, int, const Work *, int,
+                             const ArgsSolve &, hipStream_t);
+hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
+                              int, double *, int, hipStream_t);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ----------------------------------------------------------- validation helpers
+
+bool is_2a3b(int n) {
+  if (n <= 0) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+apdvm_status check_grid(const apdvm_config &c) {
+  for (int n : {c.nx, c.ny})
+    if (n < 8 || n > kFftCap || (n % 2) != 0 || !is_2a3b(n)) return APDVM_ERR_ARG;
+  if (!(c.lx > 0.0) || !(c.ly > 0.0) || !std::isfinite(c.lx) || !std::isfinite(c.ly))
+    return APDVM_ERR_ARG;
+  return APDVM_OK;
+}
+
+apdvm_status check_velset(const apdvm_config &c) {
+  if (c.q != 6) return APDVM_ERR_VELSET;
+  if ((c.cx == nullptr) != (c.cy == nullptr)) return APDVM_ERR_VELSET;
+  if (c.cx) {
+    for (int i = 0; i < 6; ++i) {
+      const double ang = M_PI * i / 3.0;
+      if (!(std::fabs(c.cx[i] - std::cos(ang)) <= 1e-12) ||
+          !(std::fabs(c.cy[i] - std::sin(ang)) <= 1e-12))
+        return APDVM_ERR_VELSET;
+    }
+  }
+  return APDVM_OK;
+}
+
+apdvm_status check_tableau(const apdvm_config &c) {
+  const int s = c.s;
+  if (s < 2 || s > kMaxStages) return APDVM_ERR_TABLEAU;
+  if (!c.a_ex || !c.b_ex || !c.a_im || !c.b_im) return APDVM_ERR_TABLEAU;
+  auto At = [&](int i, int j) { return c.a_ex[i * s + j]; };
+  auto A = [&](int i, int j) { return c.a_im[i * s + j]; };
+  for (int i = 0; i < s; ++i) {
+    for (int j = 0; j < s; ++j) {
+      if (!std::isfinite(At(i, j)) || !std::isfinite(A(i, j))) return APDVM_ERR_TABLEAU;
+      if (j >= i && At(i, j) != 0.0) return APDVM_ERR_TABLEAU;  // explicit: strictly lower
+      if (j > i && A(i, j) != 0.0) return APDVM_ERR_TABLEAU;    // implicit: DIRK
+    }
+    if (!std::isfinite(c.b_ex[i]) || !std::isfinite(c.b_im[i])) return APDVM_ERR_TABLEAU;
+  }
+  // ARS type: the first stage is explicit and the first column of A vanishes
+  if (A(0, 0) != 0.0) return APDVM_ERR_TABLEAU;
+  for (int i = 0; i < s; ++i)
+    if (A(i, 0) != 0.0) return APDVM_ERR_TABLEAU;
+  for (int i = 1; i < s; ++i)
+    if (A(i, i) == 0.0) return APDVM_ERR_TABLEAU;
+  // globally stiffly accurate: the last stage is the new time level
+  for (int j = 0; j < s; ++j)
+    if (A(s - 1, j) != c.b_im[j]) return APDVM_ERR_TABLEAU;
+  for (int j = 0; j < s - 1; ++j)
+    if (At(s - 1, j) != c.b_ex[j]) return APDVM_ERR_TABLEAU;
+  if (c.b_ex[s - 1] != 0.0) return APDVM_ERR_TABLEAU;
+  return APDVM_OK;
+}
+
+apdvm_status check_physics(const apdvm_config &c) {
+  if (!(c.eps >= 0.0) || !std::isfinite(c.eps)) return APDVM_ERR_ARG;
+  if (c.tau < 0.0) {
+    if (!(c.mach > 0.0) || !std::isfinite(c.mach)) return APDVM_ERR_ARG;
+  } else if (!std::isfinite(c.tau)) {
+    return APDVM_ERR_ARG;
+  }
+  if (!std::isfinite(c.dt)) return APDVM_ERR_ARG;
+  if (!(c.dt > 0.0)) {
+    if (!(c.cfl > 0.0) || !(c.c_visc > 0.0) || !std::isfinite(c.cfl) || !std::isfinite(c.c_visc))
+      return APDVM_ERR_ARG;
+  }
+  if (c.precision != APDVM_FP64 && c.precision != APDVM_FP32_SPLIT) return APDVM_ERR_ARG;
+  return APDVM_OK;
+}
+
+bool same_tableau(const apdvm_config &a, const apdvm_config &b) {
+  if (a.s != b.s || a.precision != b.precision) return false;
+  const size_t s = a.s;
+  return !std::memcmp(a.a_ex, b.a_ex, s * s * sizeof(double)) &&
+         !std::memcmp(a.a_im, b.a_im, s * s * sizeof(double)) &&
+         !std::memcmp(a.b_ex, b.b_ex, s * sizeof(double)) &&
+         !std::memcmp(a.b_im, b.b_im, s * sizeof(double));
+}
+
+apdvm_status validate(int n, const apdvm_config *cfgs) {
+  if (n < 1 || !cfgs) return APDVM_ERR_ARG;
+  for (int k = 0; k < n; ++k) {
+    apdvm_status st;
+    if ((st = check_grid(cfgs[k])) != APDVM_OK) return st;
+    if ((st = check_velset(cfgs[k])) != APDVM_OK) return st;
+    if ((st = check_tableau(cfgs[k])) != APDVM_OK) return st;
+    if ((st = check_physics(cfgs[k])) != APDVM_OK) return st;
+    if (k > 0 && !same_tableau(cfgs[0], cfgs[k])) return APDVM_ERR_ARG;
+  }
+  return APDVM_OK;
+}
+
+// ----------------------------------------------------------- plane layout
+
+// Slot numbers of every plane one step touches, for an s-stage ARS tableau.  Stage 0
+// is the state at time n; stages 1..s-1 are implicit; stage s-1 writes straight into
+// the other state set.
+struct Layout {
+  int s;
+  int st[2][5];  // state sets: u1, u2, v1, v2, q
+  int th[2];     // float64: theta of each state set
+  int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
+  int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
+  int ddb;
+  int Th[kMaxStages], R, spec;  // float64
+  int ntrans, ndbl;
+};
+
+Layout make_layout(int s) {
+  Layout L;
+  std::memset(&L, 0xff, sizeof(L));  // every slot starts as kNoSlot (-1)
+  L.s = s;
+  int t = 0, d = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int f = 0; f < 5; ++f) L.st[p][f] = t++;
+  L.th[0] = d++;
+  L.th[1] = d++;
+  for (int j = 0; j <= s - 2; ++j) {
+    L.E[j][0] = t++;
+    L.E[j][1] = t++;
+    L.Du[j] = t++;
+  }
+  for (int j = 1; j <= s - 2; ++j) {
+    L.V[j][0] = t++;
+    L.V[j][1] = t++;
+    L.Lt[j] = t++;
+    L.Hu[j][0] = t++;
+    L.Hu[j][1] = t++;
+    L.Gq[j] = t++;
+    L.U[j][0] = t++;
+    L.U[j][1] = t++;
+    L.Q[j] = t++;
+    L.Th[j] = d++;
+  }
+  L.ddb = t++;
+  L.R = d++;
+  L.spec = d++;
+  L.ntrans = t;
+  L.ndbl = d;
+  return L;
+}
+
+// ----------------------------------------------------------- FFT plans
+
+int fft_radices(int n, int *rad) {
+  int np = 0;
+  int m = n;
+  while (m % 8 == 0) { rad[np++] = 8; m /= 8; }
+  if (m % 4 == 0) { rad[np++] = 4; m /= 4; }
+  if (m % 2 == 0) { rad[np++] = 2; m /= 2; }
+  while (m % 3 == 0) { rad[np++] = 3; m /= 3; }
+  return np;
+}
+
+void twiddles(int n, double2 *out) {
+  for (int m = 0; m < n; ++m) {
+    const long double a = -2.0L * 3.141592653589793238462643383279502884L * m / n;
+    out[m] = make_double2((double)cosl(a), (double)sinl(a));
+  }
+}
+
+// Fourier symbol of the fourth-order central second difference on an n-point grid
+// with spacing h: (-2 cos 2 th + 32 cos th - 30) / (12 h^2), th = 2 pi k / n.
+double lap_symbol(int k, int n, double h) {
+  const long double th = 2.0L * 3.141592653589793238462643383279502884L * k / n;
+  return (double)((-2.0L * cosl(2.0L * th) + 32.0L * cosl(th) - 30.0L) / (12.0L * h * h));
+}
+
+double resolved_tau(const apdvm_config &c) { return c.tau >= 0.0 ? c.tau : 4.0 * c.eps / c.mach; }
+
+// ----------------------------------------------------------- sizes
+
+struct Sizes {
+  size_t per_inst_trans, per_inst_dbl, per_inst_tab;
+  size_t total;
+};
+
+int n_tiles(const apdvm_config &c, int ty) {
+  return ((c.nx + kTileX - 1) / kTileX) * ((c.ny + ty - 1) / ty);
+}
+int rpb(const apdvm_config &c) {
+  int r = kFftCap / c.nx;
+  if (r > c.ny / 2) r = c.ny / 2;
+  return r < 1 ? 1 : r;
+}
+int cpb(const apdvm_config &c) {
+  int r = kFftCap / c.ny;
+  if (r > c.nx / 2) r = c.nx / 2;
+  return r < 1 ? 1 : r;
+}
+int n_rowblocks(const apdvm_config &c) { return (c.ny / 2 + rpb(c) - 1) / rpb(c); }
+int n_colblocks(const apdvm_config &c) { return (c.nx / 2 + cpb(c) - 1) / cpb(c); }
+
+size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
+  const size_t plane = (size_t)c.nx * c.ny;
+  size_t b = align_up(L.ntrans * plane * tsize) + align_up(L.ndbl * plane * sizeof(double));
+  b += align_up((size_t)(c.nx + c.ny) * sizeof(double2));           // twiddles
+  b += align_up((size_t)(c.nx / 2 + 1 + c.ny) * sizeof(double));    // symbols
+  return b;
+}
+
+size_t workspace_bytes(int n, const apdvm_config *cfgs) {
+  const Layout L = make_layout(cfgs[0].s);
+  const bool split = cfgs[0].precision == APDVM_FP32_SPLIT;
+  const size_t tsize = split ? sizeof(float) : sizeof(double);
+  const int ty = split ? tile_rows<float>() : tile_rows<double>();
+  size_t b = align_up(n * sizeof(Inst));
+  size_t ntile = 0, nrow = 0, ncol = 0;
+  for (int k = 0; k < n; ++k) {
+    b += inst_bytes(cfgs[k], L, tsize);
+    ntile += n_tiles(cfgs[k], ty);
+    nrow += n_rowblocks(cfgs[k]);
+    ncol += n_colblocks(cfgs[k]);
+  }
+  b += align_up(ntile * sizeof(Work)) + align_up(nrow * sizeof(Work)) + align_up(ncol * sizeof(Work));
+  b += align_up(8 * sizeof(double) * 1024);  // diagnostics partials
+  return b;
+}
+
+}  // namespace
+
+// One kernel launch of a step: its class, arguments and algorithmic bytes (every
+// plane it must read and write, counted once).
+enum LaunchClass {
+  kRelaxV = 0, kHelmRhs = 1, kRowsFwd = 2, kColumns = 3, kRowsInv = 4, kUpdateUQ = 5,
+  kStageTerms = 6, kNumClasses = 7
+};
+
+struct Launch {
+  int cls;
+  ArgsV v;
+  ArgsR r;
+  ArgsUQ uq;
+  ArgsE e;
+  ArgsSolve sv;
+  double bytes;
+};
+
+}  // namespace apdvm
+
+using namespace apdvm;
+
+struct apdvm_ctx {
+  int n = 0;
+  int s = 0;
+  bool split = false;
+  double At[kMaxStages][kMaxStages], A[kMaxStages][kMaxStages];
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  Layout L;
+  std::vector<apdvm_config> cfg;
+  std::vector<Inst> inst;
+  Inst *d_inst = nullptr;
+  Work *d_tiles = nullptr, *d_rows = nullptr, *d_cols = nullptr;
+  int ntiles = 0, nrows = 0, ncols = 0;
+  std::vector<Work> tiles;  // host copy (diagnostics use per-instance ranges)
+  std::vector<int> tile_first, tile_count;
+  double *d_partials = nullptr;
+  int parity = 0;           // state set holding the current state
+  bool terms_ready = false; // stage-0 terms computed for the current state
+  std::vector<char> has_fields;
+  std::vector<double> umax;
+  int64_t step = 0;
+  double cells = 0.0;                 // sum of nx * ny over instances
+  std::vector<apdvm::Launch> plan[2]; // launch list of one step from each state set
+  bool use_graph = false;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  int timed_class = -1;               // kernel class bracketed by events, -1 none
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+apdvm_status hip_status(hipError_t e) { return e == hipSuccess ? APDVM_OK : APDVM_ERR_HIP; }
+
+// dt rule (see apdvm.h): largest dt with ct dt max(umax, 1, tau eps / (te2 + ct dt)) <= cfl h
+// and ct dt (tau/4) ct dt / (te2 + ct dt) <= c_visc h^2, found by bisection on the
+// monotone left-hand sides.
+double derive_dt(const apdvm_config &c, double tau, double umax, double ct) {
+  const double h = std::fmin(c.lx / c.nx, c.ly / c.ny);
+  const double te2 = tau * c.eps * c.eps;
+  auto ok = [&](double dt) {
+    const double d = ct * dt;
+    const double kin = (te2 + d) > 0.0 ? tau * c.eps / (te2 + d) : 0.0;
+    const bool hyp = d * std::fmax(std::fmax(umax, 1.0), kin) <= c.cfl * h;
+    const bool par = d * 0.25 * tau * d / (te2 + d) <= c.c_visc * h * h;
+    return hyp && par;
+  };
+  double lo = 0.0, hi = 100.0 * h;
+  if (ok(hi)) return hi;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (ok(mid)) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+void set_dt(apdvm_ctx *c, int k, double dt) {
+  Inst &I = c->inst[k];
+  I.dt = dt;
+  for (int i = 1; i < c->s; ++i) {
+    const double aii = c->A[i][i];
+    I.kinv[i] = 1.0 / (I.te2 + dt * aii);
+    I.sigma[i] = 2.0 * I.eps * I.eps / ((dt * aii) * (dt * aii));
+  }
+}
+
+apdvm_status upload_inst(apdvm_ctx *c, int k) {
+  return hip_status(hipMemcpyAsync(c->d_inst + k, &c->inst[k], sizeof(Inst), hipMemcpyHostToDevice,
+                                   c->stream));
+}
+
+// Launch list of one step starting from state set P (stage-0 terms excluded).
+std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
+  const Layout &L = c->L;
+  const int s = c->s, Q = 1 - P;
+  const double pt = c->cells * (c->split ? 4.0 : 8.0), pd = c->cells * 8.0;
+  auto later_needs = [&](int j) {
+    for (int k = j + 1; k < s; ++k)
+      if (c->A[k][j] != 0.0) return true;
+    return false;
+  };
+  std::vector<Launch> plan;
+  for (int i = 1; i < s; ++i) {
+    const bool last = i == s - 1;
+    const int v1 = last ? L.st[Q][2] : L.V[i][0], v2 = last ? L.st[Q][3] : L.V[i][1];
+    const int u1 = last ? L.st[Q][0] : L.U[i][0], u2 = last ? L.st[Q][1] : L.U[i][1];
+    const int qi = last ? L.st[Q][4] : L.Q[i];
+    const int th = last ? L.th[Q] : L.Th[i];
+    const double aii = c->A[i][i];
+    Launch l{};
+    // step 1
+    l.cls = kRelaxV;
+    ArgsV &av = l.v;
+    av.stage = i;
+    av.vn[0] = L.st[P][2]; av.vn[1] = L.st[P][3];
+    for (int j = 0; j < i; ++j) {
+      if (c->At[i][j] != 0.0) {
+        av.E[av.nE][0] = L.E[j][0]; av.E[av.nE][1] = L.E[j][1]; av.cE[av.nE++] = c->At[i][j];
+      }
+      if (j >= 1 && c->A[i][j] != 0.0) {
+        av.V[av.nV][0] = L.V[j][0]; av.V[av.nV][1] = L.V[j][1]; av.cV[av.nV++] = c->A[i][j];
+      }
+    }
+    av.out[0] = v1; av.out[1] = v2;
+    l.bytes = (4 + 2 * av.nE + 2 * av.nV) * pt;
+    plan.push_back(l);
+    // step 2 right-hand side
+    l = Launch{};
+    l.cls = kHelmRhs;
+    ArgsR &ar = l.r;
+    ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P]; ar.du0 = L.Du[0];
+    for (int j = 1; j < i; ++j) {
+      if (c->A[i][j] != 0.0) {
+        ar.D[ar.nD] = L.Du[j]; ar.cD[ar.nD++] = c->A[i][j];
+        ar.L[ar.nL] = L.Lt[j]; ar.cL[ar.nL++] = c->A[i][j];
+      }
+    }
+    ar.out_r = L.R; ar.out_ddb = L.ddb;
+    l.bytes = (2 + 1 + ar.nD + ar.nL + 1) * pt + 2 * pd;
+    plan.push_back(l);
+    // step 2 solve: three kernels
+    ArgsSolve as{};
+    as.stage = i; as.r = L.R; as.spec = L.spec; as.out = th;
+    for (int k = kRowsFwd; k <= kRowsInv; ++k) {
+      l = Launch{};
+      l.cls = k;
+      l.sv = as;
+      l.bytes = 2 * pd;
+      plan.push_back(l);
+    }
+    // steps 3 and 4
+    l = Launch{};
+    l.cls = kUpdateUQ;
+    ArgsUQ &au = l.uq;
+    au.stage = i; au.aii = aii; au.v[0] = v1; au.v[1] = v2;
+    au.partner[0] = i == 1 ? L.st[P][0] : L.U[i - 1][0];
+    au.partner[1] = i == 1 ? L.st[P][1] : L.U[i - 1][1];
+    au.th = th; au.un[0] = L.st[P][0]; au.un[1] = L.st[P][1]; au.qn = L.st[P][4];
+    for (int j = 1; j < i; ++j) {
+      if (c->A[i][j] != 0.0) {
+        au.H[au.nH][0] = L.Hu[j][0]; au.H[au.nH][1] = L.Hu[j][1]; au.cH[au.nH++] = c->A[i][j];
+        au.G[au.nG] = L.Gq[j]; au.cG[au.nG++] = c->A[i][j];
+      }
+    }
+    au.out_u[0] = u1; au.out_u[1] = u2; au.out_q = qi;
+    const bool keep = !last && later_needs(i);
+    if (keep) {
+      au.out_hu[0] = L.Hu[i][0]; au.out_hu[1] = L.Hu[i][1]; au.out_gq = L.Gq[i];
+    } else {
+      au.out_hu[0] = au.out_hu[1] = au.out_gq = kNoSlot;
+    }
+    // the partner is u^n for the first stage: read once with u^n
+    const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
+    l.bytes = (reads + 3 + (keep ? 3 : 0)) * pt + pd;
+    plan.push_back(l);
+    // terms of this stage for later stages; the last stage's are the next step's
+    // stage-0 terms
+    l = Launch{};
+    l.cls = kStageTerms;
+    ArgsE &ae = l.e;
+    ae.u[0] = u1; ae.u[1] = u2; ae.q = qi; ae.v[0] = v1; ae.v[1] = v2; ae.th = th;
+    ae.ddb = L.ddb;
+    ae.out_e[0] = last ? L.E[0][0] : L.E[i][0];
+    ae.out_e[1] = last ? L.E[0][1] : L.E[i][1];
+    ae.out_du = last ? L.Du[0] : L.Du[i];
+    ae.out_lt = keep ? L.Lt[i] : kNoSlot;
+    l.bytes = (5 + 3 + (keep ? 2 : 0)) * pt + (keep ? pd : 0.0);
+    plan.push_back(l);
+  }
+  return plan;
+}
+
+template <typename T>
+hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
+  hipStream_t st = c->stream;
+  switch (l.cls) {
+    case kRelaxV: return launch_relax_v<T>(c->d_inst, c->d_tiles, c->ntiles, l.v, st);
+    case kHelmRhs: return launch_helmholtz_rhs<T>(c->d_inst, c->d_tiles, c->ntiles, l.r, st);
+    case kRowsFwd:
+    case kColumns:
+    case kRowsInv:
+      return launch_solve_part(l.cls - kRowsFwd, c->d_inst, c->d_rows, c->nrows, c->d_cols,
+                               c->ncols, l.sv, st);
+    case kUpdateUQ: return launch_update_uq<T>(c->d_inst, c->d_tiles, c->ntiles, l.uq, st);
+    default: return launch_stage_terms<T>(c->d_inst, c->d_tiles, c->ntiles, l.e, st);
+  }
+}
+
+template <typename T>
+apdvm_status stage0_terms(apdvm_ctx *c) {
+  const Layout &L = c->L;
+  const int P = c->parity;
+  ArgsE a{};
+  a.u[0] = L.st[P][0]; a.u[1] = L.st[P][1]; a.v[0] = L.st[P][2]; a.v[1] = L.st[P][3];
+  a.q = L.st[P][4]; a.th = L.th[P]; a.ddb = kNoSlot;
+  a.out_e[0] = L.E[0][0]; a.out_e[1] = L.E[0][1]; a.out_du = L.Du[0]; a.out_lt = kNoSlot;
+  if (launch_stage_terms<T>(c->d_inst, c->d_tiles, c->ntiles, a, c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  c->terms_ready = true;
+  return APDVM_OK;
+}
+
+template <typename T>
+apdvm_status run_plan_direct(apdvm_ctx *c, const std::vector<Launch> &plan) {
+  for (const Launch &l : plan) {
+    const bool timed = c->timed_class == l.cls;
+    if (timed) {
+      if (c->ev_used == c->events.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+          return APDVM_ERR_HIP;
+        c->events.push_back({a, b});
+      }
+      if (hipEventRecord(c->events[c->ev_used].first, c->stream) != hipSuccess)
+        return APDVM_ERR_HIP;
+    }
+    if (run_launch<T>(c, l) != hipSuccess) return APDVM_ERR_HIP;
+    if (timed) {
+      if (hipEventRecord(c->events[c->ev_used].second, c->stream) != hipSuccess)
+        return APDVM_ERR_HIP;
+      ++c->ev_used;
+    }
+  }
+  return APDVM_OK;
+}
+
+// Capture the plan of parity P into a graph (once).
+template <typename T>
+apdvm_status ensure_graph(apdvm_ctx *c, int P) {
+  if (c->graph_exec[P]) return APDVM_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return APDVM_ERR_HIP;
+  bool ok = true;
+  for (const Launch &l : c->plan[P]) ok = ok && run_launch<T>(c, l) == hipSuccess;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (!ok || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return APDVM_ERR_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return APDVM_ERR_HIP;
+  c->graph_exec[P] = ex;
+  return APDVM_OK;
+}
+
+template <typename T>
+apdvm_status enqueue_step(apdvm_ctx *c) {
+  if (!c->terms_ready) {
+    const apdvm_status st = stage0_terms<T>(c);
+    if (st != APDVM_OK) return st;
+  }
+  const int P = c->parity;
+  if (c->use_graph && c->timed_class < 0) {
+    apdvm_status st = ensure_graph<T>(c, P);
+    if (st != APDVM_OK) return st;
+    if (hipGraphLaunch(c->graph_exec[P], c->stream) != hipSuccess) return APDVM_ERR_HIP;
+  } else {
+    const apdvm_status st = run_plan_direct<T>(c, c->plan[P]);
+    if (st != APDVM_OK) return st;
+  }
+  c->parity = 1 - P;
+  return APDVM_OK;
+}
+
+bool all_finite(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+long double kahan_mean(const double *p, size_t n) {
+  long double s = 0.0L;
+  for (size_t i = 0; i < n; ++i) s += p[i];
+  return s / (long double)n;
+}
+
+template <typename T>
+apdvm_status put_plane(apdvm_ctx *c, int k, int slot, const double *src, bool dev_src) {
+  const Inst &I = c->inst[k];
+  const size_t n = (size_t)I.plane;
+  T *dst = reinterpret_cast<T *>(I.tbase) + (size_t)slot * n;
+  if (sizeof(T) == sizeof(double)) {
+    return hip_status(hipMemcpyAsync(dst, src, n * sizeof(double),
+                                     dev_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                     c->stream));
+  }
+  if (dev_src) {
+    std::vector<double> tmp(n);
+    if (hipMemcpyAsync(tmp.data(), src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return APDVM_ERR_HIP;
+    std::vector<T> t(n);
+    for (size_t i = 0; i < n; ++i) t[i] = (T)tmp[i];
+    if (hipMemcpyAsync(dst, t.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return APDVM_ERR_HIP;
+    return hip_status(hipStreamSynchronize(c->stream));
+  }
+  std::vector<T> t(n);
+  for (size_t i = 0; i < n; ++i) t[i] = (T)src[i];
+  if (hipMemcpyAsync(dst, t.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  return hip_status(hipStreamSynchronize(c->stream));
+}
+
+template <typename T>
+apdvm_status get_plane(apdvm_ctx *c, int k, int slot, double *dst, bool dev_dst) {
+  const Inst &I = c->inst[k];
+  const size_t n = (size_t)I.plane;
+  const T *src = reinterpret_cast<const T *>(I.tbase) + (size_t)slot * n;
+  if (sizeof(T) == sizeof(double)) {
+    return hip_status(hipMemcpyAsync(dst, src, n * sizeof(double),
+                                     dev_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                     c->stream));
+  }
+  std::vector<T> t(n);
+  if (hipMemcpyAsync(t.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  if (dev_dst) {
+    std::vector<double> d(n);
+    for (size_t i = 0; i < n; ++i) d[i] = (double)t[i];
+    if (hipMemcpyAsync(dst, d.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess)
+      return APDVM_ERR_HIP;
+    return hip_status(hipStreamSynchronize(c->stream));
+  }
+  for (size_t i = 0; i < n; ++i) dst[i] = (double)t[i];
+  return APDVM_OK;
+}
+
+apdvm_status put_state(apdvm_ctx *c, int k, const double *const f[6], bool dev) {
+  const Layout &L = c->L;
+  const int P = c->parity;
+  const int tslots[5] = {L.st[P][0], L.st[P][1], L.st[P][2], L.st[P][3], L.st[P][4]};
+  const int fidx[5] = {0, 1, 3, 4, 5};
+  for (int m = 0; m < 5; ++m) {
+    const apdvm_status st = c->split ? put_plane<float>(c, k, tslots[m], f[fidx[m]], dev)
+                                     : put_plane<double>(c, k, tslots[m], f[fidx[m]], dev);
+    if (st != APDVM_OK) return st;
+  }
+  const Inst &I = c->inst[k];
+  double *th = I.dbase + (size_t)L.th[P] * I.plane;
+  return hip_status(hipMemcpyAsync(th, f[2], (size_t)I.plane * sizeof(double),
+                                   dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+}
+
+apdvm_status get_state(apdvm_ctx *c, int k, double *const f[6], bool dev) {
+  const Layout &L = c->L;
+  const int P = c->parity;
+  const int tslots[5] = {L.st[P][0], L.st[P][1], L.st[P][2], L.st[P][3], L.st[P][4]};
+  const int fidx[5] = {0, 1, 3, 4, 5};
+  for (int m = 0; m < 5; ++m) {
+    if (!f[fidx[m]]) continue;
+    const apdvm_status st = c->split ? get_plane<float>(c, k, tslots[m], f[fidx[m]], dev)
+                                     : get_plane<double>(c, k, tslots[m], f[fidx[m]], dev);
+    if (st != APDVM_OK) return st;
+  }
+  if (f[2]) {
+    const Inst &I = c->inst[k];
+    const double *th = I.dbase + (size_t)L.th[P] * I.plane;
+    if (hipMemcpyAsync(f[2], th, (size_t)I.plane * sizeof(double),
+                       dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return APDVM_ERR_HIP;
+  }
+  if (!dev) return hip_status(hipStreamSynchronize(c->stream));
+  return APDVM_OK;
+}
+
+// After new fields for instance k: theta mean, dt derivation, parameter upload.
+apdvm_status after_fields(apdvm_ctx *c, int k, const double *theta_host, const double *u1,
+                          const double *u2) {
+  Inst &I = c->inst[k];
+  const size_t n = (size_t)I.plane;
+  I.theta_mean = (double)kahan_mean(theta_host, n);
+  double um = 0.0;
+  for (size_t i = 0; i < n; ++i) um = std::fmax(um, std::sqrt(u1[i] * u1[i] + u2[i] * u2[i]));
+  c->umax[k] = um;
+  const apdvm_config &cf = c->cfg[k];
+  if (!(cf.dt > 0.0)) {
+    double ct = 0.0;
+    for (int i = 0; i < c->s; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < i; ++j) r += c->At[i][j];
+      ct = std::fmax(ct, r);
+    }
+    if (ct <= 0.0) ct = 1.0;
+    set_dt(c, k, derive_dt(cf, I.tau, um, ct));
+  }
+  c->has_fields[k] = 1;
+  c->terms_ready = false;
+  return upload_inst(c, k);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *apdvm_status_string(apdvm_status s) {
+  switch (s) {
+    case APDVM_OK: return "ok";
+    case APDVM_ERR_ARG: return "invalid argument";
+    case APDVM_ERR_VELSET: return "velocity set is not the six-velocity hexagonal set";
+    case APDVM_ERR_TABLEAU: return "tableau is not a GSA ARS-type IMEX Runge-Kutta tableau";
+    case APDVM_ERR_NOMEM: return "out of device memory or workspace too small";
+    case APDVM_ERR_HIP: return "HIP runtime error";
+    case APDVM_ERR_NONFINITE: return "non-finite value";
+    case APDVM_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+apdvm_status apdvm_workspace_bytes(int32_t n, const apdvm_config *cfgs, size_t *bytes) {
+  if (!bytes) return APDVM_ERR_ARG;
+  const apdvm_status st = validate(n, cfgs);
+  if (st != APDVM_OK) return st;
+  *bytes = workspace_bytes(n, cfgs);
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, size_t ws_bytes,
+                          void *hip_stream, apdvm_ctx **out) {
+  if (!out) return APDVM_ERR_ARG;
+  *out = nullptr;
+  apdvm_status st = validate(n, cfgs);
+  if (st != APDVM_OK) return st;
+  const size_t need = workspace_bytes(n, cfgs);
+  if (dev_ws && ws_bytes < need) return APDVM_ERR_NOMEM;
+
+  apdvm_ctx *c = new (std::nothrow) apdvm_ctx;
+  if (!c) return APDVM_ERR_NOMEM;
+  c->n = n;
+  c->s = cfgs[0].s;
+  c->split = cfgs[0].precision == APDVM_FP32_SPLIT;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->cfg.assign(cfgs, cfgs + n);
+  for (int k = 0; k < n; ++k) {  // the caller's tableau arrays need not outlive the call
+    c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
+    c->cfg[k].cx = c->cfg[k].cy = nullptr;
+  }
+  for (int i = 0; i < c->s; ++i)
+    for (int j = 0; j < c->s; ++j) {
+      c->At[i][j] = cfgs[0].a_ex[i * c->s + j];
+      c->A[i][j] = cfgs[0].a_im[i * c->s + j];
+    }
+  c->L = make_layout(c->s);
+  c->has_fields.assign(n, 0);
+  c->umax.assign(n, 0.0);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return APDVM_ERR_HIP;
+  }
+  if (dev_ws) {
+    c->ws = static_cast<char *>(dev_ws);
+    c->ws_bytes = ws_bytes;
+  } else {
+    if (hipMalloc(&c->ws, need) != hipSuccess) {
+      delete c;
+      return APDVM_ERR_NOMEM;
+    }
+    c->own_ws = true;
+    c->ws_bytes = need;
+  }
+
+  // carve the workspace
+  const size_t tsize = c->split ? sizeof(float) : sizeof(double);
+  const int ty = c->split ? tile_rows<float>() : tile_rows<double>();
+  char *p = c->ws;
+  c->d_inst = reinterpret_cast<Inst *>(p);
+  p += align_up(n * sizeof(Inst));
+  c->inst.resize(n);
+  std::vector<Work> rows, cols;
+  std::vector<char> host_tables;
+  struct Upload { char *dst; std::vector<char> data; };
+  std::vector<Upload> uploads;
+  for (int k = 0; k < n; ++k) {
+    const apdvm_config &cf = cfgs[k];
+    Inst &I = c->inst[k];
+    std::memset(&I, 0, sizeof(I));
+    I.nx = cf.nx;
+    I.ny = cf.ny;
+    I.plane = (long long)cf.nx * cf.ny;
+    I.ihx = cf.nx / cf.lx;
+    I.ihy = cf.ny / cf.ly;
+    I.eps = cf.eps;
+    I.tau = resolved_tau(cf);
+    I.te2 = I.tau * cf.eps * cf.eps;
+    I.inv_nxny = 1.0 / ((double)cf.nx * cf.ny);
+    const size_t plane = (size_t)I.plane;
+    I.tbase = p;
+    p += align_up(c->L.ntrans * plane * tsize);
+    I.dbase = reinterpret_cast<double *>(p);
+    p += align_up(c->L.ndbl * plane * sizeof(double));
+    // twiddles
+    double2 *tw = reinterpret_cast<double2 *>(p);
+    p += align_up((size_t)(cf.nx + cf.ny) * sizeof(double2));
+    Upload u1{reinterpret_cast<char *>(tw), std::vector<char>((cf.nx + cf.ny) * sizeof(double2))};
+    twiddles(cf.nx, reinterpret_cast<double2 *>(u1.data.data()));
+    twiddles(cf.ny, reinterpret_cast<double2 *>(u1.data.data()) + cf.nx);
+    uploads.push_back(std::move(u1));
+    I.fx.n = cf.nx;
+    I.fx.npass = fft_radices(cf.nx, I.fx.radix);
+    I.fx.tw = tw;
+    I.fy.n = cf.ny;
+    I.fy.npass = fft_radices(cf.ny, I.fy.radix);
+    I.fy.tw = tw + cf.nx;
+    // symbols
+    double *lam = reinterpret_cast<double *>(p);
+    p += align_up((size_t)(cf.nx / 2 + 1 + cf.ny) * sizeof(double));
+    Upload u2{reinterpret_cast<char *>(lam),
+              std::vector<char>((cf.nx / 2 + 1 + cf.ny) * sizeof(double))};
+    double *hl = reinterpret_cast<double *>(u2.data.data());
+    for (int kx = 0; kx <= cf.nx / 2; ++kx) hl[kx] = lap_symbol(kx, cf.nx, cf.lx / cf.nx);
+    for (int ky = 0; ky < cf.ny; ++ky) hl[cf.nx / 2 + 1 + ky] = lap_symbol(ky, cf.ny, cf.ly / cf.ny);
+    uploads.push_back(std::move(u2));
+    I.lam_x = lam;
+    I.lam_y = lam + cf.nx / 2 + 1;
+    I.row_pairs_per_block = rpb(cf);
+    I.cols_per_block = cpb(cf);
+    // work tables
+    c->tile_first.push_back((int)c->tiles.size());
+    for (int y0 = 0; y0 < cf.ny; y0 += ty)
+      for (int x0 = 0; x0 < cf.nx; x0 += kTileX) c->tiles.push_back(Work{k, x0, y0, 0});
+    c->tile_count.push_back((int)c->tiles.size() - c->tile_first.back());
+    for (int r0 = 0; r0 < cf.ny / 2; r0 += I.row_pairs_per_block) rows.push_back(Work{k, r0, 0, 0});
+    for (int k0 = 0; k0 < cf.nx / 2; k0 += I.cols_per_block) cols.push_back(Work{k, k0, 0, 0});
+    c->cfg[k] = cf;
+    c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
+    c->cfg[k].cx = c->cfg[k].cy = nullptr;
+    set_dt(c, k, cf.dt > 0.0 ? cf.dt : 0.0);
+  }
+  for (int k = 0; k < n; ++k) c->cells += (double)cfgs[k].nx * cfgs[k].ny;
+  c->plan[0] = build_plan(c, 0);
+  c->plan[1] = build_plan(c, 1);
+  c->ntiles = (int)c->tiles.size();
+  c->nrows = (int)rows.size();
+  c->ncols = (int)cols.size();
+  c->d_tiles = reinterpret_cast<Work *>(p);
+  p += align_up(c->tiles.size() * sizeof(Work));
+  c->d_rows = reinterpret_cast<Work *>(p);
+  p += align_up(rows.size() * sizeof(Work));
+  c->d_cols = reinterpret_cast<Work *>(p);
+  p += align_up(cols.size() * sizeof(Work));
+  c->d_partials = reinterpret_cast<double *>(p);
+  p += align_up(8 * sizeof(double) * 1024);
+
+  bool ok = hipMemcpyAsync(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(Work),
+                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(c->d_rows, rows.data(), rows.size() * sizeof(Work),
+                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(c->d_cols, cols.data(), cols.size() * sizeof(Work),
+                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(c->d_inst, c->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice,
+                           c->stream) == hipSuccess;
+  for (auto &u : uploads)
+    ok = ok && hipMemcpyAsync(u.dst, u.data.data(), u.data.size(), hipMemcpyHostToDevice,
+                              c->stream) == hipSuccess;
+  ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    apdvm_destroy(c);
+    return APDVM_ERR_HIP;
+  }
+  *out = c;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_set_fields(apdvm_ctx *c, int32_t k, const double *u1, const double *u2,
+                              const double *theta, const double *v1, const double *v2,
+                              const double *q) {
+  if (!c || k < 0 || k >= c->n || !u1 || !u2 || !theta) return APDVM_ERR_ARG;
+  if ((v1 == nullptr) != (v2 == nullptr)) return APDVM_ERR_ARG;
+  const size_t n = (size_t)c->inst[k].plane;
+  if (!all_finite(u1, n) || !all_finite(u2, n) || !all_finite(theta, n)) return APDVM_ERR_NONFINITE;
+  if (v1 && (!all_finite(v1, n) || !all_finite(v2, n))) return APDVM_ERR_NONFINITE;
+  if (q && !all_finite(q, n)) return APDVM_ERR_NONFINITE;
+  std::vector<double> ev1, ev2, zq;
+  if (!v1) {  // local equilibrium v = F(u)
+    ev1.resize(n);
+    ev2.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+      ev1[i] = 0.5 * (u2[i] * u2[i] - u1[i] * u1[i]);
+      ev2[i] = u1[i] * u2[i];
+    }
+    v1 = ev1.data();
+    v2 = ev2.data();
+  }
+  if (!q) {
+    zq.assign(n, 0.0);
+    q = zq.data();
+  }
+  const double *f[6] = {u1, u2, theta, v1, v2, q};
+  apdvm_status st = put_state(c, k, f, false);
+  if (st != APDVM_OK) return st;
+  st = after_fields(c, k, theta, u1, u2);
+  if (st != APDVM_OK) return st;
+  // the copies read caller-owned and temporary host arrays: finish them here
+  return hip_status(hipStreamSynchronize(c->stream));
+}
+
+apdvm_status apdvm_set_fields_device(apdvm_ctx *c, int32_t k, const double *const dev[6]) {
+  if (!c || k < 0 || k >= c->n || !dev) return APDVM_ERR_ARG;
+  for (int m = 0; m < 6; ++m)
+    if (!dev[m]) return APDVM_ERR_ARG;
+  apdvm_status st = put_state(c, k, dev, true);
+  if (st != APDVM_OK) return st;
+  // the mean of theta and the dt rule need host copies of theta and u
+  const size_t n = (size_t)c->inst[k].plane;
+  std::vector<double> th(n), u1(n), u2(n);
+  if (hipMemcpyAsync(th.data(), dev[2], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(u1.data(), dev[0], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(u2.data(), dev[1], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  st = after_fields(c, k, th.data(), u1.data(), u2.data());
+  if (st != APDVM_OK) return st;
+  return hip_status(hipStreamSynchronize(c->stream));
+}
+
+apdvm_status apdvm_set_populations(apdvm_ctx *c, int32_t k, const double *F) {
+  if (!c || k < 0 || k >= c->n || !F) return APDVM_ERR_ARG;
+  const double eps = c->inst[k].eps;
+  if (!(eps > 0.0)) return APDVM_ERR_ARG;
+  const size_t n = (size_t)c->inst[k].plane;
+  if (!all_finite(F, 6 * n)) return APDVM_ERR_NONFINITE;
+  // moment basis rows: 1, cx, cy, 1/2 - cx^2, cx cy, cx (cy^2 - 1/4)
+  double m[6][6];
+  for (int i = 0; i < 6; ++i) {
+    const double cx = std::cos(M_PI * i / 3.0), cy = std::sin(M_PI * i / 3.0);
+    m[0][i] = 1.0; m[1][i] = cx; m[2][i] = cy; m[3][i] = 0.5 - cx * cx; m[4][i] = cx * cy;
+    m[5][i] = cx * (cy * cy - 0.25);
+  }
+  std::vector<double> f(6 * n);
+  for (size_t x = 0; x < n; ++x) {
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 6; ++i)
+      for (int a = 0; a < 6; ++a) r[a] += m[a][i] * F[i * n + x];
+    f[0 * n + x] = r[1] / eps;                     // u1
+    f[1 * n + x] = r[2] / eps;                     // u2
+    f[2 * n + x] = (r[0] - 1.0) / (2 * eps * eps); // theta
+    f[3 * n + x] = r[3] / (eps * eps);             // v1
+    f[4 * n + x] = r[4] / (eps * eps);             // v2
+    f[5 * n + x] = r[5] / (eps * eps * eps);       // q
+  }
+  return apdvm_set_fields(c, k, &f[0], &f[n], &f[2 * n], &f[3 * n], &f[4 * n], &f[5 * n]);
+}
+
+apdvm_status apdvm_step(apdvm_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return APDVM_ERR_ARG;
+  for (int k = 0; k < c->n; ++k)
+    if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  if (hipSetDevice(c->device) != hipSuccess) return APDVM_ERR_HIP;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    const apdvm_status st = c->split ? enqueue_step<float>(c) : enqueue_step<double>(c);
+    if (st != APDVM_OK) return st;
+    ++c->step;
+  }
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_get_fields(apdvm_ctx *c, int32_t k, double *u1, double *u2, double *theta,
+                              double *v1, double *v2, double *q) {
+  if (!c || k < 0 || k >= c->n) return APDVM_ERR_ARG;
+  if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  double *const f[6] = {u1, u2, theta, v1, v2, q};
+  return get_state(c, k, f, false);
+}
+
+apdvm_status apdvm_get_fields_device(apdvm_ctx *c, int32_t k, double *const dev[6]) {
+  if (!c || k < 0 || k >= c->n || !dev) return APDVM_ERR_ARG;
+  if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  return get_state(c, k, dev, true);
+}
+
+apdvm_status apdvm_get_moments(apdvm_ctx *c, int32_t k, double *rho, double *u1, double *u2,
+                               double *p) {
+  if (!c || k < 0 || k >= c->n) return APDVM_ERR_ARG;
+  const size_t n = (size_t)c->inst[k].plane;
+  std::vector<double> a(n), b(n), th(n);
+  apdvm_status st = apdvm_get_fields(c, k, a.data(), b.data(), th.data(), nullptr, nullptr, nullptr);
+  if (st != APDVM_OK) return st;
+  const double e2 = c->inst[k].eps * c->inst[k].eps;
+  for (size_t i = 0; i < n; ++i) {
+    if (rho) rho[i] = 1.0 + 2.0 * e2 * th[i];
+    if (u1) u1[i] = a[i];
+    if (u2) u2[i] = b[i];
+    if (p) p[i] = th[i] - 0.5 * (a[i] * a[i] + b[i] * b[i]);
+  }
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_get_populations(apdvm_ctx *c, int32_t k, double *F) {
+  if (!c || k < 0 || k >= c->n || !F) return APDVM_ERR_ARG;
+  const double eps = c->inst[k].eps;
+  if (!(eps > 0.0)) return APDVM_ERR_ARG;
+  const size_t n = (size_t)c->inst[k].plane;
+  std::vector<double> f(6 * n);
+  apdvm_status st = apdvm_get_fields(c, k, &f[0], &f[n], &f[2 * n], &f[3 * n], &f[4 * n], &f[5 * n]);
+  if (st != APDVM_OK) return st;
+  // F_i = sum_a m_a(i) M_a / |m_a|^2 (the basis is orthogonal with norms 6, 3, 3, 3/4,
+  // 3/4, 3/8), with M = (1 + 2 eps^2 theta, eps u1, eps u2, eps^2 v1, eps^2 v2, eps^3 q).
+  const double nrm[6] = {6.0, 3.0, 3.0, 0.75, 0.75, 0.375};
+  for (int i = 0; i < 6; ++i) {
+    const double cx = std::cos(M_PI * i / 3.0), cy = std::sin(M_PI * i / 3.0);
+    const double m[6] = {1.0, cx, cy, 0.5 - cx * cx, cx * cy, cx * (cy * cy - 0.25)};
+    for (size_t x = 0; x < n; ++x) {
+      const double M[6] = {1.0 + 2.0 * eps * eps * f[2 * n + x], eps * f[x], eps * f[n + x],
+                           eps * eps * f[3 * n + x], eps * eps * f[4 * n + x],
+                           eps * eps * eps * f[5 * n + x]};
+      double v = 0.0;
+      for (int a = 0; a < 6; ++a) v += m[a] * M[a] / nrm[a];
+      F[i * n + x] = v;
+    }
+  }
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_get_info(apdvm_ctx *c, int32_t k, double *dt, double *tau, int64_t *step) {
+  if (!c || k < 0 || k >= c->n) return APDVM_ERR_ARG;
+  if (dt) *dt = c->inst[k].dt;
+  if (tau) *tau = c->inst[k].tau;
+  if (step) *step = c->step;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_set_step(apdvm_ctx *c, int64_t step) {
+  if (!c || step < 0) return APDVM_ERR_ARG;
+  c->step = step;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
+  if (!c || k < 0 || k >= c->n || !out) return APDVM_ERR_ARG;
+  if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  const Layout &L = c->L;
+  const int P = c->parity;
+  const int nblk = c->tile_count[k];
+  const int cap = 1024;
+  const int used = nblk < cap ? nblk : cap;
+  const int ty = c->split ? tile_rows<float>() : tile_rows<double>();
+  if (launch_diagnostics(c->d_inst, c->d_tiles + c->tile_first[k], nblk, ty, c->split ? 1 : 0,
+                         L.st[P][0], L.st[P][1], L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
+                         c->d_partials, used, c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  std::vector<double> part(8 * (size_t)used);
+  if (hipMemcpyAsync(part.data(), c->d_partials, part.size() * sizeof(double),
+                     hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  const Inst &I = c->inst[k];
+  const double area = (1.0 / I.ihx) * (1.0 / I.ihy);
+  double acc[8] = {0, 0, 0, 0, 1e300, -1e300, 0, 1};
+  for (int b = 0; b < used; ++b) {
+    const double *q = &part[8 * (size_t)b];
+    acc[0] += q[0]; acc[1] += q[1]; acc[2] += q[2];
+    acc[3] = std::fmax(acc[3], q[3]);
+    acc[4] = std::fmin(acc[4], q[4]);
+    acc[5] = std::fmax(acc[5], q[5]);
+    acc[6] += q[6];
+    acc[7] = std::fmin(acc[7], q[7]);
+  }
+  out[0] = acc[0] * area; out[1] = acc[1] * area; out[2] = acc[2] * area;
+  out[3] = acc[3]; out[4] = acc[4]; out[5] = acc[5];
+  out[6] = 0.5 * acc[6] * area; out[7] = acc[7];
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_launches_per_step(apdvm_ctx *c, int32_t *count) {
+  if (!c || !count) return APDVM_ERR_ARG;
+  *count = (int32_t)c->plan[0].size();
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_set_graph(apdvm_ctx *c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return APDVM_ERR_ARG;
+  if (on && c->stream == nullptr) return APDVM_ERR_ARG;  // capture needs a created stream
+  c->use_graph = on != 0;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_timing_enable(apdvm_ctx *c, int32_t cls) {
+  if (!c || cls < -1 || cls >= kNumClasses) return APDVM_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return APDVM_ERR_HIP;
+  c->timed_class = cls;
+  c->ev_used = 0;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_timing_read(apdvm_ctx *c, int64_t *launches, double *total_ms) {
+  if (!c || !launches || !total_ms) return APDVM_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return APDVM_ERR_HIP;
+  double tot = 0.0;
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->events[i].first, c->events[i].second) != hipSuccess)
+      return APDVM_ERR_HIP;
+    tot += ms;
+  }
+  *launches = (int64_t)c->ev_used;
+  *total_ms = tot;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_traffic(apdvm_ctx *c, int32_t cls, double *bytes_per_step,
+                           int32_t *launches_per_step) {
+  if (!c || !bytes_per_step || !launches_per_step || cls < -1 || cls >= kNumClasses)
+    return APDVM_ERR_ARG;
+  double b = 0.0;
+  int n = 0;
+  for (const Launch &l : c->plan[0]) {
+    if (cls >= 0 && l.cls != cls) continue;
+    b += l.bytes;
+    ++n;
+  }
+  *bytes_per_step = b;
+  *launches_per_step = n;
+  return APDVM_OK;
+}
+
+void apdvm_destroy(apdvm_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int p = 0; p < 2; ++p)
+    if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
+  for (auto &e : c->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+}  // extern "C"

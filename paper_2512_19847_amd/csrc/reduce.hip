@@ -1,0 +1,127 @@
+// Diagnostics of one instance: sum theta, sum u1, sum u2, max |D0.u| (the divergence
+// diagnostic of Section 4), min and max of the vorticity D_x u2 - D_y u1, sum |u|^2
+// and a finite flag over all six fields.  Two levels: each workgroup reduces its tiles
+// with wavefront shuffles and LDS into one record of partials; the host combines the
+// records (deterministic: no atomics).
+#include "common.hpp"
+
+namespace apdvm {
+
+namespace {
+
+__device__ __forceinline__ int wrapi(int g, int n) {
+  if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
+  return g;
+}
+
+template <typename T>
+__device__ __forceinline__ double at(const T *p, int nx, int ny, int x, int y) {
+  return (double)p[(long long)wrapi(y, ny) * nx + wrapi(x, nx)];
+}
+
+template <typename T>
+__device__ __forceinline__ double dcen(const T *p, int nx, int ny, int x, int y, int ox, int oy,
+                                       double ih12) {
+  return (at(p, nx, ny, x - 2 * ox, y - 2 * oy) - 8.0 * at(p, nx, ny, x - ox, y - oy) +
+          8.0 * at(p, nx, ny, x + ox, y + oy) - at(p, nx, ny, x + 2 * ox, y + 2 * oy)) *
+         ih12;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
+                                              const Work *__restrict__ tiles, int ntiles, int ty,
+                                              int su1, int su2, int dth, int sv1, int sv2, int sq,
+                                              double *__restrict__ partials) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 1e300, -1e300, 0.0, 1.0};
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Work wk = tiles[t];
+    const Inst &I = insts[wk.inst];
+    const int nx = I.nx, ny = I.ny;
+    const T *tb = reinterpret_cast<const T *>(I.tbase);
+    const T *u1 = tb + (long long)su1 * I.plane, *u2 = tb + (long long)su2 * I.plane;
+    const T *v1 = tb + (long long)sv1 * I.plane, *v2 = tb + (long long)sv2 * I.plane;
+    const T *q = tb + (long long)sq * I.plane;
+    const double *th = I.dbase + (long long)dth * I.plane;
+    const double ihx12 = I.ihx / 12.0, ihy12 = I.ihy / 12.0;
+    const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+    const int x = wk.a + tx;
+    if (x >= nx) continue;
+    for (int ly = ty0; ly < ty; ly += 4) {
+      const int y = wk.b + ly;
+      if (y >= ny) break;
+      const long long g = (long long)y * nx + x;
+      const double a = (double)u1[g], b = (double)u2[g], c = th[g];
+      acc[0] += c;
+      acc[1] += a;
+      acc[2] += b;
+      const double div = dcen(u1, nx, ny, x, y, 1, 0, ihx12) + dcen(u2, nx, ny, x, y, 0, 1, ihy12);
+      const double vor = dcen(u2, nx, ny, x, y, 1, 0, ihx12) - dcen(u1, nx, ny, x, y, 0, 1, ihy12);
+      acc[3] = fmax(acc[3], fabs(div));
+      acc[4] = fmin(acc[4], vor);
+      acc[5] = fmax(acc[5], vor);
+      acc[6] += a * a + b * b;
+      const bool fin = isfinite(a) && isfinite(b) && isfinite(c) && isfinite((double)v1[g]) &&
+                       isfinite((double)v2[g]) && isfinite((double)q[g]);
+      if (!fin) acc[7] = 0.0;
+    }
+  }
+  __shared__ double red[4][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double r[8];
+  r[0] = wave_sum(acc[0]);
+  r[1] = wave_sum(acc[1]);
+  r[2] = wave_sum(acc[2]);
+  r[3] = wave_max(acc[3]);
+  r[4] = wave_min(acc[4]);
+  r[5] = wave_max(acc[5]);
+  r[6] = wave_sum(acc[6]);
+  r[7] = wave_min(acc[7]);
+  if (lane == 0)
+    for (int k = 0; k < 8; ++k) red[w][k] = r[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o[8];
+    for (int k = 0; k < 8; ++k) o[k] = red[0][k];
+    for (int ww = 1; ww < 4; ++ww) {
+      o[0] += red[ww][0];
+      o[1] += red[ww][1];
+      o[2] += red[ww][2];
+      o[3] = fmax(o[3], red[ww][3]);
+      o[4] = fmin(o[4], red[ww][4]);
+      o[5] = fmax(o[5], red[ww][5]);
+      o[6] += red[ww][6];
+      o[7] = fmin(o[7], red[ww][7]);
+    }
+    for (int k = 0; k < 8; ++k) partials[8 * blockIdx.x + k] = o[k];
+  }
+}
+
+}  // namespace
+
+// tiles: the stencil work items (64 x ty cells) of one instance.
+hipError_t launch_diagnostics(const Inst *insts, const Work *tiles, int ntiles, int ty, int split,
+                              int su1, int su2, int dth, int sv1, int sv2, int sq,
+                              double *partials, int nblocks, hipStream_t st) {
+  if (split)
+    hipLaunchKernelGGL(k_diag<float>, dim3(nblocks), dim3(256), 0, st, insts, tiles, ntiles, ty,
+                       su1, su2, dth, sv1, sv2, sq, partials);
+  else
+    hipLaunchKernelGGL(k_diag<double>, dim3(nblocks), dim3(256), 0, st, insts, tiles, ntiles, ty,
+                       su1, su2, dth, sv1, sv2, sq, partials);
+  return hipGetLastError();
+}
+
+}  // namespace apdvm
