@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--workload", default="shear512")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (torch copy kernel) so that "
+                         "hardware byte counters can be scaled against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -88,6 +91,15 @@ def main():
 
     import torch
     from paper_2512_19847_amd import apdvm
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 3 copies of 268435456 bytes", file=sys.stderr)
+        del src, dst
 
     cases, tab, cfg = workload(args.workload)
     prec = apdvm.FP32_SPLIT if args.precision == "fp32split" else apdvm.FP64

@@ -166,11 +166,13 @@ apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
  * needs a created (non-NULL) stream at apdvm_create, else APDVM_ERR_ARG. */
 apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
 
-/* Kernel classes of a step, used by the two profiling calls below:
+/* Kernel classes of a step, used by the profiling calls below:
  * 0 step-1 relaxation of v, 1 step-2 right-hand side, 2 Helmholtz rows forward FFT,
- * 3 Helmholtz columns (FFT, symbol divide, inverse FFT), 4 Helmholtz rows inverse FFT,
- * 5 steps 3 and 4 (u and q updates), 6 stage terms reused by later stages. */
-#define APDVM_NUM_KERNEL_CLASSES 7
+ * 3 Helmholtz column FFT first factor, 4 Helmholtz column FFT second factor with the
+ * symbol divide and its inverse, 5 inverse column FFT first factor, 6 Helmholtz rows
+ * inverse FFT, 7 steps 3 and 4 (u and q updates), 8 stage terms reused by later
+ * stages. */
+#define APDVM_NUM_KERNEL_CLASSES 9
 
 /* From now on bracket every launch of kernel class cls with a pair of HIP events on
  * the context's stream (cls = -1 stops); graph replay is bypassed while a class is

@@ -25,8 +25,9 @@ LIB_PATH = os.path.join(_HERE, "libapdvm.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "apdvm.h")
 
 FP64, FP32_SPLIT = 0, 1
-KERNEL_CLASSES = ("relax_v", "helmholtz_rhs", "fft_rows_forward", "fft_columns",
-                  "fft_rows_inverse", "update_uq", "stage_terms")
+KERNEL_CLASSES = ("relax_v", "helmholtz_rhs", "fft_rows_forward", "fft_columns_a",
+                  "fft_columns_b", "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
+                  "stage_terms")
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_VELSET", 3: "ERR_TABLEAU", 4: "ERR_NOMEM",
           5: "ERR_HIP", 6: "ERR_NONFINITE", 7: "ERR_STATE"}
 

@@ -28,9 +28,15 @@ constexpr int kTileX = 64;
 constexpr int kHalo = 3;
 constexpr int kStencilThreads = 256;
 
-// FFT workgroups: capacity in complex float64 values held in LDS, and threads.
+// FFT row workgroups: capacity in complex float64 values held in LDS, and threads.
+// The large form takes rows longer than kRowSmallCap.
 constexpr int kFftCap = 8192;
 constexpr int kFftThreads = 1024;
+constexpr int kRowSmallCap = 1024;
+constexpr int kRowSmallThreads = 128;
+// FFT column tiles: columns per tile (16 complex float64 = 256 contiguous bytes per row).
+constexpr int kColWidth = 16;
+constexpr int kColBTarget = 1024;  // complex values per column-B tile
 
 struct FftPlan {
   int n;                  // transform length
@@ -48,13 +54,15 @@ struct Inst {
   double kinv[kMaxStages];   // 1 / (tau eps^2 + dt a_ii)
   double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
   double inv_nxny;           // 1 / (nx ny)
-  FftPlan fx, fy;
+  FftPlan fx, fy;            // lengths nx and ny (fy supplies the ny-point twiddles)
+  FftPlan f1, f2;            // four-step factors of the column FFT: ny = n1 * n2
   const double *lam_x;       // nx/2 + 1 values of the x symbol of D_Delta
   const double *lam_y;       // ny values of the y symbol
   void *tbase;               // transport arena
   double *dbase;             // float64 arena
   int row_pairs_per_block;   // FFT row kernels: row pairs per workgroup
-  int cols_per_block;        // FFT column kernel: complex columns per workgroup
+  int cols_per_block;        // FFT column kernels: complex columns per tile
+  int groups_per_block;      // FFT column kernel B: k1 groups per tile
 };
 
 // Work table entry: instance and the first cell / row pair / column of the block.
@@ -126,7 +134,8 @@ struct ArgsE {
   int out_e[2], out_du, out_lt;
 };
 
-// Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec.
+// Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec
+// (ny x (nx/2 + 1) complex: the last float64 slot, with 2 ny extra doubles).
 struct ArgsSolve {
   int stage;
   int r, spec, out;

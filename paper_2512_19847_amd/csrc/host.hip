@@ -21,8 +21,8 @@ template <typename T>
 hipError_t launch_update_uq(const Inst *, const Work *, int, const ArgsUQ &, hipStream_t);
 template <typename T>
 hipError_t launch_stage_terms(const Inst *, const Work *, int, const ArgsE &, hipStream_t);
-hipError_t launch_solve_part(int part, const Inst *, const Work *, int, const Work *, int,
-                             const ArgsSolve &, hipStream_t);
+hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
+                             int, const Work *, int, const ArgsSolve &, hipStream_t);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
                               int, double *, int, hipStream_t);
 
@@ -217,24 +217,53 @@ struct Sizes {
 int n_tiles(const apdvm_config &c, int ty) {
   return ((c.nx + kTileX - 1) / kTileX) * ((c.ny + ty - 1) / ty);
 }
-int rpb(const apdvm_config &c) {
-  int r = kFftCap / c.nx;
+// Row FFT kernels: the large form holds 8192 complex values, the small one 1024.
+bool big_rows(int n, const apdvm_config *cfgs) {
+  for (int k = 0; k < n; ++k)
+    if (cfgs[k].nx > kRowSmallCap) return true;
+  return false;
+}
+int rpb(const apdvm_config &c, bool big) {
+  int r = (big ? kFftCap : kRowSmallCap) / c.nx;
   if (r > c.ny / 2) r = c.ny / 2;
   return r < 1 ? 1 : r;
 }
-int cpb(const apdvm_config &c) {
-  int r = kFftCap / c.ny;
-  if (r > c.nx / 2) r = c.nx / 2;
-  return r < 1 ? 1 : r;
+// Column FFT of length ny = n1 n2 with n2 the largest divisor not above sqrt(ny).
+int col_n2(int ny) {
+  int best = 1;
+  for (int d = 2; d * d <= ny; ++d)
+    if (ny % d == 0) best = d;
+  return best;
 }
-int n_rowblocks(const apdvm_config &c) { return (c.ny / 2 + rpb(c) - 1) / rpb(c); }
-int n_colblocks(const apdvm_config &c) { return (c.nx / 2 + cpb(c) - 1) / cpb(c); }
+int cpb(const apdvm_config &c) {
+  // tiles of column kernels A (n1 x C) and B (n2 x G x C) must fit 2048 complex values
+  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
+  int w = kColWidth;
+  if (w > c.nx / 2 + 1) w = c.nx / 2 + 1;
+  while (w > 1 && (n1 * w > 2048 || n2 * w > 2048)) --w;
+  return w;
+}
+int gpb(const apdvm_config &c) {
+  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
+  int g = kColBTarget / (n2 * cpb(c));
+  if (g > n1) g = n1;
+  return g < 1 ? 1 : g;
+}
+int n_rowblocks(const apdvm_config &c, bool big) { return (c.ny / 2 + rpb(c, big) - 1) / rpb(c, big); }
+int n_strips(const apdvm_config &c) { return (c.nx / 2 + 1 + cpb(c) - 1) / cpb(c); }
+int n_colablocks(const apdvm_config &c) { return n_strips(c) * col_n2(c.ny); }
+int n_colbblocks(const apdvm_config &c) {
+  const int n1 = c.ny / col_n2(c.ny);
+  return n_strips(c) * ((n1 + gpb(c) - 1) / gpb(c));
+}
 
 size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
   const size_t plane = (size_t)c.nx * c.ny;
-  size_t b = align_up(L.ntrans * plane * tsize) + align_up(L.ndbl * plane * sizeof(double));
-  b += align_up((size_t)(c.nx + c.ny) * sizeof(double2));           // twiddles
-  b += align_up((size_t)(c.nx / 2 + 1 + c.ny) * sizeof(double));    // symbols
+  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
+  size_t b = align_up(L.ntrans * plane * tsize);
+  b += align_up((L.ndbl * plane + 2 * (size_t)c.ny) * sizeof(double));  // spectrum tail
+  b += align_up((size_t)(c.nx + c.ny + n1 + n2) * sizeof(double2));     // twiddles
+  b += align_up((size_t)(c.nx / 2 + 1 + c.ny) * sizeof(double));        // symbols
   return b;
 }
 
@@ -244,14 +273,17 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
   const size_t tsize = split ? sizeof(float) : sizeof(double);
   const int ty = split ? tile_rows<float>() : tile_rows<double>();
   size_t b = align_up(n * sizeof(Inst));
-  size_t ntile = 0, nrow = 0, ncol = 0;
+  const bool big = big_rows(n, cfgs);
+  size_t ntile = 0, nrow = 0, ncola = 0, ncolb = 0;
   for (int k = 0; k < n; ++k) {
     b += inst_bytes(cfgs[k], L, tsize);
     ntile += n_tiles(cfgs[k], ty);
-    nrow += n_rowblocks(cfgs[k]);
-    ncol += n_colblocks(cfgs[k]);
+    nrow += n_rowblocks(cfgs[k], big);
+    ncola += n_colablocks(cfgs[k]);
+    ncolb += n_colbblocks(cfgs[k]);
   }
-  b += align_up(ntile * sizeof(Work)) + align_up(nrow * sizeof(Work)) + align_up(ncol * sizeof(Work));
+  b += align_up(ntile * sizeof(Work)) + align_up(nrow * sizeof(Work)) +
+       align_up(ncola * sizeof(Work)) + align_up(ncolb * sizeof(Work));
   b += align_up(8 * sizeof(double) * 1024);  // diagnostics partials
   return b;
 }
@@ -261,8 +293,8 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
 // One kernel launch of a step: its class, arguments and algorithmic bytes (every
 // plane it must read and write, counted once).
 enum LaunchClass {
-  kRelaxV = 0, kHelmRhs = 1, kRowsFwd = 2, kColumns = 3, kRowsInv = 4, kUpdateUQ = 5,
-  kStageTerms = 6, kNumClasses = 7
+  kRelaxV = 0, kHelmRhs = 1, kRowsFwd = 2, kColsA = 3, kColsB = 4, kColsAInv = 5,
+  kRowsInv = 6, kUpdateUQ = 7, kStageTerms = 8, kNumClasses = 9
 };
 
 struct Launch {
@@ -293,8 +325,9 @@ struct apdvm_ctx {
   std::vector<apdvm_config> cfg;
   std::vector<Inst> inst;
   Inst *d_inst = nullptr;
-  Work *d_tiles = nullptr, *d_rows = nullptr, *d_cols = nullptr;
-  int ntiles = 0, nrows = 0, ncols = 0;
+  Work *d_tiles = nullptr, *d_rows = nullptr, *d_cola = nullptr, *d_colb = nullptr;
+  int ntiles = 0, nrows = 0, ncola = 0, ncolb = 0;
+  bool big_rows = false;
   std::vector<Work> tiles;  // host copy (diagnostics use per-instance ranges)
   std::vector<int> tile_first, tile_count;
   double *d_partials = nullptr;
@@ -304,6 +337,7 @@ struct apdvm_ctx {
   std::vector<double> umax;
   int64_t step = 0;
   double cells = 0.0;                 // sum of nx * ny over instances
+  double spec_bytes = 0.0;            // sum of ny (nx/2 + 1) * 16 over instances
   std::vector<apdvm::Launch> plan[2]; // launch list of one step from each state set
   bool use_graph = false;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -402,14 +436,15 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ar.out_r = L.R; ar.out_ddb = L.ddb;
     l.bytes = (2 + 1 + ar.nD + ar.nL + 1) * pt + 2 * pd;
     plan.push_back(l);
-    // step 2 solve: three kernels
+    // step 2 solve: five kernels, each one read and one write of a float64 plane
+    // (the spectrum holds nx/2 + 1 complex columns)
     ArgsSolve as{};
     as.stage = i; as.r = L.R; as.spec = L.spec; as.out = th;
     for (int k = kRowsFwd; k <= kRowsInv; ++k) {
       l = Launch{};
       l.cls = k;
       l.sv = as;
-      l.bytes = 2 * pd;
+      l.bytes = (k == kRowsFwd || k == kRowsInv) ? pd + c->spec_bytes : 2 * c->spec_bytes;
       plan.push_back(l);
     }
     // steps 3 and 4
@@ -461,10 +496,12 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
     case kRelaxV: return launch_relax_v<T>(c->d_inst, c->d_tiles, c->ntiles, l.v, st);
     case kHelmRhs: return launch_helmholtz_rhs<T>(c->d_inst, c->d_tiles, c->ntiles, l.r, st);
     case kRowsFwd:
-    case kColumns:
+    case kColsA:
+    case kColsB:
+    case kColsAInv:
     case kRowsInv:
-      return launch_solve_part(l.cls - kRowsFwd, c->d_inst, c->d_rows, c->nrows, c->d_cols,
-                               c->ncols, l.sv, st);
+      return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
+                               c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
     case kUpdateUQ: return launch_update_uq<T>(c->d_inst, c->d_tiles, c->ntiles, l.uq, st);
     default: return launch_stage_terms<T>(c->d_inst, c->d_tiles, c->ntiles, l.e, st);
   }
@@ -752,11 +789,12 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   // carve the workspace
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
   const int ty = c->split ? tile_rows<float>() : tile_rows<double>();
+  c->big_rows = big_rows(n, cfgs);
   char *p = c->ws;
   c->d_inst = reinterpret_cast<Inst *>(p);
   p += align_up(n * sizeof(Inst));
   c->inst.resize(n);
-  std::vector<Work> rows, cols;
+  std::vector<Work> rows, cola, colb;
   std::vector<char> host_tables;
   struct Upload { char *dst; std::vector<char> data; };
   std::vector<Upload> uploads;
@@ -777,13 +815,18 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.tbase = p;
     p += align_up(c->L.ntrans * plane * tsize);
     I.dbase = reinterpret_cast<double *>(p);
-    p += align_up(c->L.ndbl * plane * sizeof(double));
-    // twiddles
+    p += align_up((c->L.ndbl * plane + 2 * (size_t)cf.ny) * sizeof(double));
+    // twiddles for lengths nx, ny and the column factors n1, n2
+    const int n2 = col_n2(cf.ny), n1 = cf.ny / n2;
+    const int ntw = cf.nx + cf.ny + n1 + n2;
     double2 *tw = reinterpret_cast<double2 *>(p);
-    p += align_up((size_t)(cf.nx + cf.ny) * sizeof(double2));
-    Upload u1{reinterpret_cast<char *>(tw), std::vector<char>((cf.nx + cf.ny) * sizeof(double2))};
-    twiddles(cf.nx, reinterpret_cast<double2 *>(u1.data.data()));
-    twiddles(cf.ny, reinterpret_cast<double2 *>(u1.data.data()) + cf.nx);
+    p += align_up((size_t)ntw * sizeof(double2));
+    Upload u1{reinterpret_cast<char *>(tw), std::vector<char>(ntw * sizeof(double2))};
+    double2 *htw = reinterpret_cast<double2 *>(u1.data.data());
+    twiddles(cf.nx, htw);
+    twiddles(cf.ny, htw + cf.nx);
+    twiddles(n1, htw + cf.nx + cf.ny);
+    twiddles(n2, htw + cf.nx + cf.ny + n1);
     uploads.push_back(std::move(u1));
     I.fx.n = cf.nx;
     I.fx.npass = fft_radices(cf.nx, I.fx.radix);
@@ -791,6 +834,12 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.fy.n = cf.ny;
     I.fy.npass = fft_radices(cf.ny, I.fy.radix);
     I.fy.tw = tw + cf.nx;
+    I.f1.n = n1;
+    I.f1.npass = fft_radices(n1, I.f1.radix);
+    I.f1.tw = tw + cf.nx + cf.ny;
+    I.f2.n = n2;
+    I.f2.npass = fft_radices(n2, I.f2.radix);
+    I.f2.tw = tw + cf.nx + cf.ny + n1;
     // symbols
     double *lam = reinterpret_cast<double *>(p);
     p += align_up((size_t)(cf.nx / 2 + 1 + cf.ny) * sizeof(double));
@@ -802,15 +851,20 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     uploads.push_back(std::move(u2));
     I.lam_x = lam;
     I.lam_y = lam + cf.nx / 2 + 1;
-    I.row_pairs_per_block = rpb(cf);
+    I.row_pairs_per_block = rpb(cf, c->big_rows);
     I.cols_per_block = cpb(cf);
+    I.groups_per_block = gpb(cf);
     // work tables
     c->tile_first.push_back((int)c->tiles.size());
     for (int y0 = 0; y0 < cf.ny; y0 += ty)
       for (int x0 = 0; x0 < cf.nx; x0 += kTileX) c->tiles.push_back(Work{k, x0, y0, 0});
     c->tile_count.push_back((int)c->tiles.size() - c->tile_first.back());
     for (int r0 = 0; r0 < cf.ny / 2; r0 += I.row_pairs_per_block) rows.push_back(Work{k, r0, 0, 0});
-    for (int k0 = 0; k0 < cf.nx / 2; k0 += I.cols_per_block) cols.push_back(Work{k, k0, 0, 0});
+    for (int k0 = 0; k0 < cf.nx / 2 + 1; k0 += I.cols_per_block) {
+      for (int r = 0; r < n2; ++r) cola.push_back(Work{k, k0, r, 0});
+      for (int g0 = 0; g0 < n1; g0 += I.groups_per_block) colb.push_back(Work{k, k0, g0, 0});
+    }
+    c->spec_bytes += (double)cf.ny * (cf.nx / 2 + 1) * 16.0;
     c->cfg[k] = cf;
     c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
     c->cfg[k].cx = c->cfg[k].cy = nullptr;
@@ -821,13 +875,16 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->plan[1] = build_plan(c, 1);
   c->ntiles = (int)c->tiles.size();
   c->nrows = (int)rows.size();
-  c->ncols = (int)cols.size();
+  c->ncola = (int)cola.size();
+  c->ncolb = (int)colb.size();
   c->d_tiles = reinterpret_cast<Work *>(p);
   p += align_up(c->tiles.size() * sizeof(Work));
   c->d_rows = reinterpret_cast<Work *>(p);
   p += align_up(rows.size() * sizeof(Work));
-  c->d_cols = reinterpret_cast<Work *>(p);
-  p += align_up(cols.size() * sizeof(Work));
+  c->d_cola = reinterpret_cast<Work *>(p);
+  p += align_up(cola.size() * sizeof(Work));
+  c->d_colb = reinterpret_cast<Work *>(p);
+  p += align_up(colb.size() * sizeof(Work));
   c->d_partials = reinterpret_cast<double *>(p);
   p += align_up(8 * sizeof(double) * 1024);
 
@@ -835,7 +892,9 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
             hipMemcpyAsync(c->d_rows, rows.data(), rows.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->d_cols, cols.data(), cols.size() * sizeof(Work),
+            hipMemcpyAsync(c->d_cola, cola.data(), cola.size() * sizeof(Work),
+                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(c->d_colb, colb.data(), colb.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
             hipMemcpyAsync(c->d_inst, c->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice,
                            c->stream) == hipSuccess;

@@ -164,5 +164,5 @@ def test_timing_hooks_and_traffic():
         per[cls] = ms
     sim.timing_enable(-1)
     b_all, n_all = sim.traffic(-1)
-    assert abs(b_all - total) < 1e-6 * b_all and n_all == sim.launches_per_step() == 28
+    assert abs(b_all - total) < 1e-6 * b_all and n_all == sim.launches_per_step() == 9 * 4
     sim.close()
