@@ -42,6 +42,24 @@ def workload(name):
                "tableau": "ARS(4,4,3)", "space": "WENO5 + 4th-order central",
                "cfl": wl.CFL_ARS, "steps_stated": 2000}
         return cases, "ars443", cfg
+    if name == "random2048":
+        cases = [wl.random_2048()]
+        cfg = {"workload": "random_divfree_2048x2048_k8_rms0.1_eps1e-6_ma0.01_ars443",
+               "grid": [2048, 2048], "instances": 1, "eps": 1e-6, "mach": 0.01,
+               "tableau": "ARS(4,4,3)", "cfl": wl.CFL_ARS, "steps_stated": 1000}
+        return cases, "ars443", cfg
+    if name == "batched256":
+        cases = wl.batched_256()
+        cfg = {"workload": "batched_256_random_divfree_k4_sides64-512_eps1e-6-1_ma0.01-0.1_ars443",
+               "instances": len(cases), "cells": int(sum(c.nx * c.ny for c in cases)),
+               "tableau": "ARS(4,4,3)", "cfl": wl.CFL_ARS, "steps_stated": 500}
+        return cases, "ars443", cfg
+    if name == "shear8192":
+        cases = [wl.shear_layer_8192()]
+        cfg = {"workload": "shear_layer_8192x8192_eps1e-4_ma0.02_ars443", "grid": [8192, 8192],
+               "instances": 1, "eps": 1e-4, "mach": 0.02, "tableau": "ARS(4,4,3)",
+               "cfl": wl.CFL_ARS, "steps_stated": 200}
+        return cases, "ars443", cfg
     if name == "taylor_green64":
         cases = [wl.taylor_green_64("paper2")]
         cfg = {"workload": "taylor_green_64x64_eps1_ma0.1_paper2", "grid": [64, 64],
@@ -72,6 +90,38 @@ def cpu_baseline(cases, tab, budget_s=20.0):
             "sample": f"{k} instance-steps of the same workload ({el:.1f} s)"}
 
 
+def compare_fp64(apdvm, torch, stream, sim, cases, tab, args, sec):
+    """Same workload and steps in float64: speed ratio and relative L2 differences of the
+    final states (velocity, theta, density rho = 1 + 2 eps^2 theta), worst instance."""
+    ref = apdvm.Simulation([dict(nx=c.nx, ny=c.ny, eps=c.eps, tau=c.tau, dt=c.dt, lx=c.lx,
+                                 ly=c.ly) for c in cases], tableau=tab, precision=apdvm.FP64,
+                           stream=stream)
+    for k, c in enumerate(cases):
+        ref.set_fields(k, *c.state)
+    ref.set_graph(args.graph)
+    ref.autotune(3)
+    ref.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref.step(args.steps)
+    torch.cuda.synchronize()
+    sec64 = time.perf_counter() - t0
+    # the split run took warmup + 36 probe + steps steps; bring the reference level
+    ref.step(len(apdvm.KERNEL_CLASSES) * 4)
+    worst = {"u": 0.0, "theta": 0.0, "rho": 0.0}
+    for k, c in enumerate(cases):
+        a, b = sim.get_fields(k), ref.get_fields(k)
+        l2 = lambda x, y: float(np.sqrt(np.sum((x - y) ** 2)) / np.sqrt(np.sum(y ** 2)))
+        e = {"u": l2(np.stack(a[:2]), np.stack(b[:2])), "theta": l2(a[2], b[2]),
+             "rho": l2(1 + 2 * c.eps ** 2 * a[2], 1 + 2 * c.eps ** 2 * b[2])}
+        for key in worst:
+            worst[key] = max(worst[key], e[key])
+    ref.close()
+    return {"fp64_ms_per_step": sec64 / args.steps * 1e3, "speedup": sec64 / sec,
+            "rel_l2": worst, "steps_compared": args.warmup + args.steps +
+            len(apdvm.KERNEL_CLASSES) * 4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +130,10 @@ def main():
     ap.add_argument("--workload", default="shear512")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also time the float64 path on the same workload and steps and report "
+                         "the speed ratio and the relative L2 differences of the final states")
+    ap.add_argument("--graph", action="store_true", help="replay each step as a HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (torch copy kernel) so that "
                          "hardware byte counters can be scaled against a known size")
@@ -111,7 +165,9 @@ def main():
                            tableau=tab, precision=prec, stream=stream)
     for k, c in enumerate(cases):
         sim.set_fields(k, *c.state)
+    sim.set_graph(args.graph)
     cells = sum(c.nx * c.ny for c in cases)
+    tiles = sim.autotune(3)
 
     # warm-up, then find the kernel class with the largest share of a step
     sim.step(args.warmup)
@@ -161,7 +217,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == apdvm.FP64 else "f32+f64",
         "data": "synthetic",
-        "config": dict(cfg, precision=args.precision),
+        "config": dict(cfg, precision=args.precision,
+                       tile_rows={k: tiles[k] for k in ("helmholtz_rhs", "update_uq",
+                                                        "stage_terms_relax_v")}),
         "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -169,6 +227,8 @@ def main():
                      "launches_timed": n_dom},
         "finite": finite,
     }
+    if args.compare_fp64 and prec != apdvm.FP64:
+        out["vs_fp64"] = compare_fp64(apdvm, torch, stream, sim, cases, tab, args, sec)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cases, tab)
     sim.close()

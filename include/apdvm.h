@@ -166,12 +166,13 @@ apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
  * needs a created (non-NULL) stream at apdvm_create, else APDVM_ERR_ARG. */
 apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
 
-/* Kernel classes of a step, used by the profiling calls below:
- * 0 step-1 relaxation of v, 1 step-2 right-hand side, 2 Helmholtz rows forward FFT,
- * 3 Helmholtz column FFT first factor, 4 Helmholtz column FFT second factor with the
- * symbol divide and its inverse, 5 inverse column FFT first factor, 6 Helmholtz rows
- * inverse FFT, 7 steps 3 and 4 (u and q updates), 8 stage terms reused by later
- * stages. */
+/* Kernel classes of a step, used by the profiling and tuning calls below:
+ * 0 step-2 right-hand side, 1 Helmholtz rows forward FFT, 2 Helmholtz column FFT first
+ * factor, 3 Helmholtz column FFT second factor with the symbol divide and its inverse,
+ * 4 inverse column FFT first factor, 5 Helmholtz rows inverse FFT, 6 steps 3 and 4
+ * (u and q updates), 7 stage terms reused by later stages together with step 1 (the
+ * relaxation of v) of the next stage, 8 single-pass Helmholtz columns (FFT, symbol
+ * divide, inverse FFT; replaces 2-4 when the autotuner picks it). */
 #define APDVM_NUM_KERNEL_CLASSES 9
 
 /* From now on bracket every launch of kernel class cls with a pair of HIP events on
@@ -188,6 +189,24 @@ apdvm_status apdvm_timing_read(apdvm_ctx *ctx, int64_t *launches, double *total_
  * instances; and the number of such launches per step.  Host-only. */
 apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
                            int32_t *launches_per_step);
+
+/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each candidate
+ * tile height (8 or 16 rows of 64 cells), and for the Helmholtz columns the four-step
+ * form (classes 2-4) against the single pass (class 8, only when every ny <= 2048), are
+ * timed with HIP events over steps_per_trial steps of the live simulation; the fastest
+ * is kept.  The state, the step counter
+ * and the launch mode are restored afterwards (this call allocates a temporary device
+ * copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a
+ * previous choice for the same context shape is read from it and no trial runs; new
+ * choices are appended to it.  choice (may be NULL, else APDVM_NUM_KERNEL_CLASSES
+ * entries) receives the tile height of the stencil classes and 1 / 0 for the FFT column
+ * classes in use / not in use.  Needs fields on every instance. */
+apdvm_status apdvm_autotune(apdvm_ctx *ctx, int32_t steps_per_trial, int32_t *choice);
+
+/* Set the launch shapes directly, in the format apdvm_autotune reports: tile height 8
+ * or 16 for classes 0, 6 and 7, and choice[8] != 0 for the single-pass Helmholtz
+ * columns (needs every ny <= 2048); other entries are ignored.  Host-only. */
+apdvm_status apdvm_set_tuning(apdvm_ctx *ctx, const int32_t *choice);
 
 /* Release the context (and the workspace if the library allocated it).  NULL ok. */
 void apdvm_destroy(apdvm_ctx *ctx);

@@ -25,9 +25,9 @@ LIB_PATH = os.path.join(_HERE, "libapdvm.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "apdvm.h")
 
 FP64, FP32_SPLIT = 0, 1
-KERNEL_CLASSES = ("relax_v", "helmholtz_rhs", "fft_rows_forward", "fft_columns_a",
-                  "fft_columns_b", "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
-                  "stage_terms")
+KERNEL_CLASSES = ("helmholtz_rhs", "fft_rows_forward", "fft_columns_a", "fft_columns_b",
+                  "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
+                  "stage_terms_relax_v", "fft_columns_single_pass")
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_VELSET", 3: "ERR_TABLEAU", 4: "ERR_NOMEM",
           5: "ERR_HIP", 6: "ERR_NONFINITE", 7: "ERR_STATE"}
 
@@ -94,6 +94,8 @@ def _declare(L):
     L.apdvm_timing_enable.argtypes = [P, c_int32]
     L.apdvm_timing_read.argtypes = [P, POINTER(c_int64), POINTER(c_double)]
     L.apdvm_traffic.argtypes = [P, c_int32, POINTER(c_double), POINTER(c_int32)]
+    L.apdvm_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
+    L.apdvm_set_tuning.argtypes = [P, POINTER(c_int32)]
     L.apdvm_destroy.argtypes = [P]
     L.apdvm_destroy.restype = None
     for name in ("apdvm_workspace_bytes", "apdvm_create", "apdvm_set_fields",
@@ -101,7 +103,8 @@ def _declare(L):
                  "apdvm_get_fields", "apdvm_get_fields_device", "apdvm_get_moments",
                  "apdvm_get_populations", "apdvm_get_info", "apdvm_set_step",
                  "apdvm_diagnostics", "apdvm_launches_per_step", "apdvm_set_graph",
-                 "apdvm_timing_enable", "apdvm_timing_read", "apdvm_traffic"):
+                 "apdvm_timing_enable", "apdvm_timing_read", "apdvm_traffic",
+                 "apdvm_autotune", "apdvm_set_tuning"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -292,6 +295,28 @@ class Simulation:
         _check(lib().apdvm_traffic(self.ctx, int(cls), ctypes.byref(b), ctypes.byref(n)),
                "traffic")
         return b.value, n.value
+
+    def autotune(self, steps_per_trial=3):
+        """Pick the tile height of each stencil kernel class by timing; returns a dict
+        class name -> tile rows."""
+        arr = (c_int32 * len(KERNEL_CLASSES))()
+        _check(lib().apdvm_autotune(self.ctx, int(steps_per_trial), arr), "autotune")
+        return dict(zip(KERNEL_CLASSES, list(arr)))
+
+    def set_tuning(self, tile_rows=16, single_pass_columns=False):
+        """Force the launch shapes: tile_rows is one tile height for every stencil class
+        or a dict in the format autotune() returns (then single_pass_columns is read from
+        it); single_pass_columns selects the form of the Helmholtz column FFT."""
+        arr = (c_int32 * len(KERNEL_CLASSES))()
+        if isinstance(tile_rows, dict):
+            for k, name in enumerate(KERNEL_CLASSES):
+                arr[k] = int(tile_rows[name])
+            single_pass_columns = bool(tile_rows["fft_columns_single_pass"])
+        else:
+            for k in range(len(KERNEL_CLASSES)):
+                arr[k] = int(tile_rows)
+        arr[KERNEL_CLASSES.index("fft_columns_single_pass")] = 1 if single_pass_columns else 0
+        _check(lib().apdvm_set_tuning(self.ctx, arr), "set_tuning")
 
     def launches_per_step(self):
         n = c_int32()

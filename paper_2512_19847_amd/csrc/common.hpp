@@ -63,6 +63,7 @@ struct Inst {
   int row_pairs_per_block;   // FFT row kernels: row pairs per workgroup
   int cols_per_block;        // FFT column kernels: complex columns per tile
   int groups_per_block;      // FFT column kernel B: k1 groups per tile
+  int cols_full_per_block;   // single-pass column kernel: columns per tile (0: unused)
 };
 
 // Work table entry: instance and the first cell / row pair / column of the block.
@@ -76,6 +77,7 @@ struct Work {
 // ---------------------------------------------------------------- kernel arguments
 
 // Step 1 of a stage: v(i) = [te2 v^n - dt sum_j cE_j E(j) - dt sum_j cV_j v(j)] kinv.
+// stage = 0 marks "no step 1 here".
 struct ArgsV {
   int stage;
   int vn[2];
@@ -126,12 +128,16 @@ struct ArgsUQ {
 
 // Terms of a known stage that later stages reuse:
 // E = (tau/4) D0_W.B(u) + te2 D_W q[dissipation on v] - F(u), D0.u,
-// Ltheta = D0^2:B(v) + D_Delta theta.
+// Ltheta = D0^2:B(v) + D_Delta theta.  The same launch performs step 1 of the next
+// stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients of this
+// stage's E and v in that step (at_{k,j} and a_{k,j}), which stay in registers.
 struct ArgsE {
   int u[2], q, v[2];  // halo 3
   int th;             // float64 slot, halo 2 (only when out_lt != kNoSlot)
   int ddb;            // D0^2:B(v) of this stage (only when out_lt != kNoSlot)
-  int out_e[2], out_du, out_lt;
+  int out_e[2];       // kNoSlot when only the fused next step reads E
+  int out_du, out_lt;
+  double c_e_next, c_v_next;
 };
 
 // Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec

@@ -28,8 +28,6 @@
 
 namespace apdvm {
 
-namespace {
-
 __device__ __forceinline__ int xcd_item_fft(int nwork) {
   const int b = blockIdx.x;
   const int x = b & 7, i = b >> 3;
@@ -281,6 +279,45 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
   }
 }
 
+// Single pass over whole columns (ny <= kColCap / C): forward FFT along y, symbol divide
+// with the (0,0) rule, inverse FFT, for the C columns k0.. of the tile; work item
+// (inst, k0).  One launch instead of the three of the four-step form, for grids whose
+// columns fit a tile.
+__global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restrict__ insts,
+                                                           const Work *__restrict__ work,
+                                                           int nwork, ArgsSolve a) {
+  __shared__ double2 buf[kColCap];
+  const Work wk = work[xcd_item_fft(nwork)];
+  const Inst &I = insts[wk.inst];
+  const int K = I.nx / 2 + 1, n = I.ny;
+  const int k0 = wk.a;
+  const int C = min(I.cols_full_per_block, K - k0);
+  double2 *S = reinterpret_cast<double2 *>(dslot(I, a.spec));
+  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
+    const int y = idx / C, c = idx - y * C;
+    buf[idx] = S[(long long)y * K + k0 + c];
+  }
+  __syncthreads();
+  fft_lds<-1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1);
+  const double sig = I.sigma[a.stage], s = I.inv_nxny;
+  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
+    const int ky = idx / C, c = idx - ky * C;
+    const int kx = k0 + c;
+    if (kx == 0 && ky == 0) {
+      buf[idx] = make_double2(I.theta_mean, 0.0);
+    } else {
+      const double d = s / (I.lam_x[kx] + I.lam_y[ky] - sig);
+      buf[idx] = make_double2(buf[idx].x * d, buf[idx].y * d);
+    }
+  }
+  __syncthreads();
+  fft_lds<1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1);
+  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
+    const int y = idx / C, c = idx - y * C;
+    S[(long long)y * K + k0 + c] = buf[idx];
+  }
+}
+
 // ------------------------------------------------------------------ rows inverse
 
 template <int CAP, int NT>
@@ -320,14 +357,17 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   }
 }
 
-}  // namespace
-
 // part 0: rows forward, 1: columns A, 2: columns B, 3: columns A inverse, 4: rows
-// inverse.  big selects the row kernels for nx > kRowSmallCap.
+// inverse, 5: single-pass columns (cola then holds its strips).  big selects the row
+// kernels for nx > kRowSmallCap.
 hipError_t launch_solve_part(int part, bool big, const Inst *insts, const Work *rows, int nrows,
                              const Work *cola, int ncola, const Work *colb, int ncolb,
                              const ArgsSolve &a, hipStream_t st) {
   switch (part) {
+    case 5:
+      hipLaunchKernelGGL(k_cols_full, dim3(ncola), dim3(kColThreads), 0, st, insts, cola, ncola,
+                         a);
+      break;
     case 0:
       if (big)
         hipLaunchKernelGGL((k_rows_forward<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),

@@ -5,22 +5,26 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 namespace apdvm {
 
 template <typename T>
-int tile_rows();
+hipError_t launch_helmholtz_rhs(int, const Inst *, const Work *, int, const ArgsR &, hipStream_t);
 template <typename T>
-hipError_t launch_relax_v(const Inst *, const Work *, int, const ArgsV &, hipStream_t);
+hipError_t launch_update_uq(int, const Inst *, const Work *, int, const ArgsUQ &, hipStream_t);
 template <typename T>
-hipError_t launch_helmholtz_rhs(const Inst *, const Work *, int, const ArgsR &, hipStream_t);
-template <typename T>
-hipError_t launch_update_uq(const Inst *, const Work *, int, const ArgsUQ &, hipStream_t);
-template <typename T>
-hipError_t launch_stage_terms(const Inst *, const Work *, int, const ArgsE &, hipStream_t);
+hipError_t launch_stage_terms(int, const Inst *, const Work *, int, const ArgsE &, const ArgsV &,
+                              hipStream_t);
+
+// Tile heights the stencil kernels are built for; the autotuner picks one per class.
+constexpr int kTileRows[2] = {8, 16};
 hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
                              int, const Work *, int, const ArgsSolve &, hipStream_t);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
@@ -252,6 +256,19 @@ int gpb(const apdvm_config &c) {
 int n_rowblocks(const apdvm_config &c, bool big) { return (c.ny / 2 + rpb(c, big) - 1) / rpb(c, big); }
 int n_strips(const apdvm_config &c) { return (c.nx / 2 + 1 + cpb(c) - 1) / cpb(c); }
 int n_colablocks(const apdvm_config &c) { return n_strips(c) * col_n2(c.ny); }
+// single-pass column kernel: whole columns of length ny in a tile of at most 2048
+// complex values
+int cfpb(const apdvm_config &c) {
+  if (c.ny > 2048) return 0;
+  int w = kColWidth;
+  if (w > c.nx / 2 + 1) w = c.nx / 2 + 1;
+  while (w > 1 && c.ny * w > 2048) --w;
+  return w;
+}
+int n_colfblocks(const apdvm_config &c) {
+  const int w = cfpb(c);
+  return w ? (c.nx / 2 + 1 + w - 1) / w : 0;
+}
 int n_colbblocks(const apdvm_config &c) {
   const int n1 = c.ny / col_n2(c.ny);
   return n_strips(c) * ((n1 + gpb(c) - 1) / gpb(c));
@@ -271,19 +288,21 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
   const Layout L = make_layout(cfgs[0].s);
   const bool split = cfgs[0].precision == APDVM_FP32_SPLIT;
   const size_t tsize = split ? sizeof(float) : sizeof(double);
-  const int ty = split ? tile_rows<float>() : tile_rows<double>();
   size_t b = align_up(n * sizeof(Inst));
   const bool big = big_rows(n, cfgs);
-  size_t ntile = 0, nrow = 0, ncola = 0, ncolb = 0;
+  size_t ntile8 = 0, ntile16 = 0, nrow = 0, ncola = 0, ncolb = 0, ncolf = 0;
   for (int k = 0; k < n; ++k) {
     b += inst_bytes(cfgs[k], L, tsize);
-    ntile += n_tiles(cfgs[k], ty);
+    ntile8 += n_tiles(cfgs[k], kTileRows[0]);
+    ntile16 += n_tiles(cfgs[k], kTileRows[1]);
     nrow += n_rowblocks(cfgs[k], big);
     ncola += n_colablocks(cfgs[k]);
     ncolb += n_colbblocks(cfgs[k]);
+    ncolf += n_colfblocks(cfgs[k]);
   }
-  b += align_up(ntile * sizeof(Work)) + align_up(nrow * sizeof(Work)) +
-       align_up(ncola * sizeof(Work)) + align_up(ncolb * sizeof(Work));
+  b += align_up(ntile8 * sizeof(Work)) + align_up(ntile16 * sizeof(Work)) + align_up(nrow * sizeof(Work)) +
+       align_up(ncola * sizeof(Work)) + align_up(ncolb * sizeof(Work)) +
+       align_up((ncolf + 1) * sizeof(Work));
   b += align_up(8 * sizeof(double) * 1024);  // diagnostics partials
   return b;
 }
@@ -293,13 +312,13 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
 // One kernel launch of a step: its class, arguments and algorithmic bytes (every
 // plane it must read and write, counted once).
 enum LaunchClass {
-  kRelaxV = 0, kHelmRhs = 1, kRowsFwd = 2, kColsA = 3, kColsB = 4, kColsAInv = 5,
-  kRowsInv = 6, kUpdateUQ = 7, kStageTerms = 8, kNumClasses = 9
+  kHelmRhs = 0, kRowsFwd = 1, kColsA = 2, kColsB = 3, kColsAInv = 4, kRowsInv = 5,
+  kUpdateUQ = 6, kStageTerms = 7, kColsFull = 8, kNumClasses = 9
 };
 
 struct Launch {
   int cls;
-  ArgsV v;
+  ArgsV v;  // step 1 of the next stage, fused into a stage-terms launch
   ArgsR r;
   ArgsUQ uq;
   ArgsE e;
@@ -325,10 +344,15 @@ struct apdvm_ctx {
   std::vector<apdvm_config> cfg;
   std::vector<Inst> inst;
   Inst *d_inst = nullptr;
-  Work *d_tiles = nullptr, *d_rows = nullptr, *d_cola = nullptr, *d_colb = nullptr;
-  int ntiles = 0, nrows = 0, ncola = 0, ncolb = 0;
+  Work *d_tiles[2] = {nullptr, nullptr};  // tile tables for kTileRows[0] and kTileRows[1]
+  int ntiles[2] = {0, 0};
+  Work *d_rows = nullptr, *d_cola = nullptr, *d_colb = nullptr, *d_colf = nullptr;
+  int nrows = 0, ncola = 0, ncolb = 0, ncolf = 0;
+  int col_mode = 0;        // 0: four-step column FFT (3 launches), 1: single pass
+  bool col_full_ok = false;  // every instance has columns short enough for one pass
   bool big_rows = false;
-  std::vector<Work> tiles;  // host copy (diagnostics use per-instance ranges)
+  int ty_index[apdvm::kNumClasses];  // tile table used by each stencil class
+  std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
   std::vector<int> tile_first, tile_count;
   double *d_partials = nullptr;
   int parity = 0;           // state set holding the current state
@@ -387,16 +411,68 @@ apdvm_status upload_inst(apdvm_ctx *c, int k) {
                                    c->stream));
 }
 
-// Launch list of one step starting from state set P (stage-0 terms excluded).
+// Step 1 of stage k, fused into the stage-terms launch of stage k - 1 (whose E and v
+// stay in registers).  Pk is the state set of the step containing stage k.
+void fill_relax(const apdvm_ctx *c, int k, int Pk, ArgsV &nv, ArgsE &e, double pt,
+                double &bytes) {
+  const Layout &L = c->L;
+  const int s = c->s;
+  nv = ArgsV{};
+  nv.stage = k;
+  nv.vn[0] = L.st[Pk][2];
+  nv.vn[1] = L.st[Pk][3];
+  for (int j = 0; j + 1 < k; ++j) {
+    if (c->At[k][j] != 0.0) {
+      nv.E[nv.nE][0] = L.E[j][0]; nv.E[nv.nE][1] = L.E[j][1]; nv.cE[nv.nE++] = c->At[k][j];
+    }
+    if (j >= 1 && c->A[k][j] != 0.0) {
+      nv.V[nv.nV][0] = L.V[j][0]; nv.V[nv.nV][1] = L.V[j][1]; nv.cV[nv.nV++] = c->A[k][j];
+    }
+  }
+  e.c_e_next = c->At[k][k - 1];
+  e.c_v_next = k - 1 >= 1 ? c->A[k][k - 1] : 0.0;
+  const bool last = k == s - 1;
+  nv.out[0] = last ? L.st[1 - Pk][2] : L.V[k][0];
+  nv.out[1] = last ? L.st[1 - Pk][3] : L.V[k][1];
+  bytes += (2 + 2 * nv.nE + 2 * nv.nV + 2) * pt;  // v^n, history, v(k)
+}
+
+// Stage terms of stage j that a stage other than j + 1 reads (j + 1 gets them in
+// registers through the fused step 1).
+bool e_stored(const apdvm_ctx *c, int j) {
+  for (int k = j + 2; k < c->s; ++k)
+    if (c->At[k][j] != 0.0) return true;
+  return false;
+}
+bool implicit_stored(const apdvm_ctx *c, int j) {
+  for (int k = j + 1; k < c->s; ++k)
+    if (c->A[k][j] != 0.0) return true;
+  return false;
+}
+
+// Stage-terms launch for the state set P itself (stage 0), used after new fields.
+Launch stage0_launch(const apdvm_ctx *c, int P) {
+  const Layout &L = c->L;
+  const double pt = c->cells * (c->split ? 4.0 : 8.0);
+  Launch l{};
+  l.cls = kStageTerms;
+  ArgsE &a = l.e;
+  a.u[0] = L.st[P][0]; a.u[1] = L.st[P][1]; a.v[0] = L.st[P][2]; a.v[1] = L.st[P][3];
+  a.q = L.st[P][4]; a.th = L.th[P]; a.ddb = kNoSlot;
+  a.out_e[0] = e_stored(c, 0) ? L.E[0][0] : kNoSlot;
+  a.out_e[1] = e_stored(c, 0) ? L.E[0][1] : kNoSlot;
+  a.out_du = L.Du[0];
+  a.out_lt = kNoSlot;
+  l.bytes = (5 + 1 + (e_stored(c, 0) ? 2 : 0)) * pt;
+  fill_relax(c, 1, P, l.v, a, pt, l.bytes);
+  return l;
+}
+
+// Launch list of one step starting from state set P.
 std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const int s = c->s, Q = 1 - P;
   const double pt = c->cells * (c->split ? 4.0 : 8.0), pd = c->cells * 8.0;
-  auto later_needs = [&](int j) {
-    for (int k = j + 1; k < s; ++k)
-      if (c->A[k][j] != 0.0) return true;
-    return false;
-  };
   std::vector<Launch> plan;
   for (int i = 1; i < s; ++i) {
     const bool last = i == s - 1;
@@ -405,25 +481,8 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const int qi = last ? L.st[Q][4] : L.Q[i];
     const int th = last ? L.th[Q] : L.Th[i];
     const double aii = c->A[i][i];
+    // step 2 right-hand side (v(i) comes from the previous stage-terms launch)
     Launch l{};
-    // step 1
-    l.cls = kRelaxV;
-    ArgsV &av = l.v;
-    av.stage = i;
-    av.vn[0] = L.st[P][2]; av.vn[1] = L.st[P][3];
-    for (int j = 0; j < i; ++j) {
-      if (c->At[i][j] != 0.0) {
-        av.E[av.nE][0] = L.E[j][0]; av.E[av.nE][1] = L.E[j][1]; av.cE[av.nE++] = c->At[i][j];
-      }
-      if (j >= 1 && c->A[i][j] != 0.0) {
-        av.V[av.nV][0] = L.V[j][0]; av.V[av.nV][1] = L.V[j][1]; av.cV[av.nV++] = c->A[i][j];
-      }
-    }
-    av.out[0] = v1; av.out[1] = v2;
-    l.bytes = (4 + 2 * av.nE + 2 * av.nV) * pt;
-    plan.push_back(l);
-    // step 2 right-hand side
-    l = Launch{};
     l.cls = kHelmRhs;
     ArgsR &ar = l.r;
     ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P]; ar.du0 = L.Du[0];
@@ -440,7 +499,12 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     // (the spectrum holds nx/2 + 1 complex columns)
     ArgsSolve as{};
     as.stage = i; as.r = L.R; as.spec = L.spec; as.out = th;
-    for (int k = kRowsFwd; k <= kRowsInv; ++k) {
+    const int four[5] = {kRowsFwd, kColsA, kColsB, kColsAInv, kRowsInv};
+    const int full[3] = {kRowsFwd, kColsFull, kRowsInv};
+    const int *parts = c->col_mode ? full : four;
+    const int nparts = c->col_mode ? 3 : 5;
+    for (int m = 0; m < nparts; ++m) {
+      const int k = parts[m];
       l = Launch{};
       l.cls = k;
       l.sv = as;
@@ -462,7 +526,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
       }
     }
     au.out_u[0] = u1; au.out_u[1] = u2; au.out_q = qi;
-    const bool keep = !last && later_needs(i);
+    const bool keep = !last && implicit_stored(c, i);
     if (keep) {
       au.out_hu[0] = L.Hu[i][0]; au.out_hu[1] = L.Hu[i][1]; au.out_gq = L.Gq[i];
     } else {
@@ -472,18 +536,24 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
     l.bytes = (reads + 3 + (keep ? 3 : 0)) * pt + pd;
     plan.push_back(l);
-    // terms of this stage for later stages; the last stage's are the next step's
-    // stage-0 terms
+    // terms of this stage for later stages, and step 1 of the next stage; the last
+    // stage's terms are the next step's stage-0 terms
     l = Launch{};
     l.cls = kStageTerms;
     ArgsE &ae = l.e;
     ae.u[0] = u1; ae.u[1] = u2; ae.q = qi; ae.v[0] = v1; ae.v[1] = v2; ae.th = th;
     ae.ddb = L.ddb;
-    ae.out_e[0] = last ? L.E[0][0] : L.E[i][0];
-    ae.out_e[1] = last ? L.E[0][1] : L.E[i][1];
-    ae.out_du = last ? L.Du[0] : L.Du[i];
+    const int ej = last ? 0 : i;  // stage index of these terms in the step that reads them
+    const bool est = e_stored(c, ej);
+    ae.out_e[0] = est ? L.E[ej][0] : kNoSlot;
+    ae.out_e[1] = est ? L.E[ej][1] : kNoSlot;
+    ae.out_du = L.Du[ej];
     ae.out_lt = keep ? L.Lt[i] : kNoSlot;
-    l.bytes = (5 + 3 + (keep ? 2 : 0)) * pt + (keep ? pd : 0.0);
+    l.bytes = (5 + 1 + (est ? 2 : 0) + (keep ? 2 : 0)) * pt + (keep ? pd : 0.0);
+    if (last)
+      fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
+    else
+      fill_relax(c, i + 1, P, l.v, ae, pt, l.bytes);
     plan.push_back(l);
   }
   return plan;
@@ -492,9 +562,15 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
 template <typename T>
 hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
   hipStream_t st = c->stream;
+  const int ti = c->ty_index[l.cls];
+  const int ty = kTileRows[ti];
+  Work *tiles = c->d_tiles[ti];
+  const int nt = c->ntiles[ti];
   switch (l.cls) {
-    case kRelaxV: return launch_relax_v<T>(c->d_inst, c->d_tiles, c->ntiles, l.v, st);
-    case kHelmRhs: return launch_helmholtz_rhs<T>(c->d_inst, c->d_tiles, c->ntiles, l.r, st);
+    case kHelmRhs: return launch_helmholtz_rhs<T>(ty, c->d_inst, tiles, nt, l.r, st);
+    case kColsFull:
+      return launch_solve_part(5, c->big_rows, c->d_inst, c->d_rows, c->nrows, c->d_colf,
+                               c->ncolf, c->d_colb, c->ncolb, l.sv, st);
     case kRowsFwd:
     case kColsA:
     case kColsB:
@@ -502,21 +578,14 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
     case kRowsInv:
       return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
                                c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
-    case kUpdateUQ: return launch_update_uq<T>(c->d_inst, c->d_tiles, c->ntiles, l.uq, st);
-    default: return launch_stage_terms<T>(c->d_inst, c->d_tiles, c->ntiles, l.e, st);
+    case kUpdateUQ: return launch_update_uq<T>(ty, c->d_inst, tiles, nt, l.uq, st);
+    default: return launch_stage_terms<T>(ty, c->d_inst, tiles, nt, l.e, l.v, st);
   }
 }
 
 template <typename T>
 apdvm_status stage0_terms(apdvm_ctx *c) {
-  const Layout &L = c->L;
-  const int P = c->parity;
-  ArgsE a{};
-  a.u[0] = L.st[P][0]; a.u[1] = L.st[P][1]; a.v[0] = L.st[P][2]; a.v[1] = L.st[P][3];
-  a.q = L.st[P][4]; a.th = L.th[P]; a.ddb = kNoSlot;
-  a.out_e[0] = L.E[0][0]; a.out_e[1] = L.E[0][1]; a.out_du = L.Du[0]; a.out_lt = kNoSlot;
-  if (launch_stage_terms<T>(c->d_inst, c->d_tiles, c->ntiles, a, c->stream) != hipSuccess)
-    return APDVM_ERR_HIP;
+  if (run_launch<T>(c, stage0_launch(c, c->parity)) != hipSuccess) return APDVM_ERR_HIP;
   c->terms_ready = true;
   return APDVM_OK;
 }
@@ -788,13 +857,15 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
 
   // carve the workspace
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
-  const int ty = c->split ? tile_rows<float>() : tile_rows<double>();
   c->big_rows = big_rows(n, cfgs);
+  for (int k = 0; k < kNumClasses; ++k) c->ty_index[k] = 1;
+  std::vector<Work> tiles8;
   char *p = c->ws;
   c->d_inst = reinterpret_cast<Inst *>(p);
   p += align_up(n * sizeof(Inst));
   c->inst.resize(n);
-  std::vector<Work> rows, cola, colb;
+  std::vector<Work> rows, cola, colb, colf;
+  c->col_full_ok = true;
   std::vector<char> host_tables;
   struct Upload { char *dst; std::vector<char> data; };
   std::vector<Upload> uploads;
@@ -854,16 +925,23 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.row_pairs_per_block = rpb(cf, c->big_rows);
     I.cols_per_block = cpb(cf);
     I.groups_per_block = gpb(cf);
+    I.cols_full_per_block = cfpb(cf);
+    if (!I.cols_full_per_block) c->col_full_ok = false;
     // work tables
     c->tile_first.push_back((int)c->tiles.size());
-    for (int y0 = 0; y0 < cf.ny; y0 += ty)
+    for (int y0 = 0; y0 < cf.ny; y0 += kTileRows[1])
       for (int x0 = 0; x0 < cf.nx; x0 += kTileX) c->tiles.push_back(Work{k, x0, y0, 0});
     c->tile_count.push_back((int)c->tiles.size() - c->tile_first.back());
+    for (int y0 = 0; y0 < cf.ny; y0 += kTileRows[0])
+      for (int x0 = 0; x0 < cf.nx; x0 += kTileX) tiles8.push_back(Work{k, x0, y0, 0});
     for (int r0 = 0; r0 < cf.ny / 2; r0 += I.row_pairs_per_block) rows.push_back(Work{k, r0, 0, 0});
     for (int k0 = 0; k0 < cf.nx / 2 + 1; k0 += I.cols_per_block) {
       for (int r = 0; r < n2; ++r) cola.push_back(Work{k, k0, r, 0});
       for (int g0 = 0; g0 < n1; g0 += I.groups_per_block) colb.push_back(Work{k, k0, g0, 0});
     }
+    if (I.cols_full_per_block)
+      for (int k0 = 0; k0 < cf.nx / 2 + 1; k0 += I.cols_full_per_block)
+        colf.push_back(Work{k, k0, 0, 0});
     c->spec_bytes += (double)cf.ny * (cf.nx / 2 + 1) * 16.0;
     c->cfg[k] = cf;
     c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
@@ -873,22 +951,30 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   for (int k = 0; k < n; ++k) c->cells += (double)cfgs[k].nx * cfgs[k].ny;
   c->plan[0] = build_plan(c, 0);
   c->plan[1] = build_plan(c, 1);
-  c->ntiles = (int)c->tiles.size();
+  c->ntiles[1] = (int)c->tiles.size();
+  c->ntiles[0] = (int)tiles8.size();
   c->nrows = (int)rows.size();
   c->ncola = (int)cola.size();
   c->ncolb = (int)colb.size();
-  c->d_tiles = reinterpret_cast<Work *>(p);
+  c->ncolf = (int)colf.size();
+  c->d_tiles[1] = reinterpret_cast<Work *>(p);
   p += align_up(c->tiles.size() * sizeof(Work));
+  c->d_tiles[0] = reinterpret_cast<Work *>(p);
+  p += align_up(tiles8.size() * sizeof(Work));
   c->d_rows = reinterpret_cast<Work *>(p);
   p += align_up(rows.size() * sizeof(Work));
   c->d_cola = reinterpret_cast<Work *>(p);
   p += align_up(cola.size() * sizeof(Work));
   c->d_colb = reinterpret_cast<Work *>(p);
   p += align_up(colb.size() * sizeof(Work));
+  c->d_colf = reinterpret_cast<Work *>(p);
+  p += align_up((colf.size() + 1) * sizeof(Work));
   c->d_partials = reinterpret_cast<double *>(p);
   p += align_up(8 * sizeof(double) * 1024);
 
-  bool ok = hipMemcpyAsync(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(Work),
+  bool ok = hipMemcpyAsync(c->d_tiles[1], c->tiles.data(), c->tiles.size() * sizeof(Work),
+                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            hipMemcpyAsync(c->d_tiles[0], tiles8.data(), tiles8.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
             hipMemcpyAsync(c->d_rows, rows.data(), rows.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -896,6 +982,9 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
             hipMemcpyAsync(c->d_colb, colb.data(), colb.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+            (colf.empty() ||
+             hipMemcpyAsync(c->d_colf, colf.data(), colf.size() * sizeof(Work),
+                            hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
             hipMemcpyAsync(c->d_inst, c->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice,
                            c->stream) == hipSuccess;
   for (auto &u : uploads)
@@ -1085,8 +1174,8 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
   const int nblk = c->tile_count[k];
   const int cap = 1024;
   const int used = nblk < cap ? nblk : cap;
-  const int ty = c->split ? tile_rows<float>() : tile_rows<double>();
-  if (launch_diagnostics(c->d_inst, c->d_tiles + c->tile_first[k], nblk, ty, c->split ? 1 : 0,
+  if (launch_diagnostics(c->d_inst, c->d_tiles[1] + c->tile_first[k], nblk, kTileRows[1],
+                         c->split ? 1 : 0,
                          L.st[P][0], L.st[P][1], L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
                          c->d_partials, used, c->stream) != hipSuccess)
     return APDVM_ERR_HIP;
@@ -1162,6 +1251,174 @@ apdvm_status apdvm_traffic(apdvm_ctx *c, int32_t cls, double *bytes_per_step,
   }
   *bytes_per_step = b;
   *launches_per_step = n;
+  return APDVM_OK;
+}
+
+// Autotuner: for each stencil kernel class, time every tile height on the live data
+// with HIP events and keep the fastest; the state is restored afterwards.  With the
+// environment variable APDVM_TUNE_CACHE naming a file, choices are looked up there by
+// a key of the context's shape and appended after tuning.
+static void set_col_mode(apdvm_ctx *c, int mode) {
+  if (c->col_mode == mode) return;
+  c->col_mode = mode;
+  c->plan[0] = build_plan(c, 0);
+  c->plan[1] = build_plan(c, 1);
+  for (int p = 0; p < 2; ++p)
+    if (c->graph_exec[p]) {
+      (void)hipGraphExecDestroy(c->graph_exec[p]);
+      c->graph_exec[p] = nullptr;
+    }
+}
+
+static std::string tune_key(const apdvm_ctx *c) {
+  std::ostringstream k;
+  k << "gfx950 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+    << " cells=" << (long long)c->cells;
+  int mx = 0;
+  for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
+  k << " maxnx=" << mx;
+  return k.str();
+}
+
+apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choice) {
+  if (!c || steps_per_trial < 1) return APDVM_ERR_ARG;
+  for (int k = 0; k < c->n; ++k)
+    if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  const int classes[3] = {kHelmRhs, kUpdateUQ, kStageTerms};
+  const char *cache = std::getenv("APDVM_TUNE_CACHE");
+  const std::string key = tune_key(c);
+  bool cached = false;
+  if (cache) {
+    std::ifstream in(cache);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() &&
+          line[key.size()] == '|') {
+        std::istringstream rest(line.substr(key.size() + 1));
+        int t[3], mode = 0;
+        if (rest >> t[0] >> t[1] >> t[2] >> mode) {
+          for (int m = 0; m < 3; ++m) c->ty_index[classes[m]] = t[m] == kTileRows[0] ? 0 : 1;
+          set_col_mode(c, (mode && c->col_full_ok) ? 1 : 0);
+          cached = true;
+        }
+      }
+    }
+  }
+  if (!cached) {
+    // snapshot the current state of every instance
+    const Layout &L = c->L;
+    const int P = c->parity;
+    const size_t tsz = c->split ? sizeof(float) : sizeof(double);
+    size_t total = 0;
+    for (const Inst &I : c->inst) total += (size_t)I.plane * (5 * tsz + sizeof(double));
+    char *snap = nullptr;
+    if (hipMalloc(&snap, total) != hipSuccess) return APDVM_ERR_NOMEM;
+    auto copy_state = [&](bool save) {
+      char *q = snap;
+      bool ok = true;
+      for (const Inst &I : c->inst) {
+        const size_t pb = (size_t)I.plane * tsz;
+        for (int f = 0; f < 5; ++f) {
+          char *dev = static_cast<char *>(I.tbase) + (size_t)L.st[P][f] * pb;
+          ok = ok && hipMemcpyAsync(save ? q : dev, save ? dev : q, pb, hipMemcpyDeviceToDevice,
+                                    c->stream) == hipSuccess;
+          q += pb;
+        }
+        char *th = reinterpret_cast<char *>(I.dbase + (size_t)L.th[P] * I.plane);
+        const size_t db = (size_t)I.plane * sizeof(double);
+        ok = ok && hipMemcpyAsync(save ? q : th, save ? th : q, db, hipMemcpyDeviceToDevice,
+                                  c->stream) == hipSuccess;
+        q += db;
+      }
+      return ok;
+    };
+    const int64_t step0 = c->step;
+    const bool graph = c->use_graph;
+    c->use_graph = false;
+    bool ok = copy_state(true);
+    for (int m = 0; ok && m < 3; ++m) {
+      const int cls = classes[m];
+      double best = 1e300;
+      int best_ti = 1;
+      for (int ti = 0; ok && ti < 2; ++ti) {
+        c->ty_index[cls] = ti;
+        ok = apdvm_step(c, 1) == APDVM_OK;  // warm-up with this choice
+        ok = ok && apdvm_timing_enable(c, cls) == APDVM_OK;
+        ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
+        int64_t nl = 0;
+        double ms = 0.0;
+        ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
+        if (ok && ms < best) {
+          best = ms;
+          best_ti = ti;
+        }
+      }
+      c->ty_index[cls] = best_ti;
+    }
+    if (ok && c->col_full_ok) {
+      double tmode[2] = {0.0, 0.0};
+      for (int mode = 0; ok && mode < 2; ++mode) {
+        set_col_mode(c, mode);
+        ok = apdvm_step(c, 1) == APDVM_OK;
+        const int four[3] = {kColsA, kColsB, kColsAInv};
+        const int nm = mode ? 1 : 3;
+        for (int m = 0; ok && m < nm; ++m) {
+          ok = apdvm_timing_enable(c, mode ? kColsFull : four[m]) == APDVM_OK;
+          ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
+          int64_t nl = 0;
+          double ms = 0.0;
+          ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
+          tmode[mode] += ms;
+        }
+      }
+      set_col_mode(c, tmode[1] < tmode[0] ? 1 : 0);
+    }
+    ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
+    c->parity = P;
+    ok = ok && copy_state(false) && hipStreamSynchronize(c->stream) == hipSuccess;
+    (void)hipFree(snap);
+    c->terms_ready = false;
+    c->step = step0;
+    c->use_graph = graph;
+    if (!ok) return APDVM_ERR_HIP;
+    if (cache) {
+      std::ofstream out(cache, std::ios::app);
+      out << key << "|" << kTileRows[c->ty_index[classes[0]]] << " "
+          << kTileRows[c->ty_index[classes[1]]] << " " << kTileRows[c->ty_index[classes[2]]]
+          << " " << c->col_mode << "\n";
+    }
+  }
+  // the graphs captured the old launch shapes
+  for (int p = 0; p < 2; ++p)
+    if (c->graph_exec[p]) {
+      (void)hipGraphExecDestroy(c->graph_exec[p]);
+      c->graph_exec[p] = nullptr;
+    }
+  if (choice) {
+    for (int k = 0; k < kNumClasses; ++k) choice[k] = kTileRows[c->ty_index[k]];
+    // for the FFT column classes report which form runs: 1 used, 0 not used
+    choice[kColsA] = choice[kColsB] = choice[kColsAInv] = c->col_mode ? 0 : 1;
+    choice[kColsFull] = c->col_mode ? 1 : 0;
+  }
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
+  if (!c || !choice) return APDVM_ERR_ARG;
+  const int classes[3] = {kHelmRhs, kUpdateUQ, kStageTerms};
+  for (int m = 0; m < 3; ++m)
+    if (choice[classes[m]] != kTileRows[0] && choice[classes[m]] != kTileRows[1])
+      return APDVM_ERR_ARG;
+  const int mode = choice[kColsFull] ? 1 : 0;
+  if (mode && !c->col_full_ok) return APDVM_ERR_ARG;
+  for (int m = 0; m < 3; ++m)
+    c->ty_index[classes[m]] = choice[classes[m]] == kTileRows[0] ? 0 : 1;
+  set_col_mode(c, mode);
+  for (int p = 0; p < 2; ++p)
+    if (c->graph_exec[p]) {
+      (void)hipGraphExecDestroy(c->graph_exec[p]);
+      c->graph_exec[p] = nullptr;
+    }
   return APDVM_OK;
 }
 

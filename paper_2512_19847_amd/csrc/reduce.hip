@@ -7,8 +7,6 @@
 
 namespace apdvm {
 
-namespace {
-
 __device__ __forceinline__ int wrapi(int g, int n) {
   if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
   return g;
@@ -108,8 +106,6 @@ __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
     for (int k = 0; k < 8; ++k) partials[8 * blockIdx.x + k] = o[k];
   }
 }
-
-}  // namespace
 
 // tiles: the stencil work items (64 x ty cells) of one instance.
 hipError_t launch_diagnostics(const Inst *insts, const Work *tiles, int ntiles, int ty, int split,

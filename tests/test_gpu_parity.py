@@ -45,12 +45,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run_gpu(cases, tab, nsteps, precision=0):
+def _run_gpu(cases, tab, nsteps, precision=0, shape=None):
     apdvm = _apdvm()
     sim = apdvm.Simulation([dict(nx=c["state"][0].shape[1], ny=c["state"][0].shape[0],
                                  eps=c["eps"], tau=c["tau"], dt=c["dt"],
                                  lx=c.get("lx", 2 * np.pi), ly=c.get("ly", 2 * np.pi))
                             for c in cases], tableau=tab, precision=precision)
+    if shape is not None:
+        sim.set_tuning(*shape)
     for k, c in enumerate(cases):
         sim.set_fields(k, *c["state"])
     sim.step(nsteps)
@@ -88,6 +90,23 @@ def test_ragged_nonsquare(eps, tau):
     err = _relerr(got, ref)
     _say(f"  relerr {err}")
     assert max(err.values()) <= TOL, err
+
+
+@pytest.mark.parametrize("shape", [(8, False), (8, True), (16, True)])
+def test_every_launch_shape_matches_oracle(shape):
+    """The shapes the autotuner can pick: tile height 8 or 16, four-step or single-pass
+    column FFT; ragged non-square grid, two instances."""
+    cases = [dict(state=wl.random_divfree(96, 72, kmax=4, rms=0.1, seed=31), eps=0.05, tau=0.3,
+                  dt=0.01),
+             dict(state=wl.random_divfree(48, 36, kmax=4, rms=0.1, seed=32), eps=1e-5, tau=0.05,
+                  dt=0.02)]
+    _say(f"case launch shape {shape}")
+    got = _run_gpu(cases, "ars443", 4, shape=shape)
+    for k, c in enumerate(cases):
+        ref = _oracle(c["state"], c["eps"], c["tau"], c["dt"], "ars443", 4)
+        err = _relerr(got[k], ref)
+        _say(f"  instance {k} relerr {err}")
+        assert max(err.values()) <= TOL, (k, err)
 
 
 @pytest.mark.parametrize("n", [8, 16, 24])
