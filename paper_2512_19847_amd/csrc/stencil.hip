@@ -38,42 +38,133 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
-// Jiang-Shu WENO5 value at the right face of cell c from cells a..e (left-biased):
-// candidates q_k, smoothness indicators beta_k, weights d_k / (eps_w + beta_k)^2 with
-// d = (1, 6, 3)/10 and eps_w = 1e-6.  The weights are normalised with one division:
-// w_k proportional to d_k times the product of the other two (eps_w + beta)^2.
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
-  const double q0 = (2.0 * a - 7.0 * b + 11.0 * c) * (1.0 / 6.0);
-  const double q1 = (-b + 5.0 * c + 2.0 * d) * (1.0 / 6.0);
-  const double q2 = (2.0 * c + 5.0 * d - e) * (1.0 / 6.0);
-  const double t0 = a - 2.0 * b + c, t1 = a - 4.0 * b + 3.0 * c;
-  const double t2 = b - 2.0 * c + d, t3 = b - d;
-  const double t4 = c - 2.0 * d + e, t5 = 3.0 * c - 4.0 * d + e;
-  double s0 = 1e-6 + (13.0 / 12.0) * t0 * t0 + 0.25 * t1 * t1;
-  double s1 = 1e-6 + (13.0 / 12.0) * t2 * t2 + 0.25 * t3 * t3;
-  double s2 = 1e-6 + (13.0 / 12.0) * t4 * t4 + 0.25 * t5 * t5;
-  s0 *= s0;
-  s1 *= s1;
-  s2 *= s2;
-  const double w0 = 0.1 * s1 * s2, w1 = 0.6 * s0 * s2, w2 = 0.3 * s0 * s1;
-  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+// WENO5 of Jiang and Shu, written through 3-cell windows.  For cells g_{k-1}, g_k,
+// g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and D = g_{k+1} - g_{k-1}.  With eps_w = 1e-6
+// and linear weights d = (1, 6, 3)/10, the left-biased reconstruction at face i+1/2 uses
+//   beta0 = 13/12 S^2 + 1/4 (2S + D)^2 on window i-1, beta1 = 13/12 S^2 + 1/4 D^2 on window
+//   i, beta2 = 13/12 S^2 + 1/4 (2S - D)^2 on window i+1,
+//   q0 = (2 g_{i-2} - 7 g_{i-1} + 11 g_i)/6, q1 = (-g_{i-1} + 5 g_i + 2 g_{i+1})/6,
+//   q2 = (2 g_i + 5 g_{i+1} - g_{i+2})/6,
+// weights alpha_k = d_k / (eps_w + beta_k)^2; the right-biased one is its mirror image.
+// These are the Jiang-Shu smoothness indicators and candidates rewritten in S and D
+// (a - 4b + 3c = 2S + D and 3c - 4d + e = 2S - D on the respective windows).
+
+struct Win {  // one window: 13/12 S^2, S, D
+  double a, s, d;
+};
+struct WinF {
+  float a, s, d;
+};
+__device__ __forceinline__ Win win(double l, double c, double r) {
+  const double S = l - 2.0 * c + r;
+  return Win{(13.0 / 12.0) * S * S, S, r - l};
+}
+__device__ __forceinline__ WinF win(float l, float c, float r) {
+  const float S = l - 2.0f * c + r;
+  return WinF{(13.0f / 12.0f) * S * S, S, r - l};
+}
+template <typename W, typename T>
+__device__ __forceinline__ T sq_eps(T beta) {
+  const T x = T(1e-6) + beta;
+  return x * x;
+}
+// (eps_w + beta)^2 of the three indicator forms of a window
+template <typename W, typename T>
+__device__ __forceinline__ T ind0(const W &w) {
+  const T t = T(2) * w.s + w.d;
+  return sq_eps<W, T>(w.a + T(0.25) * t * t);
+}
+template <typename W, typename T>
+__device__ __forceinline__ T ind1(const W &w) {
+  return sq_eps<W, T>(w.a + T(0.25) * w.d * w.d);
+}
+template <typename W, typename T>
+__device__ __forceinline__ T ind2(const W &w) {
+  const T t = T(2) * w.s - w.d;
+  return sq_eps<W, T>(w.a + T(0.25) * t * t);
 }
 
-// float form: three hardware reciprocals (a product form could overflow float).
-__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e) {
-  const float q0 = (2.0f * a - 7.0f * b + 11.0f * c) * (1.0f / 6.0f);
-  const float q1 = (-b + 5.0f * c + 2.0f * d) * (1.0f / 6.0f);
-  const float q2 = (2.0f * c + 5.0f * d - e) * (1.0f / 6.0f);
-  const float t0 = a - 2.0f * b + c, t1 = a - 4.0f * b + 3.0f * c;
-  const float t2 = b - 2.0f * c + d, t3 = b - d;
-  const float t4 = c - 2.0f * d + e, t5 = 3.0f * c - 4.0f * d + e;
-  float s0 = 1e-6f + (13.0f / 12.0f) * t0 * t0 + 0.25f * t1 * t1;
-  float s1 = 1e-6f + (13.0f / 12.0f) * t2 * t2 + 0.25f * t3 * t3;
-  float s2 = 1e-6f + (13.0f / 12.0f) * t4 * t4 + 0.25f * t5 * t5;
-  const float w0 = 0.1f * __builtin_amdgcn_rcpf(s0 * s0);
-  const float w1 = 0.6f * __builtin_amdgcn_rcpf(s1 * s1);
-  const float w2 = 0.3f * __builtin_amdgcn_rcpf(s2 * s2);
-  return (w0 * q0 + w1 * q1 + w2 * q2) * __builtin_amdgcn_rcpf(w0 + w1 + w2);
+// float64 quotient through the hardware reciprocal refined by Newton steps.
+__device__ __forceinline__ double qdiv(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = n * r;
+  return fma(r, fma(-d, q, n), q);
+}
+
+// Numerator and denominator of one reconstruction: weights proportional to
+// d_k / s_k with s_k = (eps_w + beta_k)^2, normalised through products of the others
+// (float64), or through reciprocals (float, where products could overflow).
+__device__ __forceinline__ void nd(double s0, double s1, double s2, double q0, double q1,
+                                   double q2, double &n, double &den) {
+  const double w0 = 0.1 * s1 * s2, w1 = 0.6 * s0 * s2, w2 = 0.3 * s0 * s1;
+  n = w0 * q0 + w1 * q1 + w2 * q2;
+  den = w0 + w1 + w2;
+}
+__device__ __forceinline__ void nd(float s0, float s1, float s2, float q0, float q1, float q2,
+                                   float &n, float &den) {
+  const float w0 = 0.1f * __builtin_amdgcn_rcpf(s0), w1 = 0.6f * __builtin_amdgcn_rcpf(s1),
+              w2 = 0.3f * __builtin_amdgcn_rcpf(s2);
+  n = w0 * q0 + w1 * q1 + w2 * q2;
+  den = w0 + w1 + w2;
+}
+// n+/d+ + n-/d- with one division
+__device__ __forceinline__ double sum2(double np, double dp, double nm, double dm) {
+  return qdiv(np * dm + nm * dp, dp * dm);
+}
+__device__ __forceinline__ float sum2(float np, float dp, float nm, float dm) {
+  return (np * dm + nm * dp) * __builtin_amdgcn_rcpf(dp * dm);
+}
+
+template <typename T>
+struct WinOf;
+template <>
+struct WinOf<double> {
+  using type = Win;
+};
+template <>
+struct WinOf<float> {
+  using type = WinF;
+};
+
+// Face between cells c2 and c3 of six consecutive values c0..c5 of one function g:
+// left-biased reconstruction plus right-biased reconstruction of the same g (the
+// Lax-Friedrichs split without dissipation, g = f/2).  The two share windows i and i+1
+// and two candidates.
+template <typename T>
+__device__ __forceinline__ T flux_sym(T c0, T c1, T c2, T c3, T c4, T c5) {
+  using W = typename WinOf<T>::type;
+  const W wa = win(c0, c1, c2), wb = win(c1, c2, c3), wc = win(c2, c3, c4), wd = win(c3, c4, c5);
+  const T sixth = T(1.0 / 6.0);
+  const T M = (-c1 + T(5) * c2 + T(2) * c3) * sixth;  // window i at i+1/2
+  const T N = (T(2) * c2 + T(5) * c3 - c4) * sixth;   // window i+1 at i+1/2
+  const T P = (T(2) * c0 - T(7) * c1 + T(11) * c2) * sixth;
+  const T Pm = (T(2) * c5 - T(7) * c4 + T(11) * c3) * sixth;
+  T np, dp, nm, dm;
+  nd(ind0<W, T>(wa), ind1<W, T>(wb), ind2<W, T>(wc), P, M, N, np, dp);
+  nd(ind2<W, T>(wd), ind1<W, T>(wc), ind0<W, T>(wb), Pm, N, M, nm, dm);
+  return sum2(np, dp, nm, dm);
+}
+
+// Same face for two functions: p (left-biased) and m (right-biased), the split fluxes
+// f + w and f - w of a dissipative Lax-Friedrichs flux (inputs already halved).
+template <typename T>
+__device__ __forceinline__ T flux_lf(const T *p, const T *m) {
+  using W = typename WinOf<T>::type;
+  const T sixth = T(1.0 / 6.0);
+  const W pa = win(p[0], p[1], p[2]), pb = win(p[1], p[2], p[3]), pc = win(p[2], p[3], p[4]);
+  const T q0 = (T(2) * p[0] - T(7) * p[1] + T(11) * p[2]) * sixth;
+  const T q1 = (-p[1] + T(5) * p[2] + T(2) * p[3]) * sixth;
+  const T q2 = (T(2) * p[2] + T(5) * p[3] - p[4]) * sixth;
+  const W mb = win(m[1], m[2], m[3]), mc = win(m[2], m[3], m[4]), md = win(m[3], m[4], m[5]);
+  const T r0 = (T(2) * m[5] - T(7) * m[4] + T(11) * m[3]) * sixth;
+  const T r1 = (T(2) * m[2] + T(5) * m[3] - m[4]) * sixth;
+  const T r2 = (-m[1] + T(5) * m[2] + T(2) * m[3]) * sixth;
+  T np, dp, nm, dm;
+  nd(ind0<W, T>(pa), ind1<W, T>(pb), ind2<W, T>(pc), q0, q1, q2, np, dp);
+  nd(ind2<W, T>(md), ind1<W, T>(mc), ind0<W, T>(mb), r0, r1, r2, nm, dm);
+  return sum2(np, dp, nm, dm);
 }
 
 // Numerical flux at the face between cells k = 2 and k = 3 of six consecutive cells
@@ -82,20 +173,18 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
 // (DISS) or alpha = 0: left-biased WENO5 of f+ plus right-biased WENO5 of f-.
 template <typename T, bool DISS>
 __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf) {
-  T p[6], m[6];
+  if (DISS) {
+    T p[6], m[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const T fk = sf * f[k * stride];
-    if (DISS) {
-      const T wk = w[k * stride];
+    for (int k = 0; k < 6; ++k) {
+      const T fk = sf * f[k * stride], wk = w[k * stride];
       p[k] = fk + wk;
       m[k] = fk - wk;
-    } else {
-      p[k] = fk;
-      m[k] = fk;
     }
+    return flux_lf(p, m);
   }
-  return weno5(p[0], p[1], p[2], p[3], p[4]) + weno5(m[5], m[4], m[3], m[2], m[1]);
+  return flux_sym(sf * f[0], sf * f[stride], sf * f[2 * stride], sf * f[3 * stride],
+                  sf * f[4 * stride], sf * f[5 * stride]);
 }
 
 // LDS tile geometry for a 64 x TY tile with a 3-cell halo.
@@ -111,24 +200,44 @@ struct Geo {
   __device__ static int at(int lx, int ly) { return (ly + kHalo) * W + lx + kHalo; }
 };
 
-// Stage a plane (with periodic halo) into LDS, converting to S and scaling by sc.
-template <int TY, typename S, typename G>
-__device__ __forceinline__ void stage_plane(S *lds, const G *__restrict__ plane, int nx, int ny,
-                                            int x0, int y0, S sc) {
+// Staging of NP planes (with periodic halo) into LDS in two phases: load() issues every
+// global load of the thread into registers, store() converts, scales and writes them to
+// LDS.  Loads of several planes (and of later phases) are thus in flight together
+// instead of each waiting for the one before.
+template <int TY, int NP, typename G>
+struct Stage {
   using Gm = Geo<TY>;
-  const bool inner = x0 >= kHalo && x0 + kTileX + kHalo <= nx && y0 >= kHalo &&
-                     y0 + TY + kHalo <= ny;
-  for (int idx = threadIdx.x; idx < Gm::PL; idx += kStencilThreads) {
-    const int ly = idx / Gm::W;
-    const int lx = idx - ly * Gm::W;
-    int gx = x0 + lx - kHalo, gy = y0 + ly - kHalo;
-    if (!inner) {
-      gx = wrap(gx, nx);
-      gy = wrap(gy, ny);
+  static constexpr int IT = (Gm::PL + kStencilThreads - 1) / kStencilThreads;
+  G v[NP][IT];
+  __device__ __forceinline__ void load(const G *const *plane, int nx, int ny, int x0, int y0) {
+    const bool inner = x0 >= kHalo && x0 + kTileX + kHalo <= nx && y0 >= kHalo &&
+                       y0 + TY + kHalo <= ny;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * kStencilThreads;
+      const int ly = idx / Gm::W;
+      const int lx = idx - ly * Gm::W;
+      int gx = x0 + lx - kHalo, gy = y0 + ly - kHalo;
+      if (!inner) {
+        gx = wrap(gx, nx);
+        gy = wrap(gy, ny);
+      }
+      const long long off = idx < Gm::PL ? (long long)gy * nx + gx : 0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) v[p][it] = plane[p][off];
     }
-    lds[idx] = sc * (S)plane[(long long)gy * nx + gx];
   }
-}
+  template <typename S>
+  __device__ __forceinline__ void store(S *const *lds, S sc) const {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * kStencilThreads;
+        if (idx < Gm::PL) lds[p][idx] = sc * (S)v[p][it];
+      }
+  }
+};
 
 // x faces (TY rows x 65) and y faces (TY + 1 rows x 64) of two fluxes in one index
 // space; the x part is padded to whole wavefronts so no wavefront mixes the two.
@@ -199,25 +308,6 @@ __device__ __forceinline__ double *dplane(const Inst &I, int slot) {
   return I.dbase + (long long)slot * I.plane;
 }
 
-// Step 1 at cell g: v(i) = [te2 v^n - dt (sum_j at_ij E(j) + sum_j a_ij v(j))] kinv,
-// the history sum in float64.  eh and vh are the terms of the newest stage when they are
-// held in registers (nE / nV then cover the older ones only).
-template <typename T>
-__device__ __forceinline__ void relax_v_at(const Inst &I, const ArgsV &a, long long g, double vn1,
-                                           double vn2, double h1, double h2) {
-  for (int j = 0; j < a.nE; ++j) {
-    h1 += a.cE[j] * (double)tplane<T>(I, a.E[j][0])[g];
-    h2 += a.cE[j] * (double)tplane<T>(I, a.E[j][1])[g];
-  }
-  for (int j = 0; j < a.nV; ++j) {
-    h1 += a.cV[j] * (double)tplane<T>(I, a.V[j][0])[g];
-    h2 += a.cV[j] * (double)tplane<T>(I, a.V[j][1])[g];
-  }
-  const double kinv = I.kinv[a.stage], te2 = I.te2, dt = I.dt;
-  tplane<T>(I, a.out[0])[g] = (T)((te2 * vn1 - dt * h1) * kinv);
-  tplane<T>(I, a.out[1])[g] = (T)((te2 * vn2 - dt * h2) * kinv);
-}
-
 // ------------------------------------------------------------------ step 2 RHS
 
 template <typename T, int TY>
@@ -228,17 +318,40 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
   __shared__ T sV1[Gm::PL], sV2[Gm::PL];
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
-  stage_plane<TY>(sV1, tplane<T>(I, a.v[0]), I.nx, I.ny, wk.a, wk.b, T(1));
-  stage_plane<TY>(sV2, tplane<T>(I, a.v[1]), I.nx, I.ny, wk.a, wk.b, T(1));
-  __syncthreads();
+  Stage<TY, 2, T> st;
+  {
+    const T *g[2] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    st.load(g, I.nx, I.ny, wk.a, wk.b);
+  }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = wk.a + tx;
-  if (gx >= I.nx) return;
-  const T ihx12 = T(I.ihx / 12.0), ihy12 = T(I.ihy / 12.0);
-  const T ihx2 = T(I.ihx * I.ihx / 12.0), ihy2 = T(I.ihy * I.ihy / 12.0);
+  const bool col = gx < I.nx;
+  // pointwise inputs of the right-hand side, loaded while the tile arrives
   const double sig = I.sigma[a.stage];
   const double c_d = 1.0 / (I.dt * a.aii * a.aii), c_0 = 1.0 / (I.dt * a.aii), c_l = 1.0 / a.aii;
-  const double *thn = dplane(I, a.thn);
+  double base[Gm::ROWS];
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int gy = wk.b + ty0 + 4 * r;
+    base[r] = 0.0;
+    if (col && gy < I.ny) {
+      const long long g = (long long)gy * I.nx + gx;
+      double hd = 0.0, hl = 0.0;
+      for (int j = 0; j < a.nD; ++j) hd += a.cD[j] * (double)tplane<T>(I, a.D[j])[g];
+      for (int j = 0; j < a.nL; ++j) hl += a.cL[j] * (double)tplane<T>(I, a.L[j])[g];
+      base[r] = -sig * dplane(I, a.thn)[g] + c_d * hd + c_0 * (double)tplane<T>(I, a.du0)[g] -
+                c_l * hl;
+    }
+  }
+  {
+    T *l[2] = {sV1, sV2};
+    st.store(l, T(1));
+  }
+  __syncthreads();
+  if (!col) return;
+  const T ihx12 = T(I.ihx / 12.0), ihy12 = T(I.ihy / 12.0);
+  const T ihx2 = T(I.ihx * I.ihx / 12.0), ihy2 = T(I.ihy * I.ihy / 12.0);
+#pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + 4 * r;
     const int gy = wk.b + ly;
@@ -248,12 +361,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
     const T ddb = -cd2(sV1, c, 1, ihx2) + T(2) * cdxy(sV2, c, Gm::W, ihx12, ihy12) +
                   cd2(sV1, c, Gm::W, ihy2);
     const long long g = (long long)gy * I.nx + gx;
-    double hd = 0.0, hl = 0.0;
-    for (int j = 0; j < a.nD; ++j) hd += a.cD[j] * (double)tplane<T>(I, a.D[j])[g];
-    for (int j = 0; j < a.nL; ++j) hl += a.cL[j] * (double)tplane<T>(I, a.L[j])[g];
-    const double du0 = (double)tplane<T>(I, a.du0)[g];
-    const double R = -sig * thn[g] + c_d * hd + c_0 * du0 - (double)ddb - c_l * hl;
-    dplane(I, a.out_r)[g] = R;
+    dplane(I, a.out_r)[g] = base[r] - (double)ddb;
     tplane<T>(I, a.out_ddb)[g] = ddb;
   }
 }
@@ -268,19 +376,44 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   // v1, v2 and the partner velocity (halved for the fluxes); theta reuses the partner
   // planes once the fluxes that need them are done.
   __shared__ T sV1[Gm::PL], sV2[Gm::PL];
-  __shared__ T sP[2 * Gm::PL];
+  __shared__ __align__(16) T sP[2 * Gm::PL];
   __shared__ T fx[Gm::FXN], fy[Gm::FYN];
   static_assert(sizeof(T) * 2 * Gm::PL >= sizeof(double) * Gm::PL, "theta reuse");
   T *sP1 = sP, *sP2 = sP + Gm::PL;
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
-  stage_plane<TY>(sV1, tplane<T>(I, a.v[0]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sV2, tplane<T>(I, a.v[1]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sP1, tplane<T>(I, a.partner[0]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sP2, tplane<T>(I, a.partner[1]), nx, ny, wk.a, wk.b, T(0.5));
-  __syncthreads();
+  {
+    Stage<TY, 4, T> st;
+    const T *g[4] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0]),
+                     tplane<T>(I, a.partner[1])};
+    st.load(g, nx, ny, wk.a, wk.b);
+    T *l[4] = {sV1, sV2, sP1, sP2};
+    st.store(l, T(0.5));
+  }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  const bool col = gx < nx;
+  // pointwise inputs of the updates (state n and the stage history), loaded early;
+  // the float64 history sums are formed before the fluxes
+  double un1[Gm::ROWS], un2[Gm::ROWS], qn[Gm::ROWS], h1[Gm::ROWS], h2[Gm::ROWS], hg[Gm::ROWS];
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int gy = wk.b + ty0 + 4 * r;
+    un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
+    if (col && gy < ny) {
+      const long long g = (long long)gy * nx + gx;
+      un1[r] = (double)tplane<T>(I, a.un[0])[g];
+      un2[r] = (double)tplane<T>(I, a.un[1])[g];
+      qn[r] = (double)tplane<T>(I, a.qn)[g];
+      for (int j = 0; j < a.nH; ++j) {
+        h1[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][0])[g];
+        h2[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][1])[g];
+      }
+      for (int j = 0; j < a.nG; ++j) hg[r] += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
+    }
+  }
+  __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   T hu1[Gm::ROWS], hu2[Gm::ROWS], dv[Gm::ROWS];
   // first row of B(v) = (-v1, v2), dissipation on u1
@@ -297,17 +430,24 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   for (int r = 0; r < Gm::ROWS; ++r)
     hu2[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
   __syncthreads();
-  // div v without dissipation; theta (float64) into the partner planes meanwhile
+  // div v without dissipation; theta (float64) loaded meanwhile into the partner planes
+  Stage<TY, 1, double> sth;
+  {
+    const double *g[1] = {dplane(I, a.th)};
+    sth.load(g, nx, ny, wk.a, wk.b);
+  }
   faces<TY, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
   double *sTh = reinterpret_cast<double *>(sP);
-  stage_plane<TY>(sTh, dplane(I, a.th), nx, ny, wk.a, wk.b, 1.0);
+  {
+    double *l[1] = {sTh};
+    sth.store(l, 1.0);
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     dv[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
 
-  const int gx = wk.a + tx;
-  if (gx >= nx) return;
+  if (!col) return;
   const double ihx12 = I.ihx / 12.0, ihy12 = I.ihy / 12.0;
   const double dt = I.dt, te2 = I.te2, kinv = I.kinv[a.stage], aii = a.aii;
   const double htau = 0.5 * I.tau;
@@ -321,16 +461,10 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
     // implicit velocity terms: D_W.B(v) + D0 theta (theta float64)
     const double Hu1 = (double)hu1[r] + cd1(sTh, c, 1, ihx12);
     const double Hu2 = (double)hu2[r] + cd1(sTh, c, Gm::W, ihy12);
-    double s1 = aii * Hu1, s2 = aii * Hu2, sq = 0.0;
-    for (int j = 0; j < a.nH; ++j) {
-      s1 += a.cH[j] * (double)tplane<T>(I, a.H[j][0])[g];
-      s2 += a.cH[j] * (double)tplane<T>(I, a.H[j][1])[g];
-    }
-    for (int j = 0; j < a.nG; ++j) sq += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
-    const double u1 = (double)tplane<T>(I, a.un[0])[g] - dt * s1;
-    const double u2 = (double)tplane<T>(I, a.un[1])[g] - dt * s2;
+    const double u1 = un1[r] - dt * (h1[r] + aii * Hu1);
+    const double u2 = un2[r] - dt * (h2[r] + aii * Hu2);
     const double Hq = htau * (double)dv[r];
-    const double q = (te2 * (double)tplane<T>(I, a.qn)[g] - dt * aii * Hq - dt * sq) * kinv;
+    const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
     tplane<T>(I, a.out_u[0])[g] = (T)u1;
     tplane<T>(I, a.out_u[1])[g] = (T)u2;
     tplane<T>(I, a.out_q)[g] = (T)q;
@@ -345,14 +479,14 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
 // ------------------------------------------------------------------ stage terms
 
 // E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u), D0.u and Ltheta of a known stage, and,
-// fused, step 1 of the next stage: v(next) from v^n, the history and this E.
+// fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
 template <typename T, int TY>
 __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
   using Gm = Geo<TY>;
   // sU1 and sU2 are contiguous so that theta (float64) can reuse them at the end.
-  __shared__ T sU[2 * Gm::PL];
+  __shared__ __align__(16) T sU[2 * Gm::PL];
   __shared__ T sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
   __shared__ T fx[Gm::FXN], fy[Gm::FYN];
   static_assert(sizeof(T) * 2 * Gm::PL >= sizeof(double) * Gm::PL, "theta reuse");
@@ -360,117 +494,120 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
-  stage_plane<TY>(sU1, tplane<T>(I, a.u[0]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sU2, tplane<T>(I, a.u[1]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sQ, tplane<T>(I, a.q), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sV1, tplane<T>(I, a.v[0]), nx, ny, wk.a, wk.b, T(0.5));
-  stage_plane<TY>(sV2, tplane<T>(I, a.v[1]), nx, ny, wk.a, wk.b, T(0.5));
-  __syncthreads();
+  {
+    Stage<TY, 5, T> st;
+    const T *g[5] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1]), tplane<T>(I, a.q),
+                     tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    st.load(g, nx, ny, wk.a, wk.b);
+    T *l[5] = {sU1, sU2, sQ, sV1, sV2};
+    st.store(l, T(0.5));
+  }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  const bool col = gx < nx;
+  const bool want_lt = a.out_lt != kNoSlot;
+  // pointwise inputs, loaded early: D0^2:B(v) for Ltheta, and for the fused step 1
+  // rv = te2 v^n - dt * (its history), formed in float64 now
+  const double dt = I.dt, te2d = I.te2;
+  double ddb[Gm::ROWS], rv1[Gm::ROWS], rv2[Gm::ROWS];
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int gy = wk.b + ty0 + 4 * r;
+    ddb[r] = rv1[r] = rv2[r] = 0.0;
+    if (col && gy < ny) {
+      const long long g = (long long)gy * nx + gx;
+      if (want_lt) ddb[r] = (double)tplane<T>(I, a.ddb)[g];
+      if (nv.stage > 0) {
+        double h1 = 0.0, h2 = 0.0;
+        for (int j = 0; j < nv.nE; ++j) {
+          h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
+          h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
+        }
+        for (int j = 0; j < nv.nV; ++j) {
+          h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
+          h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
+        }
+        rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
+        rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
+      }
+    }
+  }
+  __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
   const T ihx6 = T(I.ihx / 6.0), ihy6 = T(I.ihy / 6.0);
-  T b1[Gm::ROWS], b2[Gm::ROWS], g1[Gm::ROWS], g2[Gm::ROWS], du[Gm::ROWS], F1[Gm::ROWS],
-      F2[Gm::ROWS];
+  const T qt = T(0.25 * I.tau), te2 = T(I.te2);
+  // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
+  T e1[Gm::ROWS], e2[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
   faces<TY, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
-    b1[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
+    e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy));
   __syncthreads();
-  // second row of B(u) = (u2, u1)
+  // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
   faces<TY, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + 4 * r;
-    b2[r] = face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy);
     const int c = Gm::at(tx, ly);
-    du[r] = cd1(sU1, c, 1, ihx6) + cd1(sU2, c, Gm::W, ihy6);
     const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
-    F1[r] = T(0.5) * (u2 * u2 - u1 * u1);
-    F2[r] = u1 * u2;
+    e1[r] -= T(0.5) * (u2 * u2 - u1 * u1);
+    e2[r] = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2;
+    const int gy = wk.b + ly;
+    if (col && gy < ny)
+      tplane<T>(I, a.out_du)[(long long)gy * nx + gx] =
+          cd1(sU1, c, 1, ihx6) + cd1(sU2, c, Gm::W, ihy6);
   }
   __syncthreads();
-  // grad q with dissipation on v1 (x) and v2 (y)
+  // grad q with dissipation on v1 (x) and v2 (y); theta loaded meanwhile
+  Stage<TY, 1, double> sth;
+  if (want_lt) {
+    const double *g[1] = {dplane(I, a.th)};
+    sth.load(g, nx, ny, wk.a, wk.b);
+  }
   faces<TY, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
-  const bool want_lt = a.out_lt != kNoSlot;
   double *sTh = reinterpret_cast<double *>(sU);
-  if (want_lt) stage_plane<TY>(sTh, dplane(I, a.th), nx, ny, wk.a, wk.b, 1.0);
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r) {
-    g1[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx);
-    g2[r] = face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
+  if (want_lt) {
+    double *l[1] = {sTh};
+    sth.store(l, 1.0);
   }
-  const int gx = wk.a + tx;
-  if (gx >= nx) return;
-  const T qt = T(0.25 * I.tau), te2 = T(I.te2);
+  __syncthreads();
+  if (!col) return;
   const double ihx2 = I.ihx * I.ihx / 12.0, ihy2 = I.ihy * I.ihy / 12.0;
+  const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + 4 * r;
     const int gy = wk.b + ly;
     if (gy >= ny) break;
     const long long g = (long long)gy * nx + gx;
-    const T e1 = qt * b1[r] + te2 * g1[r] - F1[r];
-    const T e2 = qt * b2[r] + te2 * g2[r] - F2[r];
+    const int c = Gm::at(tx, ly);
+    const T E1 = e1[r] + te2 * face_dx<TY>(fx, tx, ly, ihx);
+    const T E2 = e2[r] + te2 * face_dy<TY>(fy, tx, ly, ihy);
     if (a.out_e[0] != kNoSlot) {
-      tplane<T>(I, a.out_e[0])[g] = e1;
-      tplane<T>(I, a.out_e[1])[g] = e2;
+      tplane<T>(I, a.out_e[0])[g] = E1;
+      tplane<T>(I, a.out_e[1])[g] = E2;
     }
-    tplane<T>(I, a.out_du)[g] = du[r];
     if (want_lt) {
-      const int c = Gm::at(tx, ly);
       const double lap = cd2(sTh, c, 1, ihx2) + cd2(sTh, c, Gm::W, ihy2);
-      tplane<T>(I, a.out_lt)[g] = (T)((double)tplane<T>(I, a.ddb)[g] + lap);
+      tplane<T>(I, a.out_lt)[g] = (T)(ddb[r] + lap);
     }
     if (nv.stage > 0) {
       // step 1 of the next stage; its newest history terms are this E and this v
-      const int c = Gm::at(tx, ly);
-      const double ce = a.c_e_next, cv = a.c_v_next;
       const double v1 = 2.0 * (double)sV1[c], v2 = 2.0 * (double)sV2[c];
-      relax_v_at<T>(I, nv, g, (double)tplane<T>(I, nv.vn[0])[g],
-                    (double)tplane<T>(I, nv.vn[1])[g], ce * (double)e1 + cv * v1,
-                    ce * (double)e2 + cv * v2);
+      const double s1 = a.c_e_next * (double)E1 + a.c_v_next * v1;
+      const double s2 = a.c_e_next * (double)E2 + a.c_v_next * v2;
+      tplane<T>(I, nv.out[0])[g] = (T)((rv1[r] - dt * s1) * kinv);
+      tplane<T>(I, nv.out[1])[g] = (T)((rv2[r] - dt * s2) * kinv);
     }
-  }
-}
-
-// Step 1 on its own (the stage right after new fields, when no stage-terms launch of
-// the previous stage could fuse it).
-template <typename T, int TY>
-__global__ __launch_bounds__(kStencilThreads) void k_relax_v(const Inst *__restrict__ insts,
-                                                             const Work *__restrict__ work,
-                                                             int nwork, ArgsV a) {
-  const Work wk = work[xcd_item(nwork)];
-  const Inst &I = insts[wk.inst];
-  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
-  const int gx = wk.a + tx;
-  if (gx >= I.nx) return;
-  for (int r = 0; r < TY / 4; ++r) {
-    const int gy = wk.b + ty0 + 4 * r;
-    if (gy >= I.ny) break;
-    const long long g = (long long)gy * I.nx + gx;
-    relax_v_at<T>(I, a, g, (double)tplane<T>(I, a.vn[0])[g], (double)tplane<T>(I, a.vn[1])[g],
-                  0.0, 0.0);
   }
 }
 
 // ------------------------------------------------------------------ launchers
 
-template <typename T>
-hipError_t launch_relax_v(int ty, const Inst *insts, const Work *work, int nwork, const ArgsV &a,
-                          hipStream_t st) {
-  if (ty == 8)
-    hipLaunchKernelGGL((k_relax_v<T, 8>), dim3(nwork), dim3(kStencilThreads), 0, st, insts, work,
-                       nwork, a);
-  else
-    hipLaunchKernelGGL((k_relax_v<T, 16>), dim3(nwork), dim3(kStencilThreads), 0, st, insts, work,
-                       nwork, a);
-  return hipGetLastError();
-}
 template <typename T>
 hipError_t launch_helmholtz_rhs(int ty, const Inst *insts, const Work *work, int nwork,
                                 const ArgsR &a, hipStream_t st) {
@@ -506,8 +643,6 @@ hipError_t launch_stage_terms(int ty, const Inst *insts, const Work *work, int n
 }
 
 #define APDVM_INST(T)                                                                           \
-  template hipError_t launch_relax_v<T>(int, const Inst *, const Work *, int, const ArgsV &,   \
-                                        hipStream_t);                                          \
   template hipError_t launch_helmholtz_rhs<T>(int, const Inst *, const Work *, int,            \
                                               const ArgsR &, hipStream_t);                     \
   template hipError_t launch_update_uq<T>(int, const Inst *, const Work *, int, const ArgsUQ &, \
