@@ -19,6 +19,17 @@
 
 namespace apdvm {
 
+// Global-memory pointers.  Plane, table and symbol addresses are read from the device
+// Inst table, where the compiler cannot see their address space; through a generic
+// pointer every access would be a FLAT instruction, which also counts against the LDS
+// wait counter and so makes LDS reads wait for global loads still in flight.
+template <class T>
+using Gp = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ Gp<T> gp(T *p) {
+  return (Gp<T>)p;
+}
+
 constexpr int kMaxStages = 8;
 constexpr int kMaxPasses = 16;
 constexpr int kNoSlot = -1;
@@ -38,11 +49,19 @@ constexpr int kRowSmallThreads = 128;
 constexpr int kColWidth = 16;
 constexpr int kColBTarget = 1024;  // complex values per column-B tile
 
+// Two-level twiddle table of a length-n transform, staged into LDS by every FFT kernel:
+// with B = 2^lb the smallest power of two whose square is at least n, entries
+// [0, B) hold exp(-2 pi i b / n) and entries [B, B + ceil(n / B)) hold
+// exp(-2 pi i a B / n), so exp(-2 pi i m / n) = hi[m >> lb] * lo[m & (B - 1)].
+constexpr int kTwCap = 256;  // B + ceil(n / B) for every n <= 16384
+
 struct FftPlan {
   int n;                  // transform length
   int npass;              // number of Stockham passes
   int radix[kMaxPasses];  // radices (2, 3, 4 or 8), first pass first
   const double2 *tw;      // tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device)
+  const double2 *tw2;     // two-level table (device), ntw entries
+  int lb, ntw;
 };
 
 struct Inst {

@@ -98,16 +98,70 @@ __device__ __forceinline__ void dft(double2 *v) {
   }
 }
 
+// Exact x / d by a multiply-high, for 0 <= x with x d < 2^32 (LDS indexes): m =
+// ceil(2^32 / d), and the error x (m d - 2^32) / (d 2^32) stays below 1 / d.
+struct Div {
+  unsigned long long m;
+  unsigned d;
+  __device__ __forceinline__ explicit Div(unsigned dd) : m(0xFFFFFFFFull / dd + 1), d(dd) {}
+  __device__ __forceinline__ int q(int x) const {
+    return (int)(((unsigned long long)(unsigned)x * m) >> 32);
+  }
+};
+
+// Complex values in global memory, accessed as a native two-lane vector (one 16-byte
+// load or store).
+using dv2 = double __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldc(Gp<const dv2> p) {
+  const dv2 t = *p;
+  return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void stc(Gp<dv2> p, double2 v) {
+  dv2 t;
+  t.x = v.x;
+  t.y = v.y;
+  *p = t;
+}
+
+// exp(-2 pi i m / n) from the two-level table staged in LDS (lo at t, hi at t + 2^lb).
+__device__ __forceinline__ double2 tw_at(const double2 *t, int lb, int m) {
+  return cmul(t[(1 << lb) + (m >> lb)], t[m & ((1 << lb) - 1)]);
+}
+
+// The two-level twiddle table of a plan passes through registers into LDS, so its global
+// loads travel with the data loads of the kernel.
+template <int NT>
+struct TwStage {
+  static constexpr int K = (kTwCap + NT - 1) / NT;
+  double2 v[K];
+  __device__ __forceinline__ void load(const FftPlan &P) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * NT;
+      if (i < P.ntw) v[k] = ldc(reinterpret_cast<Gp<const dv2>>(gp(P.tw2)) + i);
+    }
+  }
+  __device__ __forceinline__ void store(double2 *t, const FftPlan &P) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * NT;
+      if (i < P.ntw) t[i] = make_double2(v[k].x, v[k].y);
+    }
+  }
+};
+
 // One Stockham pass over nb transforms of length n held in LDS, element j of
 // transform b at buf[j * es + b * bs].  BMAJOR: consecutive threads take consecutive
-// transforms (column tiles) instead of consecutive butterflies (rows).
+// transforms (column tiles) instead of consecutive butterflies (rows).  The first pass
+// (Ns = 1) has unit twiddles and skips them.
 template <int R, int DIR, bool BMAJOR, int CAP, int NT>
 __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs, int Ns,
-                                     const double2 *__restrict__ tw) {
+                                     const double2 *tws, int lb) {
   constexpr int NPER = (CAP + R * NT - 1) / (R * NT);
   const int nbf = n / R;
   const int total = nbf * nb;
   const int twstep = n / (Ns * R);
+  const Div dmaj(BMAJOR ? nb : nbf), dns(Ns);
   double2 v[NPER][R];
   int dst[NPER];
 #pragma unroll
@@ -117,23 +171,25 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
     if (t < total) {
       int j, b;
       if (BMAJOR) {
-        j = t / nb;
+        j = dmaj.q(t);
         b = t - j * nb;
       } else {
-        b = t / nbf;
+        b = dmaj.q(t);
         j = t - b * nbf;
       }
-      const int k = j % Ns;
+      const int jq = dns.q(j), k = j - jq * Ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[p][r] = buf[(j + r * nbf) * es + b * bs];
+      if (Ns > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        double2 w = tw[k * r * twstep];
-        if (DIR > 0) w.y = -w.y;
-        v[p][r] = cmul(v[p][r], w);
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw_at(tws, lb, k * r * twstep);
+          if (DIR > 0) w.y = -w.y;
+          v[p][r] = cmul(v[p][r], w);
+        }
       }
       dft<R, DIR>(v[p]);
-      dst[p] = ((j / Ns) * Ns * R + k) * es + b * bs;
+      dst[p] = (jq * Ns * R + k) * es + b * bs;
     }
   }
   __syncthreads();
@@ -148,23 +204,33 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
 }
 
 template <int DIR, bool BMAJOR, int CAP, int NT>
-__device__ void fft_lds(double2 *buf, const FftPlan &P, int nb, int es, int bs) {
+__device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb, int es, int bs,
+                                        const double2 *tws) {
   int Ns = 1;
   for (int ps = 0; ps < P.npass; ++ps) {
     const int R = P.radix[ps];
     switch (R) {
-      case 8: pass<8, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, P.tw); break;
-      case 4: pass<4, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, P.tw); break;
-      case 3: pass<3, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, P.tw); break;
-      default: pass<2, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, P.tw); break;
+      case 8: pass<8, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
+      case 4: pass<4, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
+      case 3: pass<3, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
+      default: pass<2, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
     }
     Ns *= R;
   }
 }
 
-__device__ __forceinline__ double *dslot(const Inst &I, int slot) {
-  return I.dbase + (long long)slot * I.plane;
+__device__ __forceinline__ Gp<double> dslot(const Inst &I, int slot) {
+  return gp(I.dbase + (long long)slot * I.plane);
 }
+__device__ __forceinline__ Gp<dv2> cslot(const Inst &I, int slot) {
+  return reinterpret_cast<Gp<dv2>>(dslot(I, slot));
+}
+
+
+
+// Each kernel below stages its tile in two phases: every thread first issues all of its
+// global loads (data, twiddle table, and the Helmholtz divisors of the elements it will
+// scale), then writes them to LDS, so one memory round trip covers the whole tile.
 
 // ------------------------------------------------------------------ rows forward
 
@@ -173,30 +239,47 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
   __shared__ double2 buf[CAP];
+  __shared__ double2 tws[kTwCap];
+  constexpr int E = CAP / NT;
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
   const int n = I.nx, h = n / 2, K = h + 1;
   const int p0 = wk.a;
   const int np = min(I.row_pairs_per_block, I.ny / 2 - p0);
-  const double *R = dslot(I, a.r);
-  for (int idx = threadIdx.x; idx < np * n; idx += NT) {
-    const int p = idx / n, x = idx - p * n;
-    const long long ya = 2LL * (p0 + p);
-    buf[idx] = make_double2(R[ya * n + x], R[(ya + 1) * n + x]);
+  const int cnt = np * n;
+  const Gp<const double> R = dslot(I, a.r) + 2LL * p0 * n;
+  const Div dn(n);
+  TwStage<NT> tw;
+  tw.load(I.fx);
+  double ra[E], rb[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int o = idx + dn.q(idx) * n;  // row 2p, column x
+      ra[e] = R[o];
+      rb[e] = R[o + n];
+    }
+  }
+  tw.store(tws, I.fx);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) buf[idx] = make_double2(ra[e], rb[e]);
   }
   __syncthreads();
-  fft_lds<-1, false, CAP, NT>(buf, I.fx, np, 1, n);
-  double2 *S = reinterpret_cast<double2 *>(dslot(I, a.spec));
+  fft_lds<-1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
+  const Gp<dv2> S = cslot(I, a.spec) + 2LL * p0 * K;
+  const Div dk(K);
   for (int idx = threadIdx.x; idx < np * K; idx += NT) {
-    const int p = idx / K, k = idx - p * K;
+    const int p = dk.q(idx), k = idx - p * K;
     const double2 Z = buf[p * n + (k == h ? h : k)];
-    const double2 W = buf[p * n + ((n - k) % n)];  // Z[n-k]; its conjugate pairs with Z[k]
+    const double2 W = buf[p * n + (k == 0 ? 0 : n - k)];  // Z[n-k]; its conjugate pairs with Z[k]
     // A = (Z + conj W) / 2, B = (Z - conj W) / 2i: the spectra of the two real rows
     const double2 A = make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
     const double2 B = make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x));
-    const long long ya = 2LL * (p0 + p);
-    S[ya * K + k] = A;
-    S[(ya + 1) * K + k] = B;
+    stc(S + 2 * p * K + k, A);
+    stc(S + (2 * p + 1) * K + k, B);
   }
 }
 
@@ -205,6 +288,7 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
 // Tile of C columns of the spectrum: element j of column c at buf[j * es + c].
 constexpr int kColCap = 2048;
 constexpr int kColThreads = 256;
+constexpr int kColPer = kColCap / kColThreads;
 
 // A: length-n1 FFT over rows y = r + n2 m, m = 0..n1-1, for the C columns k0.. of the
 // tile; work item (inst, k0, r).
@@ -213,22 +297,49 @@ __global__ __launch_bounds__(kColThreads) void k_cols_a(const Inst *__restrict__
                                                         const Work *__restrict__ work,
                                                         int nwork, ArgsSolve a) {
   __shared__ double2 buf[kColCap];
+  __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
   const int K = I.nx / 2 + 1, n1 = I.f1.n, n2 = I.f2.n;
   const int k0 = wk.a, r = wk.b;
   const int C = min(I.cols_per_block, K - k0);
-  double2 *S = reinterpret_cast<double2 *>(dslot(I, a.spec));
-  for (int idx = threadIdx.x; idx < n1 * C; idx += kColThreads) {
-    const int m = idx / C, c = idx - m * C;
-    buf[idx] = S[(long long)(r + n2 * m) * K + k0 + c];
+  const int cnt = n1 * C;
+  const Gp<dv2> S = cslot(I, a.spec) + (long long)r * K + k0;
+  const long long stride = (long long)n2 * K;
+  const Div dc(C);
+  TwStage<kColThreads> tw;
+  tw.load(I.f1);
+  double2 v[kColPer];
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    if (idx < cnt) {
+      const int m = dc.q(idx), c = idx - m * C;
+      v[e] = ldc(S + m * stride + c);
+    }
+  }
+  tw.store(tws, I.f1);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    if (idx < cnt) buf[idx] = make_double2(v[e].x, v[e].y);
   }
   __syncthreads();
-  fft_lds<DIR, true, kColCap, kColThreads>(buf, I.f1, C, C, 1);
-  for (int idx = threadIdx.x; idx < n1 * C; idx += kColThreads) {
-    const int m = idx / C, c = idx - m * C;
-    S[(long long)(r + n2 * m) * K + k0 + c] = buf[idx];
+  fft_lds<DIR, true, kColCap, kColThreads>(buf, I.f1, C, C, 1, tws);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    if (idx < cnt) {
+      const int m = dc.q(idx), c = idx - m * C;
+      stc(S + m * stride + c, buf[idx]);
+    }
   }
+}
+
+// Divisor of mode (kx, ky): 1 / ((lambda_x + lambda_y - sigma) nx ny); the (0,0) mode is
+// replaced by theta_mean instead (flagged by a zero divisor slot).
+__device__ __forceinline__ double mode_scale(const Inst &I, double sig, int kx, int ky) {
+  return (kx == 0 && ky == 0) ? 0.0 : I.inv_nxny / (gp(I.lam_x)[kx] + gp(I.lam_y)[ky] - sig);
 }
 
 // B: for G groups k1 = g0.. of n2 contiguous rows n2 k1 + r: twiddle, length-n2 FFT,
@@ -237,6 +348,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
                                                         const Work *__restrict__ work, int nwork,
                                                         ArgsSolve a) {
   __shared__ double2 buf[kColCap];
+  __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
   const int K = I.nx / 2 + 1, n = I.ny, n1 = I.f1.n, n2 = I.f2.n;
@@ -244,38 +356,56 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
   const int C = min(I.cols_per_block, K - k0);
   const int G = min(I.groups_per_block, n1 - g0);
   const int GC = G * C;
-  double2 *S = reinterpret_cast<double2 *>(dslot(I, a.spec));
-  const double2 *twn = I.fy.tw;  // exp(-2 pi i m / ny)
-  for (int idx = threadIdx.x; idx < n2 * GC; idx += kColThreads) {
-    const int r = idx / GC, rem = idx - r * GC;
-    const int g = rem / C, c = rem - g * C;
-    const int k1 = g0 + g;
-    const double2 v = S[(long long)(n2 * k1 + r) * K + k0 + c];
-    buf[idx] = cmul(v, twn[(r * k1) % n]);
+  const int cnt = n2 * GC;
+  const Gp<dv2> S = cslot(I, a.spec) + k0;
+  const Gp<const dv2> twn = reinterpret_cast<Gp<const dv2>>(gp(I.fy.tw));  // exp(-2 pi i m / ny)
+  const double sig = I.sigma[a.stage];
+  const Div dgc(GC), dc(C), dn(n);
+  TwStage<kColThreads> tw;
+  tw.load(I.f2);
+  double2 v[kColPer], w[kColPer];
+  double d[kColPer];
+  int off[kColPer];
+  // element idx = (r, g, c): row n2 (g0 + g) + r of the spectrum before the n2-point FFT,
+  // mode ky = g0 + g + n1 r after it
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    off[e] = -1;
+    if (idx < cnt) {
+      const int r = dgc.q(idx), rem = idx - r * GC;
+      const int g = dc.q(rem), c = rem - g * C;
+      const int k1 = g0 + g;
+      off[e] = (n2 * k1 + r) * K + c;
+      v[e] = ldc(S + off[e]);
+      const int m = r * k1;
+      w[e] = ldc(twn + (m - dn.q(m) * n));
+      d[e] = mode_scale(I, sig, k0 + c, k1 + n1 * r);
+    }
   }
+  tw.store(tws, I.f2);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e)
+    if (off[e] >= 0) buf[threadIdx.x + e * kColThreads] = cmul(v[e], w[e]);
   __syncthreads();
-  fft_lds<-1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1);
-  const double sig = I.sigma[a.stage], s = I.inv_nxny;
-  for (int idx = threadIdx.x; idx < n2 * GC; idx += kColThreads) {
-    const int k2 = idx / GC, rem = idx - k2 * GC;
-    const int g = rem / C, c = rem - g * C;
-    const int ky = g0 + g + n1 * k2, kx = k0 + c;
-    if (kx == 0 && ky == 0) {
-      buf[idx] = make_double2(I.theta_mean, 0.0);
-    } else {
-      const double d = s / (I.lam_x[kx] + I.lam_y[ky] - sig);
-      buf[idx] = make_double2(buf[idx].x * d, buf[idx].y * d);
+  fft_lds<-1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1, tws);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    if (off[e] >= 0) {
+      const double2 z = buf[idx];
+      buf[idx] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
+                             : make_double2(z.x * d[e], z.y * d[e]);
     }
   }
   __syncthreads();
-  fft_lds<1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1);
-  for (int idx = threadIdx.x; idx < n2 * GC; idx += kColThreads) {
-    const int r = idx / GC, rem = idx - r * GC;
-    const int g = rem / C, c = rem - g * C;
-    const int k1 = g0 + g;
-    double2 w = twn[(r * k1) % n];
-    w.y = -w.y;
-    S[(long long)(n2 * k1 + r) * K + k0 + c] = cmul(buf[idx], w);
+  fft_lds<1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1, tws);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    if (off[e] >= 0) {
+      const double2 c = make_double2(w[e].x, -w[e].y);
+      stc(S + off[e], cmul(buf[threadIdx.x + e * kColThreads], c));
+    }
   }
 }
 
@@ -287,35 +417,52 @@ __global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restric
                                                            const Work *__restrict__ work,
                                                            int nwork, ArgsSolve a) {
   __shared__ double2 buf[kColCap];
+  __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
-  const int K = I.nx / 2 + 1, n = I.ny;
+  const int K = I.nx / 2 + 1;
   const int k0 = wk.a;
   const int C = min(I.cols_full_per_block, K - k0);
-  double2 *S = reinterpret_cast<double2 *>(dslot(I, a.spec));
-  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
-    const int y = idx / C, c = idx - y * C;
-    buf[idx] = S[(long long)y * K + k0 + c];
+  const int cnt = I.ny * C;
+  const Gp<dv2> S = cslot(I, a.spec) + k0;
+  const double sig = I.sigma[a.stage];
+  const Div dc(C);
+  TwStage<kColThreads> tw;
+  tw.load(I.fy);
+  double2 v[kColPer];
+  double d[kColPer];
+  int off[kColPer];
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    off[e] = -1;
+    if (idx < cnt) {
+      const int y = dc.q(idx), c = idx - y * C;
+      off[e] = y * K + c;
+      v[e] = ldc(S + off[e]);
+      d[e] = mode_scale(I, sig, k0 + c, y);
+    }
   }
+  tw.store(tws, I.fy);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e)
+    if (off[e] >= 0) buf[threadIdx.x + e * kColThreads] = make_double2(v[e].x, v[e].y);
   __syncthreads();
-  fft_lds<-1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1);
-  const double sig = I.sigma[a.stage], s = I.inv_nxny;
-  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
-    const int ky = idx / C, c = idx - ky * C;
-    const int kx = k0 + c;
-    if (kx == 0 && ky == 0) {
-      buf[idx] = make_double2(I.theta_mean, 0.0);
-    } else {
-      const double d = s / (I.lam_x[kx] + I.lam_y[ky] - sig);
-      buf[idx] = make_double2(buf[idx].x * d, buf[idx].y * d);
+  fft_lds<-1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e) {
+    const int idx = threadIdx.x + e * kColThreads;
+    if (off[e] >= 0) {
+      const double2 z = buf[idx];
+      buf[idx] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
+                             : make_double2(z.x * d[e], z.y * d[e]);
     }
   }
   __syncthreads();
-  fft_lds<1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1);
-  for (int idx = threadIdx.x; idx < n * C; idx += kColThreads) {
-    const int y = idx / C, c = idx - y * C;
-    S[(long long)y * K + k0 + c] = buf[idx];
-  }
+  fft_lds<1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
+#pragma unroll
+  for (int e = 0; e < kColPer; ++e)
+    if (off[e] >= 0) stc(S + off[e], buf[threadIdx.x + e * kColThreads]);
 }
 
 // ------------------------------------------------------------------ rows inverse
@@ -325,35 +472,63 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
   __shared__ double2 buf[CAP];
+  __shared__ double2 tws[kTwCap];
+  constexpr int E = CAP / (2 * NT);
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
   const int n = I.nx, h = n / 2, K = h + 1;
   const int p0 = wk.a;
   const int np = min(I.row_pairs_per_block, I.ny / 2 - p0);
-  const double2 *S = reinterpret_cast<const double2 *>(dslot(I, a.spec));
-  for (int idx = threadIdx.x; idx < np * h; idx += NT) {
-    const int p = idx / h, k = idx - p * h;
-    const long long ya = 2LL * (p0 + p);
-    const double2 A = S[ya * K + k], B = S[(ya + 1) * K + k];
-    if (k == 0) {
-      // kx = 0 and kx = nx/2 are real for a real row
-      const double2 AN = S[ya * K + h], BN = S[(ya + 1) * K + h];
-      buf[p * n] = make_double2(A.x, B.x);
-      buf[p * n + h] = make_double2(AN.x, BN.x);
-    } else {
-      buf[p * n + k] = make_double2(A.x - B.y, A.y + B.x);          // A + i B
-      buf[p * n + n - k] = make_double2(A.x + B.y, B.x - A.y);      // conj A + i conj B
+  const int cnt = np * h;
+  const Gp<const dv2> S = cslot(I, a.spec) + 2LL * p0 * K;
+  const Div dh(h);
+  TwStage<NT> tw;
+  tw.load(I.fx);
+  double2 A[E], B[E], AN, BN;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int p = dh.q(idx), k = idx - p * h;
+      A[e] = ldc(S + 2 * p * K + k);
+      B[e] = ldc(S + (2 * p + 1) * K + k);
     }
   }
+  // kx = nx/2 of pair p = threadIdx.x (np <= NT)
+  const int pn = threadIdx.x;
+  if (pn < np) {
+    AN = ldc(S + 2 * pn * K + h);
+    BN = ldc(S + (2 * pn + 1) * K + h);
+  }
+  tw.store(tws, I.fx);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int p = dh.q(idx), k = idx - p * h;
+      if (k == 0) {
+        // kx = 0 and kx = nx/2 are real for a real row
+        buf[p * n] = make_double2(A[e].x, B[e].x);
+      } else {
+        buf[p * n + k] = make_double2(A[e].x - B[e].y, A[e].y + B[e].x);      // A + i B
+        buf[p * n + n - k] = make_double2(A[e].x + B[e].y, B[e].x - A[e].y);  // conj A + i conj B
+      }
+    }
+  }
+  if (pn < np) buf[pn * n + h] = make_double2(AN.x, BN.x);
   __syncthreads();
-  fft_lds<1, false, CAP, NT>(buf, I.fx, np, 1, n);
-  double *T = dslot(I, a.out);
-  for (int idx = threadIdx.x; idx < np * n; idx += NT) {
-    const int p = idx / n, x = idx - p * n;
-    const long long ya = 2LL * (p0 + p);
-    const double2 z = buf[idx];
-    T[ya * n + x] = z.x;
-    T[(ya + 1) * n + x] = z.y;
+  fft_lds<1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
+  const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
+  const Div dn(n);
+#pragma unroll
+  for (int e = 0; e < 2 * E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < np * n) {
+      const int o = idx + dn.q(idx) * n;
+      const double2 z = buf[idx];
+      T[o] = z.x;
+      T[o + n] = z.y;
+    }
   }
 }
 

@@ -202,6 +202,22 @@ void twiddles(int n, double2 *out) {
   }
 }
 
+// Two-level table (see FftPlan): lo[b] = w^b for b < B, hi[a] = w^(a B), w = exp(-2 pi i / n).
+// Returns the number of entries; *lb receives log2 B.
+int twiddles2(int n, double2 *out, int *lb) {
+  int l = 0;
+  while ((1 << l) * (1 << l) < n) ++l;
+  const int B = 1 << l, nhi = (n + B - 1) / B;
+  const long double c = -2.0L * 3.141592653589793238462643383279502884L / n;
+  for (int b = 0; b < B; ++b) out[b] = make_double2((double)cosl(c * b), (double)sinl(c * b));
+  for (int a = 0; a < nhi; ++a) {
+    const long double t = c * ((long double)a * B);
+    out[B + a] = make_double2((double)cosl(t), (double)sinl(t));
+  }
+  *lb = l;
+  return B + nhi;
+}
+
 // Fourier symbol of the fourth-order central second difference on an n-point grid
 // with spacing h: (-2 cos 2 th + 32 cos th - 30) / (12 h^2), th = 2 pi k / n.
 double lap_symbol(int k, int n, double h) {
@@ -280,6 +296,7 @@ size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
   size_t b = align_up(L.ntrans * plane * tsize);
   b += align_up((L.ndbl * plane + 2 * (size_t)c.ny) * sizeof(double));  // spectrum tail
   b += align_up((size_t)(c.nx + c.ny + n1 + n2) * sizeof(double2));     // twiddles
+  b += align_up((size_t)4 * kTwCap * sizeof(double2));                 // two-level twiddles
   b += align_up((size_t)(c.nx / 2 + 1 + c.ny) * sizeof(double));        // symbols
   return b;
 }
@@ -911,6 +928,16 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.f2.n = n2;
     I.f2.npass = fft_radices(n2, I.f2.radix);
     I.f2.tw = tw + cf.nx + cf.ny + n1;
+    double2 *tw2 = reinterpret_cast<double2 *>(p);
+    p += align_up((size_t)4 * kTwCap * sizeof(double2));
+    Upload u3{reinterpret_cast<char *>(tw2), std::vector<char>(4 * kTwCap * sizeof(double2))};
+    double2 *htw2 = reinterpret_cast<double2 *>(u3.data.data());
+    FftPlan *plans[4] = {&I.fx, &I.fy, &I.f1, &I.f2};
+    for (int q = 0; q < 4; ++q) {
+      plans[q]->ntw = twiddles2(plans[q]->n, htw2 + q * kTwCap, &plans[q]->lb);
+      plans[q]->tw2 = tw2 + q * kTwCap;
+    }
+    uploads.push_back(std::move(u3));
     // symbols
     double *lam = reinterpret_cast<double *>(p);
     p += align_up((size_t)(cf.nx / 2 + 1 + cf.ny) * sizeof(double));

@@ -209,7 +209,7 @@ struct Stage {
   using Gm = Geo<TY>;
   static constexpr int IT = (Gm::PL + kStencilThreads - 1) / kStencilThreads;
   G v[NP][IT];
-  __device__ __forceinline__ void load(const G *const *plane, int nx, int ny, int x0, int y0) {
+  __device__ __forceinline__ void load(const Gp<const G> *plane, int nx, int ny, int x0, int y0) {
     const bool inner = x0 >= kHalo && x0 + kTileX + kHalo <= nx && y0 >= kHalo &&
                        y0 + TY + kHalo <= ny;
 #pragma unroll
@@ -301,11 +301,11 @@ __device__ __forceinline__ S cdxy(const S *p, int c, int W, S ihx12, S ihy12) {
 }
 
 template <typename T>
-__device__ __forceinline__ T *tplane(const Inst &I, int slot) {
-  return reinterpret_cast<T *>(I.tbase) + (long long)slot * I.plane;
+__device__ __forceinline__ Gp<T> tplane(const Inst &I, int slot) {
+  return gp(reinterpret_cast<T *>(I.tbase) + (long long)slot * I.plane);
 }
-__device__ __forceinline__ double *dplane(const Inst &I, int slot) {
-  return I.dbase + (long long)slot * I.plane;
+__device__ __forceinline__ Gp<double> dplane(const Inst &I, int slot) {
+  return gp(I.dbase + (long long)slot * I.plane);
 }
 
 // ------------------------------------------------------------------ step 2 RHS
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
   const Inst &I = insts[wk.inst];
   Stage<TY, 2, T> st;
   {
-    const T *g[2] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    const Gp<const T> g[2] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
     st.load(g, I.nx, I.ny, wk.a, wk.b);
   }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   const int nx = I.nx, ny = I.ny;
   {
     Stage<TY, 4, T> st;
-    const T *g[4] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0]),
+    const Gp<const T> g[4] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0]),
                      tplane<T>(I, a.partner[1])};
     st.load(g, nx, ny, wk.a, wk.b);
     T *l[4] = {sV1, sV2, sP1, sP2};
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   // div v without dissipation; theta (float64) loaded meanwhile into the partner planes
   Stage<TY, 1, double> sth;
   {
-    const double *g[1] = {dplane(I, a.th)};
+    const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
   faces<TY, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   const int nx = I.nx, ny = I.ny;
   {
     Stage<TY, 5, T> st;
-    const T *g[5] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1]), tplane<T>(I, a.q),
+    const Gp<const T> g[5] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1]), tplane<T>(I, a.q),
                      tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
     st.load(g, nx, ny, wk.a, wk.b);
     T *l[5] = {sU1, sU2, sQ, sV1, sV2};
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   // grad q with dissipation on v1 (x) and v2 (y); theta loaded meanwhile
   Stage<TY, 1, double> sth;
   if (want_lt) {
-    const double *g[1] = {dplane(I, a.th)};
+    const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
   faces<TY, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
