@@ -39,49 +39,53 @@ __device__ __forceinline__ int wrap(int g, int n) {
 }
 
 // WENO5 of Jiang and Shu, written through 3-cell windows.  For cells g_{k-1}, g_k,
-// g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and D = g_{k+1} - g_{k-1}.  With eps_w = 1e-6
-// and linear weights d = (1, 6, 3)/10, the left-biased reconstruction at face i+1/2 uses
-//   beta0 = 13/12 S^2 + 1/4 (2S + D)^2 on window i-1, beta1 = 13/12 S^2 + 1/4 D^2 on window
-//   i, beta2 = 13/12 S^2 + 1/4 (2S - D)^2 on window i+1,
-//   q0 = (2 g_{i-2} - 7 g_{i-1} + 11 g_i)/6, q1 = (-g_{i-1} + 5 g_i + 2 g_{i+1})/6,
-//   q2 = (2 g_i + 5 g_{i+1} - g_{i+2})/6,
-// weights alpha_k = d_k / (eps_w + beta_k)^2; the right-biased one is its mirror image.
-// These are the Jiang-Shu smoothness indicators and candidates rewritten in S and D
-// (a - 4b + 3c = 2S + D and 3c - 4d + e = 2S - D on the respective windows).
+// g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and h = (g_{k+1} - g_{k-1}) / 2.  The
+// Jiang-Shu smoothness indicators of the three sub-stencils of a reconstruction are
+//   beta0 = 13/12 S^2 + (S + h)^2 on window i-1, beta1 = 13/12 S^2 + h^2 on window i,
+//   beta2 = 13/12 S^2 + (S - h)^2 on window i+1
+// (for window i-1, a - 4b + 3c = 2(S + h); for window i+1, 3c - 4d + e = 2(S - h)).
+// A window carries e = eps_w + 13/12 S^2 (eps_w = 1e-6), S and h, so each indicator
+// term (eps_w + beta)^2 is one fused multiply-add and a square.  Candidates at face
+// i+1/2: q0 = (2 g_{i-2} - 7 g_{i-1} + 11 g_i)/6, q1 = (-g_{i-1} + 5 g_i + 2 g_{i+1})/6,
+// q2 = (2 g_i + 5 g_{i+1} - g_{i+2})/6, weights alpha_k = d_k / (eps_w + beta_k)^2 with
+// d = (1, 6, 3)/10; the right-biased reconstruction is the mirror image.
 
-struct Win {  // one window: 13/12 S^2, S, D
-  double a, s, d;
+template <typename T>
+struct Win {
+  T e, s, h;
 };
-struct WinF {
-  float a, s, d;
-};
-__device__ __forceinline__ Win win(double l, double c, double r) {
-  const double S = l - 2.0 * c + r;
-  return Win{(13.0 / 12.0) * S * S, S, r - l};
+template <typename T>
+__device__ __forceinline__ Win<T> win(T l, T c, T r) {
+  const T S = fma(T(-2), c, l + r);
+  return Win<T>{fma(T(13.0 / 12.0) * S, S, T(1e-6)), S, T(0.5) * (r - l)};
 }
-__device__ __forceinline__ WinF win(float l, float c, float r) {
-  const float S = l - 2.0f * c + r;
-  return WinF{(13.0f / 12.0f) * S * S, S, r - l};
-}
-template <typename W, typename T>
-__device__ __forceinline__ T sq_eps(T beta) {
-  const T x = T(1e-6) + beta;
+// (eps_w + beta_k)^2 of the three indicator forms of a window
+template <typename T>
+__device__ __forceinline__ T ind0(const Win<T> &w) {
+  const T t = w.s + w.h;
+  const T x = fma(t, t, w.e);
   return x * x;
 }
-// (eps_w + beta)^2 of the three indicator forms of a window
-template <typename W, typename T>
-__device__ __forceinline__ T ind0(const W &w) {
-  const T t = T(2) * w.s + w.d;
-  return sq_eps<W, T>(w.a + T(0.25) * t * t);
+template <typename T>
+__device__ __forceinline__ T ind1(const Win<T> &w) {
+  const T x = fma(w.h, w.h, w.e);
+  return x * x;
 }
-template <typename W, typename T>
-__device__ __forceinline__ T ind1(const W &w) {
-  return sq_eps<W, T>(w.a + T(0.25) * w.d * w.d);
+template <typename T>
+__device__ __forceinline__ T ind2(const Win<T> &w) {
+  const T t = w.s - w.h;
+  const T x = fma(t, t, w.e);
+  return x * x;
 }
-template <typename W, typename T>
-__device__ __forceinline__ T ind2(const W &w) {
-  const T t = T(2) * w.s - w.d;
-  return sq_eps<W, T>(w.a + T(0.25) * t * t);
+// Candidates: the window (a, b, c) evaluated one and a half cells right of b, and the
+// window centred on c evaluated half a cell towards d.
+template <typename T>
+__device__ __forceinline__ T cfar(T a, T b, T c) {
+  return fma(T(1.0 / 3.0), a, fma(T(-7.0 / 6.0), b, T(11.0 / 6.0) * c));
+}
+template <typename T>
+__device__ __forceinline__ T cnear(T b, T c, T d) {
+  return fma(T(-1.0 / 6.0), b, fma(T(5.0 / 6.0), c, T(1.0 / 3.0) * d));
 }
 
 // float64 quotient through the hardware reciprocal refined by Newton steps.
@@ -94,56 +98,46 @@ __device__ __forceinline__ double qdiv(double n, double d) {
 }
 
 // Numerator and denominator of one reconstruction: weights proportional to
-// d_k / s_k with s_k = (eps_w + beta_k)^2, normalised through products of the others
-// (float64), or through reciprocals (float, where products could overflow).
+// d_k / s_k with s_k = (eps_w + beta_k)^2, normalised through products of the other two
+// (float64; the common factor 10 / (s0 s1 s2) cancels), or through reciprocals (float,
+// where the products could overflow).
 __device__ __forceinline__ void nd(double s0, double s1, double s2, double q0, double q1,
                                    double q2, double &n, double &den) {
-  const double w0 = 0.1 * s1 * s2, w1 = 0.6 * s0 * s2, w2 = 0.3 * s0 * s1;
-  n = w0 * q0 + w1 * q1 + w2 * q2;
+  const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
+  n = fma(w0, q0, fma(w1, q1, w2 * q2));
   den = w0 + w1 + w2;
 }
 __device__ __forceinline__ void nd(float s0, float s1, float s2, float q0, float q1, float q2,
                                    float &n, float &den) {
   const float w0 = 0.1f * __builtin_amdgcn_rcpf(s0), w1 = 0.6f * __builtin_amdgcn_rcpf(s1),
               w2 = 0.3f * __builtin_amdgcn_rcpf(s2);
-  n = w0 * q0 + w1 * q1 + w2 * q2;
+  n = fma(w0, q0, fma(w1, q1, w2 * q2));
   den = w0 + w1 + w2;
 }
 // n+/d+ + n-/d- with one division
 __device__ __forceinline__ double sum2(double np, double dp, double nm, double dm) {
-  return qdiv(np * dm + nm * dp, dp * dm);
+  return qdiv(fma(np, dm, nm * dp), dp * dm);
 }
 __device__ __forceinline__ float sum2(float np, float dp, float nm, float dm) {
-  return (np * dm + nm * dp) * __builtin_amdgcn_rcpf(dp * dm);
+  return fma(np, dm, nm * dp) * __builtin_amdgcn_rcpf(dp * dm);
 }
-
-template <typename T>
-struct WinOf;
-template <>
-struct WinOf<double> {
-  using type = Win;
-};
-template <>
-struct WinOf<float> {
-  using type = WinF;
-};
 
 // Face between cells c2 and c3 of six consecutive values c0..c5 of one function g:
 // left-biased reconstruction plus right-biased reconstruction of the same g (the
 // Lax-Friedrichs split without dissipation, g = f/2).  The two share windows i and i+1
-// and two candidates.
+// and two candidates.  Every operation commutes exactly with negation, so the flux of
+// -g is the negated flux of g.
 template <typename T>
 __device__ __forceinline__ T flux_sym(T c0, T c1, T c2, T c3, T c4, T c5) {
-  using W = typename WinOf<T>::type;
-  const W wa = win(c0, c1, c2), wb = win(c1, c2, c3), wc = win(c2, c3, c4), wd = win(c3, c4, c5);
-  const T sixth = T(1.0 / 6.0);
-  const T M = (-c1 + T(5) * c2 + T(2) * c3) * sixth;  // window i at i+1/2
-  const T N = (T(2) * c2 + T(5) * c3 - c4) * sixth;   // window i+1 at i+1/2
-  const T P = (T(2) * c0 - T(7) * c1 + T(11) * c2) * sixth;
-  const T Pm = (T(2) * c5 - T(7) * c4 + T(11) * c3) * sixth;
+  const Win<T> wa = win(c0, c1, c2), wb = win(c1, c2, c3), wc = win(c2, c3, c4),
+               wd = win(c3, c4, c5);
+  const T M = cnear(c1, c2, c3);  // window i at i+1/2
+  const T N = cnear(c4, c3, c2);  // window i+1 at i+1/2
+  const T P = cfar(c0, c1, c2);
+  const T Pm = cfar(c5, c4, c3);
   T np, dp, nm, dm;
-  nd(ind0<W, T>(wa), ind1<W, T>(wb), ind2<W, T>(wc), P, M, N, np, dp);
-  nd(ind2<W, T>(wd), ind1<W, T>(wc), ind0<W, T>(wb), Pm, N, M, nm, dm);
+  nd(ind0(wa), ind1(wb), ind2(wc), P, M, N, np, dp);
+  nd(ind2(wd), ind1(wc), ind0(wb), Pm, N, M, nm, dm);
   return sum2(np, dp, nm, dm);
 }
 
@@ -151,40 +145,39 @@ __device__ __forceinline__ T flux_sym(T c0, T c1, T c2, T c3, T c4, T c5) {
 // f + w and f - w of a dissipative Lax-Friedrichs flux (inputs already halved).
 template <typename T>
 __device__ __forceinline__ T flux_lf(const T *p, const T *m) {
-  using W = typename WinOf<T>::type;
-  const T sixth = T(1.0 / 6.0);
-  const W pa = win(p[0], p[1], p[2]), pb = win(p[1], p[2], p[3]), pc = win(p[2], p[3], p[4]);
-  const T q0 = (T(2) * p[0] - T(7) * p[1] + T(11) * p[2]) * sixth;
-  const T q1 = (-p[1] + T(5) * p[2] + T(2) * p[3]) * sixth;
-  const T q2 = (T(2) * p[2] + T(5) * p[3] - p[4]) * sixth;
-  const W mb = win(m[1], m[2], m[3]), mc = win(m[2], m[3], m[4]), md = win(m[3], m[4], m[5]);
-  const T r0 = (T(2) * m[5] - T(7) * m[4] + T(11) * m[3]) * sixth;
-  const T r1 = (T(2) * m[2] + T(5) * m[3] - m[4]) * sixth;
-  const T r2 = (-m[1] + T(5) * m[2] + T(2) * m[3]) * sixth;
+  const Win<T> pa = win(p[0], p[1], p[2]), pb = win(p[1], p[2], p[3]), pc = win(p[2], p[3], p[4]);
+  const T q0 = cfar(p[0], p[1], p[2]);
+  const T q1 = cnear(p[1], p[2], p[3]);
+  const T q2 = cnear(p[4], p[3], p[2]);
+  const Win<T> mb = win(m[1], m[2], m[3]), mc = win(m[2], m[3], m[4]), md = win(m[3], m[4], m[5]);
+  const T r0 = cfar(m[5], m[4], m[3]);
+  const T r1 = cnear(m[4], m[3], m[2]);
+  const T r2 = cnear(m[1], m[2], m[3]);
   T np, dp, nm, dm;
-  nd(ind0<W, T>(pa), ind1<W, T>(pb), ind2<W, T>(pc), q0, q1, q2, np, dp);
-  nd(ind2<W, T>(md), ind1<W, T>(mc), ind0<W, T>(mb), r0, r1, r2, nm, dm);
+  nd(ind0(pa), ind1(pb), ind2(pc), q0, q1, q2, np, dp);
+  nd(ind2(md), ind1(mc), ind0(mb), r0, r1, r2, nm, dm);
   return sum2(np, dp, nm, dm);
 }
 
 // Numerical flux at the face between cells k = 2 and k = 3 of six consecutive cells
 // (stride apart in LDS).  f and w are staged halved, so f+ = sf f + w and
 // f- = sf f - w are the Lax-Friedrichs split fluxes (sf f +- alpha w)/2 with alpha = 1
-// (DISS) or alpha = 0: left-biased WENO5 of f+ plus right-biased WENO5 of f-.
+// (DISS) or alpha = 0: left-biased WENO5 of f+ plus right-biased WENO5 of f-.  sf is
+// +1 or -1.
 template <typename T, bool DISS>
 __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf) {
   if (DISS) {
     T p[6], m[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const T fk = sf * f[k * stride], wk = w[k * stride];
-      p[k] = fk + wk;
-      m[k] = fk - wk;
+      const T fk = f[k * stride], wk = w[k * stride];
+      p[k] = fma(sf, fk, wk);
+      m[k] = fma(sf, fk, -wk);
     }
     return flux_lf(p, m);
   }
-  return flux_sym(sf * f[0], sf * f[stride], sf * f[2 * stride], sf * f[3 * stride],
-                  sf * f[4 * stride], sf * f[5 * stride]);
+  return sf * flux_sym(f[0], f[stride], f[2 * stride], f[3 * stride], f[4 * stride],
+                       f[5 * stride]);
 }
 
 // LDS tile geometry for a 64 x TY tile with a 3-cell halo.
