@@ -21,6 +21,9 @@ reading used here:
     component) and u2 (second component) for div B(v) in the u equations.
   * Fourth-order central first derivative D, second derivative L, mixed derivative
     D_x D_y.
+Third-order variant (Section 4.1 convergence tables, "third order WENO"): WENO3 of
+Jiang and Shu (two two-cell candidates, linear weights 1/3 and 2/3) on the same split
+fluxes, used with the second-order central differences of the printed template.
 Pins (tests/test_operators.py): polynomial exactness of the WENO candidates and of
 the linear-weight reconstruction, order of accuracy, Fourier symbols of the central
 operators, first-order limit equal to the printed Lax-Friedrichs flux.
@@ -50,16 +53,33 @@ def weno5_face(a, b, c, d, e, eps_w=WENO_EPS):
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
 
 
+def weno3_face(a, b, c, eps_w=WENO_EPS):
+    """WENO3 value at the right face of cell b from the three cells a, b, c centred on b
+    (left-biased; Jiang and Shu with r = 2): candidates (3b - a)/2 on {a, b} and
+    (b + c)/2 on {b, c}, smoothness indicators (b - a)^2 and (c - b)^2, linear weights
+    1/3 and 2/3, weights proportional to d_k / (eps_w + beta_k)^2."""
+    q0 = (3.0 * b - a) / 2.0
+    q1 = (b + c) / 2.0
+    a0 = (1.0 / 3.0) / (eps_w + (b - a) ** 2) ** 2
+    a1 = (2.0 / 3.0) / (eps_w + (c - b) ** 2) ** 2
+    return (a0 * q0 + a1 * q1) / (a0 + a1)
+
+
 def _shift(f, k, axis):
     """g[i] = f[i + k] along axis (periodic)."""
     return np.roll(f, -k, axis=axis)
 
 
-def weno_flux(f, w, alpha, axis, eps_w=WENO_EPS):
+def weno_flux(f, w, alpha, axis, eps_w=WENO_EPS, order=5):
     """Numerical flux at faces i+1/2 along axis for flux values f with
-    Lax-Friedrichs dissipation alpha on the variable w."""
+    Lax-Friedrichs dissipation alpha on the variable w: left-biased WENO (order 5 or 3)
+    of f+ plus its mirror image, right-biased, of f-."""
     fp = 0.5 * (f + alpha * w)
     fm = 0.5 * (f - alpha * w)
+    if order == 3:
+        plus = weno3_face(_shift(fp, -1, axis), fp, _shift(fp, 1, axis), eps_w)
+        minus = weno3_face(_shift(fm, 2, axis), _shift(fm, 1, axis), fm, eps_w)
+        return plus + minus
     plus = weno5_face(_shift(fp, -2, axis), _shift(fp, -1, axis), fp,
                       _shift(fp, 1, axis), _shift(fp, 2, axis), eps_w)
     minus = weno5_face(_shift(fm, 3, axis), _shift(fm, 2, axis), _shift(fm, 1, axis),
@@ -67,9 +87,9 @@ def weno_flux(f, w, alpha, axis, eps_w=WENO_EPS):
     return plus + minus
 
 
-def weno_derivative(f, w, alpha, axis, h, eps_w=WENO_EPS):
+def weno_derivative(f, w, alpha, axis, h, eps_w=WENO_EPS, order=5):
     """(fhat_{i+1/2} - fhat_{i-1/2}) / h along axis."""
-    fh = weno_flux(f, w, alpha, axis, eps_w)
+    fh = weno_flux(f, w, alpha, axis, eps_w, order)
     return (fh - _shift(fh, -1, axis)) / h
 
 
@@ -128,21 +148,24 @@ AX_X, AX_Y = 1, 0
 
 
 class Production:
-    """Operators of the high-order scheme (WENO5 + fourth-order central)."""
+    """Operators of the scheme: WENO5 + fourth-order central differences (the
+    high-order extension), or the narrower WENO3 + second-order central differences the
+    paper's convergence tables use (weno_order, central_order)."""
 
-    def __init__(self, hx, hy, alpha=1.0, central_order=4, eps_w=WENO_EPS):
+    def __init__(self, hx, hy, alpha=1.0, central_order=4, eps_w=WENO_EPS, weno_order=5):
         self.hx, self.hy, self.alpha = hx, hy, alpha
         self.co = central_order
         self.eps_w = eps_w
+        self.wo = weno_order
 
     # W^0 / W^1 directional flux derivatives
     def _w0(self, f, axis):
         h = self.hx if axis == AX_X else self.hy
-        return weno_derivative(f, 0.0 * f, 0.0, axis, h, self.eps_w)
+        return weno_derivative(f, 0.0 * f, 0.0, axis, h, self.eps_w, self.wo)
 
     def _w1(self, f, w, axis):
         h = self.hx if axis == AX_X else self.hy
-        return weno_derivative(f, w, self.alpha, axis, h, self.eps_w)
+        return weno_derivative(f, w, self.alpha, axis, h, self.eps_w, self.wo)
 
     def div0_B(self, u1, u2):
         """D0_LF . B(u) -> WENO without dissipation: rows of B(u) = [[-u1, u2],[u2, u1]]."""
