@@ -77,6 +77,13 @@ typedef enum {
  * |u| of the fields given to apdvm_set_fields (the derivation happens there), and 1
  * the Lax-Friedrichs dissipation speed (alpha = 1, Section 3.2), whose jump term acts
  * explicitly.
+ *
+ * Space discretisation (Section 3.2): weno_order 5 (or 0) reconstructs every
+ * Lax-Friedrichs flux with fifth-order WENO (Jiang-Shu), 3 with the third-order WENO of
+ * the convergence tables of Section 4.1; central_order 4 (or 0) uses fourth-order
+ * central differences for D0.u, D0 theta, D0^2:B(v) and D_Delta (and the matching
+ * Fourier symbol in the Helmholtz solve), 2 the second-order ones printed in Section
+ * 3.2.  Both must be the same for every instance of a context; else APDVM_ERR_ARG.
  */
 typedef struct {
   int32_t nx, ny;
@@ -88,6 +95,7 @@ typedef struct {
   const double *a_ex, *b_ex, *a_im, *b_im;
   double dt, cfl, c_visc;
   int32_t precision; /* apdvm_precision; must be the same for every instance */
+  int32_t weno_order, central_order; /* 5 / 4 (0 = default) or 3 / 2 */
 } apdvm_config;
 
 typedef struct apdvm_ctx apdvm_ctx;

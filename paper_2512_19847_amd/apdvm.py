@@ -45,7 +45,7 @@ class Config(ctypes.Structure):
                 ("s", c_int32), ("a_ex", POINTER(c_double)), ("b_ex", POINTER(c_double)),
                 ("a_im", POINTER(c_double)), ("b_im", POINTER(c_double)),
                 ("dt", c_double), ("cfl", c_double), ("c_visc", c_double),
-                ("precision", c_int32)]
+                ("precision", c_int32), ("weno_order", c_int32), ("central_order", c_int32)]
 
 
 def _tableaux():
@@ -144,7 +144,8 @@ def _dptr(a):
 
 
 def make_config(nx, ny=None, eps=1.0, mach=0.1, tau=-1.0, tableau="ars443", dt=0.0,
-                lx=2 * np.pi, ly=2 * np.pi, cfl=0.4, c_visc=0.2, precision=FP64, keep=None):
+                lx=2 * np.pi, ly=2 * np.pi, cfl=0.4, c_visc=0.2, precision=FP64, keep=None,
+                weno_order=5, central_order=4):
     """A Config for one instance.  keep: list that receives the numpy arrays the
     Config points to (they must stay alive until the C call that reads them)."""
     ny = nx if ny is None else ny
@@ -160,6 +161,7 @@ def make_config(nx, ny=None, eps=1.0, mach=0.1, tau=-1.0, tableau="ars443", dt=0
     cfg.a_ex, cfg.b_ex, cfg.a_im, cfg.b_im = _dptr(At), _dptr(bt), _dptr(A), _dptr(b)
     cfg.dt, cfg.cfl, cfg.c_visc = float(dt), float(cfl), float(c_visc)
     cfg.precision = int(precision)
+    cfg.weno_order, cfg.central_order = int(weno_order), int(central_order)
     return cfg
 
 
@@ -174,9 +176,11 @@ class Simulation:
     """A context of one or more instances stepped together.
 
     cases: list of dicts with keys nx, ny, eps, tau (or mach), dt, and optionally lx,
-    ly, cfl, c_visc.  All instances share the tableau and the precision."""
+    ly, cfl, c_visc.  All instances share the tableau, the precision and the space
+    discretisation (weno_order 5 or 3, central_order 4 or 2)."""
 
-    def __init__(self, cases, tableau="ars443", precision=FP64, device=0, stream=None):
+    def __init__(self, cases, tableau="ars443", precision=FP64, device=0, stream=None,
+                 weno_order=5, central_order=4):
         import torch
 
         if not torch.cuda.is_available():
@@ -191,7 +195,8 @@ class Simulation:
                                     tau=c.get("tau", -1.0), tableau=tableau, dt=c.get("dt", 0.0),
                                     lx=c.get("lx", 2 * np.pi), ly=c.get("ly", 2 * np.pi),
                                     cfl=c.get("cfl", 0.4), c_visc=c.get("c_visc", 0.2),
-                                    precision=precision, keep=keep))
+                                    precision=precision, keep=keep, weno_order=weno_order,
+                                    central_order=central_order))
         self.n = len(cfgs)
         self.shapes = [(c.ny, c.nx) for c in cfgs]
         nbytes = workspace_bytes(cfgs)

@@ -15,13 +15,16 @@
 
 namespace apdvm {
 
+// Stencil launches: tile height, WENO order (5 or 3), central-difference order (4 or 2).
 template <typename T>
-hipError_t launch_helmholtz_rhs(int, const Inst *, const Work *, int, const ArgsR &, hipStream_t);
+hipError_t launch_helmholtz_rhs(int, int, int, const Inst *, const Work *, int, const ArgsR &,
+                                hipStream_t);
 template <typename T>
-hipError_t launch_update_uq(int, const Inst *, const Work *, int, const ArgsUQ &, hipStream_t);
+hipError_t launch_update_uq(int, int, int, const Inst *, const Work *, int, const ArgsUQ &,
+                            hipStream_t);
 template <typename T>
-hipError_t launch_stage_terms(int, const Inst *, const Work *, int, const ArgsE &, const ArgsV &,
-                              hipStream_t);
+hipError_t launch_stage_terms(int, int, int, const Inst *, const Work *, int, const ArgsE &,
+                              const ArgsV &, hipStream_t);
 
 // Tile heights the stencil kernels are built for; the autotuner picks one per class.
 constexpr int kTileRows[2] = {8, 16};
@@ -108,8 +111,13 @@ apdvm_status check_physics(const apdvm_config &c) {
       return APDVM_ERR_ARG;
   }
   if (c.precision != APDVM_FP64 && c.precision != APDVM_FP32_SPLIT) return APDVM_ERR_ARG;
+  if (c.weno_order != 0 && c.weno_order != 3 && c.weno_order != 5) return APDVM_ERR_ARG;
+  if (c.central_order != 0 && c.central_order != 2 && c.central_order != 4) return APDVM_ERR_ARG;
   return APDVM_OK;
 }
+
+int weno_order_of(const apdvm_config &c) { return c.weno_order == 3 ? 3 : 5; }
+int central_order_of(const apdvm_config &c) { return c.central_order == 2 ? 2 : 4; }
 
 bool same_tableau(const apdvm_config &a, const apdvm_config &b) {
   if (a.s != b.s || a.precision != b.precision) return false;
@@ -129,6 +137,9 @@ apdvm_status validate(int n, const apdvm_config *cfgs) {
     if ((st = check_tableau(cfgs[k])) != APDVM_OK) return st;
     if ((st = check_physics(cfgs[k])) != APDVM_OK) return st;
     if (k > 0 && !same_tableau(cfgs[0], cfgs[k])) return APDVM_ERR_ARG;
+    if (weno_order_of(cfgs[k]) != weno_order_of(cfgs[0]) ||
+        central_order_of(cfgs[k]) != central_order_of(cfgs[0]))
+      return APDVM_ERR_ARG;
   }
   return APDVM_OK;
 }
@@ -218,9 +229,14 @@ int twiddles2(int n, double2 *out, int *lb) {
   return B + nhi;
 }
 
-// Fourier symbol of the fourth-order central second difference on an n-point grid
-// with spacing h: (-2 cos 2 th + 32 cos th - 30) / (12 h^2), th = 2 pi k / n.
-double lap_symbol(int k, int n, double h) {
+// Fourier symbol of the central second difference on an n-point grid with spacing h,
+// th = 2 pi k / n: (-2 cos 2 th + 32 cos th - 30) / (12 h^2) for the fourth-order one.
+double lap_symbol(int k, int n, double h, int order) {
+  if (order == 2) {
+    // (2 cos th - 2) / h^2 of the second-order central second difference
+    const long double th = 2.0L * 3.141592653589793238462643383279502884L * k / n;
+    return (double)((2.0L * cosl(th) - 2.0L) / ((long double)h * h));
+  }
   const long double th = 2.0L * 3.141592653589793238462643383279502884L * k / n;
   return (double)((-2.0L * cosl(2.0L * th) + 32.0L * cosl(th) - 30.0L) / (12.0L * h * h));
 }
@@ -369,6 +385,7 @@ struct apdvm_ctx {
   bool col_full_ok = false;  // every instance has columns short enough for one pass
   bool big_rows = false;
   int ty_index[apdvm::kNumClasses];  // tile table used by each stencil class
+  int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
   std::vector<int> tile_first, tile_count;
   double *d_partials = nullptr;
@@ -584,7 +601,8 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
   Work *tiles = c->d_tiles[ti];
   const int nt = c->ntiles[ti];
   switch (l.cls) {
-    case kHelmRhs: return launch_helmholtz_rhs<T>(ty, c->d_inst, tiles, nt, l.r, st);
+    case kHelmRhs:
+      return launch_helmholtz_rhs<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.r, st);
     case kColsFull:
       return launch_solve_part(5, c->big_rows, c->d_inst, c->d_rows, c->nrows, c->d_colf,
                                c->ncolf, c->d_colb, c->ncolb, l.sv, st);
@@ -595,8 +613,10 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
     case kRowsInv:
       return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
                                c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
-    case kUpdateUQ: return launch_update_uq<T>(ty, c->d_inst, tiles, nt, l.uq, st);
-    default: return launch_stage_terms<T>(ty, c->d_inst, tiles, nt, l.e, l.v, st);
+    case kUpdateUQ:
+      return launch_update_uq<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st);
+    default:
+      return launch_stage_terms<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st);
   }
 }
 
@@ -876,6 +896,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
   c->big_rows = big_rows(n, cfgs);
   for (int k = 0; k < kNumClasses; ++k) c->ty_index[k] = 1;
+  c->wo = weno_order_of(cfgs[0]);
+  c->co = central_order_of(cfgs[0]);
   std::vector<Work> tiles8;
   char *p = c->ws;
   c->d_inst = reinterpret_cast<Inst *>(p);
@@ -944,8 +966,10 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     Upload u2{reinterpret_cast<char *>(lam),
               std::vector<char>((cf.nx / 2 + 1 + cf.ny) * sizeof(double))};
     double *hl = reinterpret_cast<double *>(u2.data.data());
-    for (int kx = 0; kx <= cf.nx / 2; ++kx) hl[kx] = lap_symbol(kx, cf.nx, cf.lx / cf.nx);
-    for (int ky = 0; ky < cf.ny; ++ky) hl[cf.nx / 2 + 1 + ky] = lap_symbol(ky, cf.ny, cf.ly / cf.ny);
+    const int co = central_order_of(cf);
+    for (int kx = 0; kx <= cf.nx / 2; ++kx) hl[kx] = lap_symbol(kx, cf.nx, cf.lx / cf.nx, co);
+    for (int ky = 0; ky < cf.ny; ++ky)
+      hl[cf.nx / 2 + 1 + ky] = lap_symbol(ky, cf.ny, cf.ly / cf.ny, co);
     uploads.push_back(std::move(u2));
     I.lam_x = lam;
     I.lam_y = lam + cf.nx / 2 + 1;
@@ -1300,7 +1324,7 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
   k << "gfx950 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
-    << " cells=" << (long long)c->cells;
+    << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
   k << " maxnx=" << mx;

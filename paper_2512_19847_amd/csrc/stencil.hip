@@ -159,25 +159,74 @@ __device__ __forceinline__ T flux_lf(const T *p, const T *m) {
   return sum2(np, dp, nm, dm);
 }
 
+// WENO3 of Jiang and Shu (r = 2) for the convergence tables of Section 4.1: at face
+// i+1/2 the left-biased value combines (3 g_i - g_{i-1})/2 and (g_i + g_{i+1})/2 with
+// linear weights 1/3 and 2/3 and indicators (g_i - g_{i-1})^2 and (g_{i+1} - g_i)^2;
+// multiplied through by 3 (eps_w + beta_0)^2 (eps_w + beta_1)^2 the weights become
+// s1 and 2 s0 with s_k = (eps_w + beta_k)^2 (float: reciprocals, as for WENO5).
+template <typename T>
+__device__ __forceinline__ T sq3(T d) {
+  const T x = fma(d, d, T(1e-6));
+  return x * x;
+}
+__device__ __forceinline__ void nd3(double s0, double s1, double q0, double q1, double &n,
+                                    double &den) {
+  const double w1 = 2.0 * s0;
+  n = fma(s1, q0, w1 * q1);
+  den = s1 + w1;
+}
+__device__ __forceinline__ void nd3(float s0, float s1, float q0, float q1, float &n,
+                                    float &den) {
+  const float w0 = (1.0f / 3.0f) * __builtin_amdgcn_rcpf(s0),
+              w1 = (2.0f / 3.0f) * __builtin_amdgcn_rcpf(s1);
+  n = fma(w0, q0, w1 * q1);
+  den = w0 + w1;
+}
+// Face between cells c2 and c3 of g (c1..c4 used): left- plus right-biased WENO3; the
+// two share the candidate (c2 + c3)/2 and the indicator (c3 - c2)^2.
+template <typename T>
+__device__ __forceinline__ T flux3_sym(T c1, T c2, T c3, T c4) {
+  const T mid = T(0.5) * (c2 + c3);
+  const T sm = sq3(c3 - c2);
+  T np, dp, nm, dm;
+  nd3(sq3(c2 - c1), sm, fma(T(1.5), c2, T(-0.5) * c1), mid, np, dp);
+  nd3(sq3(c3 - c4), sm, fma(T(1.5), c3, T(-0.5) * c4), mid, nm, dm);
+  return sum2(np, dp, nm, dm);
+}
+// Same face for the split fluxes p (left-biased) and m (right-biased).
+template <typename T>
+__device__ __forceinline__ T flux3_lf(const T *p, const T *m) {
+  T np, dp, nm, dm;
+  nd3(sq3(p[2] - p[1]), sq3(p[3] - p[2]), fma(T(1.5), p[2], T(-0.5) * p[1]),
+      T(0.5) * (p[2] + p[3]), np, dp);
+  nd3(sq3(m[3] - m[4]), sq3(m[2] - m[3]), fma(T(1.5), m[3], T(-0.5) * m[4]),
+      T(0.5) * (m[3] + m[2]), nm, dm);
+  return sum2(np, dp, nm, dm);
+}
+
 // Numerical flux at the face between cells k = 2 and k = 3 of six consecutive cells
 // (stride apart in LDS).  f and w are staged halved, so f+ = sf f + w and
 // f- = sf f - w are the Lax-Friedrichs split fluxes (sf f +- alpha w)/2 with alpha = 1
-// (DISS) or alpha = 0: left-biased WENO5 of f+ plus right-biased WENO5 of f-.  sf is
-// +1 or -1.
-template <typename T, bool DISS>
+// (DISS) or alpha = 0: left-biased WENO of f+ plus right-biased WENO of f- (order WO,
+// 5 or 3; WENO3 reads cells 1..4 only).  sf is +1 or -1.
+template <typename T, bool DISS, int WO>
 __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf) {
+  constexpr int K0 = WO == 5 ? 0 : 1, K1 = WO == 5 ? 6 : 5;
   if (DISS) {
     T p[6], m[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = K0; k < K1; ++k) {
       const T fk = f[k * stride], wk = w[k * stride];
       p[k] = fma(sf, fk, wk);
       m[k] = fma(sf, fk, -wk);
     }
-    return flux_lf(p, m);
+    if (WO == 5) return flux_lf(p, m);
+    return flux3_lf(p, m);
   }
-  return sf * flux_sym(f[0], f[stride], f[2 * stride], f[3 * stride], f[4 * stride],
-                       f[5 * stride]);
+  if (WO == 5)
+    return sf * flux_sym(f[0], f[stride], f[2 * stride], f[3 * stride], f[4 * stride],
+                         f[5 * stride]);
+  return sf * flux3_sym(f[stride], f[2 * stride], f[3 * stride], f[4 * stride]);
 }
 
 // LDS tile geometry for a 64 x TY tile with a 3-cell halo.
@@ -234,7 +283,7 @@ struct Stage {
 
 // x faces (TY rows x 65) and y faces (TY + 1 rows x 64) of two fluxes in one index
 // space; the x part is padded to whole wavefronts so no wavefront mixes the two.
-template <int TY, typename T, bool DX, bool DY>
+template <int TY, int WO, typename T, bool DX, bool DY>
 __device__ __forceinline__ void faces(T *fx, T *fy, const T *fxf, const T *fxw, T sx,
                                       const T *fyf, const T *fyw, T sy) {
   using Gm = Geo<TY>;
@@ -244,14 +293,14 @@ __device__ __forceinline__ void faces(T *fx, T *fy, const T *fxf, const T *fxw, 
         const int ly = idx / (kTileX + 1);
         const int f = idx - ly * (kTileX + 1);
         const int base = (ly + kHalo) * Gm::W + f;  // cell f - 3 of row ly
-        fx[idx] = face_flux<T, DX>(fxf + base, fxw + base, 1, sx);
+        fx[idx] = face_flux<T, DX, WO>(fxf + base, fxw + base, 1, sx);
       }
     } else {
       const int j = idx - Gm::FXP;
       const int f = j / kTileX;
       const int lx = j - f * kTileX;
       const int base = f * Gm::W + lx + kHalo;  // cell f - 3 of column lx
-      fy[j] = face_flux<T, DY>(fyf + base, fyw + base, Gm::W, sy);
+      fy[j] = face_flux<T, DY, WO>(fyf + base, fyw + base, Gm::W, sy);
     }
   }
 }
@@ -265,33 +314,63 @@ __device__ __forceinline__ T face_dy(const T *fy, int lx, int ly, T ihy) {
   return (fy[(ly + 1) * kTileX + lx] - fy[ly * kTileX + lx]) * ihy;
 }
 
-// Fourth-order central first and second derivatives from an LDS plane at index c
-// (stride 1 for x, W for y): D f = (f-2 - 8 f-1 + 8 f+1 - f+2) / (12 h),
-// L f = (-f-2 + 16 f-1 - 30 f0 + 16 f+1 - f+2) / (12 h^2).
-template <typename S>
-__device__ __forceinline__ S cd1(const S *p, int c, int st, S ih12) {
-  return (p[c - 2 * st] - S(8) * p[c - st] + S(8) * p[c + st] - p[c + 2 * st]) * ih12;
-}
-template <typename S>
-__device__ __forceinline__ S cd2(const S *p, int c, int st, S ih2_12) {
-  return (-p[c - 2 * st] + S(16) * p[c - st] - S(30) * p[c] + S(16) * p[c + st] - p[c + 2 * st]) *
-         ih2_12;
-}
-// D_x D_y f
-template <typename S>
-__device__ __forceinline__ S cdxy(const S *p, int c, int W, S ihx12, S ihy12) {
-  const int o[4] = {-2, -1, 1, 2};
-  const S w[4] = {S(1), S(-8), S(8), S(-1)};
-  S acc = S(0);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    S dy = S(0);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) dy += w[b] * p[c + o[a] + o[b] * W];
-    acc += w[a] * (dy * ihy12);
+// Central differences from an LDS plane at index c (stride st: 1 for x, W for y), with
+// the scale factor f passed in: order 4 (the high-order extension of Section 3.2)
+//   D f = (f-2 - 8 f-1 + 8 f+1 - f+2) / (12 h),
+//   L f = (-f-2 + 16 f-1 - 30 f0 + 16 f+1 - f+2) / (12 h^2),
+// order 2 (as printed in Section 3.2) D f = (f+1 - f-1) / (2 h), L f = (f-1 - 2 f0 + f+1)
+// / h^2; D_xy = D_x D_y in both.  f1(ih) and f2(ih) give the factors for 1/h = ih.
+template <int CO>
+struct Central;
+template <>
+struct Central<4> {
+  static constexpr int R = 2;  // reach
+  __host__ __device__ static double f1(double ih) { return ih / 12.0; }
+  __host__ __device__ static double f2(double ih) { return ih * ih / 12.0; }
+  template <typename S>
+  __device__ static S d1(const S *p, int c, int st, S f) {
+    return (p[c - 2 * st] - S(8) * p[c - st] + S(8) * p[c + st] - p[c + 2 * st]) * f;
   }
-  return acc * ihx12;
-}
+  template <typename S>
+  __device__ static S d2(const S *p, int c, int st, S f) {
+    return (-p[c - 2 * st] + S(16) * p[c - st] - S(30) * p[c] + S(16) * p[c + st] -
+            p[c + 2 * st]) *
+           f;
+  }
+  template <typename S>
+  __device__ static S dxy(const S *p, int c, int W, S fx, S fy) {
+    const int o[4] = {-2, -1, 1, 2};
+    const S w[4] = {S(1), S(-8), S(8), S(-1)};
+    S acc = S(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      S dy = S(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) dy += w[b] * p[c + o[a] + o[b] * W];
+      acc += w[a] * (dy * fy);
+    }
+    return acc * fx;
+  }
+};
+template <>
+struct Central<2> {
+  static constexpr int R = 1;
+  __host__ __device__ static double f1(double ih) { return 0.5 * ih; }
+  __host__ __device__ static double f2(double ih) { return ih * ih; }
+  template <typename S>
+  __device__ static S d1(const S *p, int c, int st, S f) {
+    return (p[c + st] - p[c - st]) * f;
+  }
+  template <typename S>
+  __device__ static S d2(const S *p, int c, int st, S f) {
+    return (p[c - st] - S(2) * p[c] + p[c + st]) * f;
+  }
+  template <typename S>
+  __device__ static S dxy(const S *p, int c, int W, S fx, S fy) {
+    const S dyp = (p[c + 1 + W] - p[c + 1 - W]) * fy, dym = (p[c - 1 + W] - p[c - 1 - W]) * fy;
+    return (dyp - dym) * fx;
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ Gp<T> tplane(const Inst &I, int slot) {
@@ -303,7 +382,7 @@ __device__ __forceinline__ Gp<double> dplane(const Inst &I, int slot) {
 
 // ------------------------------------------------------------------ step 2 RHS
 
-template <typename T, int TY>
+template <typename T, int TY, int CO>
 __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *__restrict__ insts,
                                                                    const Work *__restrict__ work,
                                                                    int nwork, ArgsR a) {
@@ -342,8 +421,9 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
   }
   __syncthreads();
   if (!col) return;
-  const T ihx12 = T(I.ihx / 12.0), ihy12 = T(I.ihy / 12.0);
-  const T ihx2 = T(I.ihx * I.ihx / 12.0), ihy2 = T(I.ihy * I.ihy / 12.0);
+  using C = Central<CO>;
+  const T ihx12 = T(C::f1(I.ihx)), ihy12 = T(C::f1(I.ihy));
+  const T ihx2 = T(C::f2(I.ihx)), ihy2 = T(C::f2(I.ihy));
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + 4 * r;
@@ -351,8 +431,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
     if (gy >= I.ny) break;
     const int c = Gm::at(tx, ly);
     // D0^2 : B(v) = -D_xx v1 + 2 D_x D_y v2 + D_yy v1
-    const T ddb = -cd2(sV1, c, 1, ihx2) + T(2) * cdxy(sV2, c, Gm::W, ihx12, ihy12) +
-                  cd2(sV1, c, Gm::W, ihy2);
+    const T ddb = -C::d2(sV1, c, 1, ihx2) + T(2) * C::dxy(sV2, c, Gm::W, ihx12, ihy12) +
+                  C::d2(sV1, c, Gm::W, ihy2);
     const long long g = (long long)gy * I.nx + gx;
     dplane(I, a.out_r)[g] = base[r] - (double)ddb;
     tplane<T>(I, a.out_ddb)[g] = ddb;
@@ -361,7 +441,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
 
 // ------------------------------------------------------------------ steps 3 and 4
 
-template <typename T, int TY>
+template <typename T, int TY, int WO, int CO>
 __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
@@ -410,14 +490,14 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   T hu1[Gm::ROWS], hu2[Gm::ROWS], dv[Gm::ROWS];
   // first row of B(v) = (-v1, v2), dissipation on u1
-  faces<TY, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
+  faces<TY, WO, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     hu1[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
   __syncthreads();
   // second row of B(v) = (v2, v1), dissipation on u2
-  faces<TY, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
+  faces<TY, WO, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
@@ -429,7 +509,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
     const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
-  faces<TY, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
+  faces<TY, WO, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
   double *sTh = reinterpret_cast<double *>(sP);
   {
     double *l[1] = {sTh};
@@ -441,7 +521,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
     dv[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
 
   if (!col) return;
-  const double ihx12 = I.ihx / 12.0, ihy12 = I.ihy / 12.0;
+  using C = Central<CO>;
+  const double ihx12 = C::f1(I.ihx), ihy12 = C::f1(I.ihy);
   const double dt = I.dt, te2 = I.te2, kinv = I.kinv[a.stage], aii = a.aii;
   const double htau = 0.5 * I.tau;
 #pragma unroll
@@ -452,8 +533,8 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
     const int c = Gm::at(tx, ly);
     const long long g = (long long)gy * nx + gx;
     // implicit velocity terms: D_W.B(v) + D0 theta (theta float64)
-    const double Hu1 = (double)hu1[r] + cd1(sTh, c, 1, ihx12);
-    const double Hu2 = (double)hu2[r] + cd1(sTh, c, Gm::W, ihy12);
+    const double Hu1 = (double)hu1[r] + C::d1(sTh, c, 1, ihx12);
+    const double Hu2 = (double)hu2[r] + C::d1(sTh, c, Gm::W, ihy12);
     const double u1 = un1[r] - dt * (h1[r] + aii * Hu1);
     const double u2 = un2[r] - dt * (h2[r] + aii * Hu2);
     const double Hq = htau * (double)dv[r];
@@ -473,7 +554,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
 
 // E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u), D0.u and Ltheta of a known stage, and,
 // fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
-template <typename T, int TY>
+template <typename T, int TY, int WO, int CO>
 __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
@@ -528,19 +609,20 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
-  const T ihx6 = T(I.ihx / 6.0), ihy6 = T(I.ihy / 6.0);
+  using C = Central<CO>;
+  const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
   const T qt = T(0.25 * I.tau), te2 = T(I.te2);
   // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
   T e1[Gm::ROWS], e2[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
-  faces<TY, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
+  faces<TY, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy));
   __syncthreads();
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
-  faces<TY, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
+  faces<TY, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -552,7 +634,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
     const int gy = wk.b + ly;
     if (col && gy < ny)
       tplane<T>(I, a.out_du)[(long long)gy * nx + gx] =
-          cd1(sU1, c, 1, ihx6) + cd1(sU2, c, Gm::W, ihy6);
+          C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
   }
   __syncthreads();
   // grad q with dissipation on v1 (x) and v2 (y); theta loaded meanwhile
@@ -561,7 +643,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
     const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
-  faces<TY, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
+  faces<TY, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
   double *sTh = reinterpret_cast<double *>(sU);
   if (want_lt) {
     double *l[1] = {sTh};
@@ -569,7 +651,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   }
   __syncthreads();
   if (!col) return;
-  const double ihx2 = I.ihx * I.ihx / 12.0, ihy2 = I.ihy * I.ihy / 12.0;
+  const double ihx2 = C::f2(I.ihx), ihy2 = C::f2(I.ihy);
   const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -585,7 +667,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
       tplane<T>(I, a.out_e[1])[g] = E2;
     }
     if (want_lt) {
-      const double lap = cd2(sTh, c, 1, ihx2) + cd2(sTh, c, Gm::W, ihy2);
+      const double lap = C::d2(sTh, c, 1, ihx2) + C::d2(sTh, c, Gm::W, ihy2);
       tplane<T>(I, a.out_lt)[g] = (T)(ddb[r] + lap);
     }
     if (nv.stage > 0) {
@@ -601,47 +683,61 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
 
 // ------------------------------------------------------------------ launchers
 
+// Dispatch on the tile height (8 or 16), the WENO order (5 or 3) and the central order
+// (4 or 2); the right-hand side kernel has no WENO flux.
 template <typename T>
-hipError_t launch_helmholtz_rhs(int ty, const Inst *insts, const Work *work, int nwork,
-                                const ArgsR &a, hipStream_t st) {
-  if (ty == 8)
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 8>), dim3(nwork), dim3(kStencilThreads), 0, st, insts,
-                       work, nwork, a);
+hipError_t launch_helmholtz_rhs(int ty, int wo, int co, const Inst *insts, const Work *work,
+                                int nwork, const ArgsR &a, hipStream_t st) {
+  (void)wo;
+  const dim3 g(nwork), b(kStencilThreads);
+  if (ty == 8 && co == 4)
+    hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 4>), g, b, 0, st, insts, work, nwork, a);
+  else if (ty == 8)
+    hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 2>), g, b, 0, st, insts, work, nwork, a);
+  else if (co == 4)
+    hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 4>), g, b, 0, st, insts, work, nwork, a);
   else
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 16>), dim3(nwork), dim3(kStencilThreads), 0, st, insts,
-                       work, nwork, a);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_update_uq(int ty, const Inst *insts, const Work *work, int nwork,
-                            const ArgsUQ &a, hipStream_t st) {
-  if (ty == 8)
-    hipLaunchKernelGGL((k_update_uq<T, 8>), dim3(nwork), dim3(kStencilThreads), 0, st, insts, work,
-                       nwork, a);
-  else
-    hipLaunchKernelGGL((k_update_uq<T, 16>), dim3(nwork), dim3(kStencilThreads), 0, st, insts,
-                       work, nwork, a);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_stage_terms(int ty, const Inst *insts, const Work *work, int nwork,
-                              const ArgsE &a, const ArgsV &nv, hipStream_t st) {
-  if (ty == 8)
-    hipLaunchKernelGGL((k_stage_terms<T, 8>), dim3(nwork), dim3(kStencilThreads), 0, st, insts,
-                       work, nwork, a, nv);
-  else
-    hipLaunchKernelGGL((k_stage_terms<T, 16>), dim3(nwork), dim3(kStencilThreads), 0, st, insts,
-                       work, nwork, a, nv);
+    hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 2>), g, b, 0, st, insts, work, nwork, a);
   return hipGetLastError();
 }
 
+#define APDVM_DISPATCH(KERNEL, ...)                                                        \
+  do {                                                                                     \
+    const dim3 g(nwork), b(kStencilThreads);                                               \
+    const int key = (ty == 8 ? 0 : 4) + (wo == 5 ? 0 : 2) + (co == 4 ? 0 : 1);              \
+    switch (key) {                                                                         \
+      case 0: hipLaunchKernelGGL((KERNEL<T, 8, 5, 4>), g, b, 0, st, __VA_ARGS__); break;    \
+      case 1: hipLaunchKernelGGL((KERNEL<T, 8, 5, 2>), g, b, 0, st, __VA_ARGS__); break;    \
+      case 2: hipLaunchKernelGGL((KERNEL<T, 8, 3, 4>), g, b, 0, st, __VA_ARGS__); break;    \
+      case 3: hipLaunchKernelGGL((KERNEL<T, 8, 3, 2>), g, b, 0, st, __VA_ARGS__); break;    \
+      case 4: hipLaunchKernelGGL((KERNEL<T, 16, 5, 4>), g, b, 0, st, __VA_ARGS__); break;   \
+      case 5: hipLaunchKernelGGL((KERNEL<T, 16, 5, 2>), g, b, 0, st, __VA_ARGS__); break;   \
+      case 6: hipLaunchKernelGGL((KERNEL<T, 16, 3, 4>), g, b, 0, st, __VA_ARGS__); break;   \
+      default: hipLaunchKernelGGL((KERNEL<T, 16, 3, 2>), g, b, 0, st, __VA_ARGS__); break;  \
+    }                                                                                      \
+  } while (0)
+
+template <typename T>
+hipError_t launch_update_uq(int ty, int wo, int co, const Inst *insts, const Work *work,
+                            int nwork, const ArgsUQ &a, hipStream_t st) {
+  APDVM_DISPATCH(k_update_uq, insts, work, nwork, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_stage_terms(int ty, int wo, int co, const Inst *insts, const Work *work,
+                              int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st) {
+  APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
+  return hipGetLastError();
+}
+#undef APDVM_DISPATCH
+
 #define APDVM_INST(T)                                                                           \
-  template hipError_t launch_helmholtz_rhs<T>(int, const Inst *, const Work *, int,            \
+  template hipError_t launch_helmholtz_rhs<T>(int, int, int, const Inst *, const Work *, int,  \
                                               const ArgsR &, hipStream_t);                     \
-  template hipError_t launch_update_uq<T>(int, const Inst *, const Work *, int, const ArgsUQ &, \
-                                          hipStream_t);                                        \
-  template hipError_t launch_stage_terms<T>(int, const Inst *, const Work *, int, const ArgsE &, \
-                                            const ArgsV &, hipStream_t);
+  template hipError_t launch_update_uq<T>(int, int, int, const Inst *, const Work *, int,      \
+                                          const ArgsUQ &, hipStream_t);                        \
+  template hipError_t launch_stage_terms<T>(int, int, int, const Inst *, const Work *, int,    \
+                                            const ArgsE &, const ArgsV &, hipStream_t);
 APDVM_INST(double)
 APDVM_INST(float)
 #undef APDVM_INST

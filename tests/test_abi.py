@@ -117,6 +117,23 @@ def test_rejects_bad_physics():
     assert _code(cfg) == 1
 
 
+def test_space_discretisation_orders():
+    keep = []
+    for wo, co in ((5, 4), (3, 2), (3, 4), (5, 2), (0, 0)):
+        assert _ws(apdvm.make_config(16, keep=keep, weno_order=wo, central_order=co)) > 0
+    assert _code(apdvm.make_config(16, keep=keep, weno_order=4)) == 1
+    assert _code(apdvm.make_config(16, keep=keep, central_order=6)) == 1
+    # every instance of a context must use the same operators
+    a = apdvm.make_config(16, keep=keep, weno_order=3, central_order=2)
+    b = apdvm.make_config(16, keep=keep)
+    arr = (apdvm.Config * 2)(a, b)
+    out = ctypes.c_size_t(0)
+    assert apdvm.lib().apdvm_workspace_bytes(2, arr, ctypes.byref(out)) == 1
+    c = apdvm.make_config(16, keep=keep, weno_order=0, central_order=0)
+    arr = (apdvm.Config * 2)(b, c)
+    assert apdvm.lib().apdvm_workspace_bytes(2, arr, ctypes.byref(out)) == 0
+
+
 def test_binding_tableaux_match_golden():
     import json
     import os

@@ -23,10 +23,10 @@ def _apdvm():
     return apdvm
 
 
-def _oracle(state, eps, tau, dt, tab, nsteps, lx=2 * np.pi, ly=2 * np.pi):
+def _oracle(state, eps, tau, dt, tab, nsteps, lx=2 * np.pi, ly=2 * np.pi, wo=5, co=4):
     ny, nx = state[0].shape
     return scheme.run(state, scheme.Params(eps, tau, dt), otab.preset(tab),
-                      Production(lx / nx, ly / ny), nsteps)
+                      Production(lx / nx, ly / ny, central_order=co, weno_order=wo), nsteps)
 
 
 def _relerr(got, ref):
@@ -45,12 +45,13 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run_gpu(cases, tab, nsteps, precision=0, shape=None):
+def _run_gpu(cases, tab, nsteps, precision=0, shape=None, wo=5, co=4):
     apdvm = _apdvm()
     sim = apdvm.Simulation([dict(nx=c["state"][0].shape[1], ny=c["state"][0].shape[0],
                                  eps=c["eps"], tau=c["tau"], dt=c["dt"],
                                  lx=c.get("lx", 2 * np.pi), ly=c.get("ly", 2 * np.pi))
-                            for c in cases], tableau=tab, precision=precision)
+                            for c in cases], tableau=tab, precision=precision,
+                           weno_order=wo, central_order=co)
     if shape is not None:
         sim.set_tuning(*shape)
     for k, c in enumerate(cases):
@@ -178,6 +179,43 @@ def test_shear_layer_512_one_step(eps):
     c = dict(state=case.state, eps=case.eps, tau=case.tau, dt=case.dt)
     got = _run_gpu([c], "ars443", 1)[0]
     ref = _oracle(case.state, case.eps, case.tau, case.dt, "ars443", 1)
+    err = _relerr(got, ref)
+    _say(f"  relerr {err}")
+    assert max(err.values()) <= TOL, err
+
+
+@pytest.mark.parametrize("wo,co,tab,shape", [(3, 2, "euler1", (8, False)),
+                                             (3, 2, "paper2", (16, True)),
+                                             (3, 4, "paper2", (8, True)),
+                                             (5, 2, "ars443", (16, False))])
+def test_space_orders_match_oracle(wo, co, tab, shape):
+    """WENO3 and second-order central differences (the convergence-table operators) and
+    the mixed combinations, on two ragged non-square instances from kinetic to small eps."""
+    cases = [dict(state=wl.random_divfree(96, 72, kmax=4, rms=0.1, seed=41), eps=0.05, tau=0.3,
+                  dt=0.005, ly=3 * np.pi),
+             dict(state=wl.random_divfree(48, 36, kmax=4, rms=0.1, seed=42), eps=1e-6, tau=0.05,
+                  dt=0.01)]
+    _say(f"case space orders weno={wo} central={co} {tab} shape={shape}")
+    got = _run_gpu(cases, tab, 6, shape=shape, wo=wo, co=co)
+    for k, c in enumerate(cases):
+        ref = _oracle(c["state"], c["eps"], c["tau"], c["dt"], tab, 6, ly=c.get("ly", 2 * np.pi),
+                      wo=wo, co=co)
+        err = _relerr(got[k], ref)
+        _say(f"  instance {k} relerr {err}")
+        assert max(err.values()) <= TOL, (k, err)
+
+
+@pytest.mark.parametrize("tab", ["euler1", "paper2"])
+def test_shear_layer_convergence_table_setting(tab):
+    """The setting of the convergence tables (Section 4.1): 64^2 thick shear layer,
+    eps = 1e-6, tau = 0, WENO3 + second-order central, dt = 1 / (2N)."""
+    n = 64
+    st = wl.shear_layer(n)
+    dt, nsteps = 1.0 / (2 * n), 16
+    _say(f"case table setting shear64 {tab}")
+    c = dict(state=st, eps=1e-6, tau=0.0, dt=dt)
+    got = _run_gpu([c], tab, nsteps, wo=3, co=2)[0]
+    ref = _oracle(st, 1e-6, 0.0, dt, tab, nsteps, wo=3, co=2)
     err = _relerr(got, ref)
     _say(f"  relerr {err}")
     assert max(err.values()) <= TOL, err

@@ -201,6 +201,33 @@ def test_taylor_green_low_order_bundle(name):
     assert errs[-1] < 1e-3 and obs > 2.2, (errs, obs)
 
 
+def test_fixed_grid_time_order_of_the_printed_operators():
+    """On a fixed grid in the stiff regime (eps = 1e-6) the fully discrete scheme has the
+    tableau's order in time with the consistent bundle, but only first order with the
+    printed operators: D_Delta and D0^2:B(v) are not the compositions of the first
+    derivatives that substituting step 3 into the theta equation assumes, which leaves
+    an O(dt h^4) term (fourth-order operators).  With dt proportional to h this is
+    O(h^5), below the space error, as in the convergence tables of Section 4.1."""
+    T, tau = 0.5, 0.05
+    tab = tb.preset("ars443")
+
+    def errs(ops, n):
+        st = wl.taylor_green(n)
+        ref = scheme.run(st, scheme.Params(1e-6, tau, T / 256), tab, ops, 256)
+        out = []
+        for m in (8, 16):
+            o = scheme.run(st, scheme.Params(1e-6, tau, T / m), tab, ops, m)
+            out.append(max(np.max(np.abs(o[k] - ref[k])) for k in (0, 1)))
+        return out
+
+    h16, h32 = 2 * np.pi / 16, 2 * np.pi / 32
+    c = errs(Consistent(h32, h32), 32)
+    assert math.log2(c[0] / c[1]) > 2.6 and c[1] < 1e-12, c
+    p16, p32 = errs(Production(h16, h16), 16), errs(Production(h32, h32), 32)
+    assert 0.8 < math.log2(p32[0] / p32[1]) < 1.3, p32
+    assert 10.0 < p16[1] / p32[1] < 30.0, (p16, p32)  # about 2^4
+
+
 def test_eps_zero_tau_zero_runs_finite():
     n = 32
     st = wl.shear_layer(n)
