@@ -160,8 +160,8 @@ apdvm_status apdvm_set_step(apdvm_ctx *ctx, int64_t step);
 
 /* Diagnostics of instance k, computed on the device and synchronised:
  * out[0] sum theta h_x h_y, out[1] sum u1 h_x h_y, out[2] sum u2 h_x h_y,
- * out[3] max |D0.u| (fourth-order central divergence, the divergence diagnostic of
- * Section 4), out[4] min vorticity, out[5] max vorticity (fourth-order central
+ * out[3] max |D0.u| (central divergence of the context's central_order, the divergence
+ * diagnostic of Section 4), out[4] min vorticity, out[5] max vorticity (the same central
  * D_x u2 - D_y u1), out[6] kinetic energy 1/2 sum |u|^2 h_x h_y, out[7] 1 if every
  * value of the six fields is finite else 0. */
 apdvm_status apdvm_diagnostics(apdvm_ctx *ctx, int32_t k, double out[8]);

@@ -31,7 +31,7 @@ constexpr int kTileRows[2] = {8, 16};
 hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
                              int, const Work *, int, const ArgsSolve &, hipStream_t);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
-                              int, double *, int, hipStream_t);
+                              int, int, double *, int, hipStream_t);
 
 namespace {
 
@@ -1228,7 +1228,7 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
   if (launch_diagnostics(c->d_inst, c->d_tiles[1] + c->tile_first[k], nblk, kTileRows[1],
                          c->split ? 1 : 0,
                          L.st[P][0], L.st[P][1], L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
-                         c->d_partials, used, c->stream) != hipSuccess)
+                         c->co, c->d_partials, used, c->stream) != hipSuccess)
     return APDVM_ERR_HIP;
   std::vector<double> part(8 * (size_t)used);
   if (hipMemcpyAsync(part.data(), c->d_partials, part.size() * sizeof(double),

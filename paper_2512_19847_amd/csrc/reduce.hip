@@ -1,5 +1,6 @@
 // Diagnostics of one instance: sum theta, sum u1, sum u2, max |D0.u| (the divergence
-// diagnostic of Section 4), min and max of the vorticity D_x u2 - D_y u1, sum |u|^2
+// diagnostic of Section 4, with the central differences of the scheme: fourth or second
+// order), min and max of the vorticity D_x u2 - D_y u1, sum |u|^2
 // and a finite flag over all six fields.  Two levels: each workgroup reduces its tiles
 // with wavefront shuffles and LDS into one record of partials; the host combines the
 // records (deterministic: no atomics).
@@ -17,12 +18,14 @@ __device__ __forceinline__ double at(const T *p, int nx, int ny, int x, int y) {
   return (double)p[(long long)wrapi(y, ny) * nx + wrapi(x, nx)];
 }
 
+// Central first derivative along (ox, oy); f = 1/(12h) for order 4, 1/(2h) for order 2.
 template <typename T>
 __device__ __forceinline__ double dcen(const T *p, int nx, int ny, int x, int y, int ox, int oy,
-                                       double ih12) {
+                                       double f, int co) {
+  if (co == 2) return (at(p, nx, ny, x + ox, y + oy) - at(p, nx, ny, x - ox, y - oy)) * f;
   return (at(p, nx, ny, x - 2 * ox, y - 2 * oy) - 8.0 * at(p, nx, ny, x - ox, y - oy) +
           8.0 * at(p, nx, ny, x + ox, y + oy) - at(p, nx, ny, x + 2 * ox, y + 2 * oy)) *
-         ih12;
+         f;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -42,7 +45,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
                                               const Work *__restrict__ tiles, int ntiles, int ty,
                                               int su1, int su2, int dth, int sv1, int sv2, int sq,
-                                              double *__restrict__ partials) {
+                                              int co, double *__restrict__ partials) {
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 1e300, -1e300, 0.0, 1.0};
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Work wk = tiles[t];
@@ -53,7 +56,8 @@ __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
     const T *v1 = tb + (long long)sv1 * I.plane, *v2 = tb + (long long)sv2 * I.plane;
     const T *q = tb + (long long)sq * I.plane;
     const double *th = I.dbase + (long long)dth * I.plane;
-    const double ihx12 = I.ihx / 12.0, ihy12 = I.ihy / 12.0;
+    const double ihx12 = co == 2 ? 0.5 * I.ihx : I.ihx / 12.0;
+    const double ihy12 = co == 2 ? 0.5 * I.ihy : I.ihy / 12.0;
     const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
     const int x = wk.a + tx;
     if (x >= nx) continue;
@@ -65,8 +69,10 @@ __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
       acc[0] += c;
       acc[1] += a;
       acc[2] += b;
-      const double div = dcen(u1, nx, ny, x, y, 1, 0, ihx12) + dcen(u2, nx, ny, x, y, 0, 1, ihy12);
-      const double vor = dcen(u2, nx, ny, x, y, 1, 0, ihx12) - dcen(u1, nx, ny, x, y, 0, 1, ihy12);
+      const double div =
+          dcen(u1, nx, ny, x, y, 1, 0, ihx12, co) + dcen(u2, nx, ny, x, y, 0, 1, ihy12, co);
+      const double vor =
+          dcen(u2, nx, ny, x, y, 1, 0, ihx12, co) - dcen(u1, nx, ny, x, y, 0, 1, ihy12, co);
       acc[3] = fmax(acc[3], fabs(div));
       acc[4] = fmin(acc[4], vor);
       acc[5] = fmax(acc[5], vor);
@@ -109,14 +115,14 @@ __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
 
 // tiles: the stencil work items (64 x ty cells) of one instance.
 hipError_t launch_diagnostics(const Inst *insts, const Work *tiles, int ntiles, int ty, int split,
-                              int su1, int su2, int dth, int sv1, int sv2, int sq,
+                              int su1, int su2, int dth, int sv1, int sv2, int sq, int co,
                               double *partials, int nblocks, hipStream_t st) {
   if (split)
     hipLaunchKernelGGL(k_diag<float>, dim3(nblocks), dim3(256), 0, st, insts, tiles, ntiles, ty,
-                       su1, su2, dth, sv1, sv2, sq, partials);
+                       su1, su2, dth, sv1, sv2, sq, co, partials);
   else
     hipLaunchKernelGGL(k_diag<double>, dim3(nblocks), dim3(256), 0, st, insts, tiles, ntiles, ty,
-                       su1, su2, dth, sv1, sv2, sq, partials);
+                       su1, su2, dth, sv1, sv2, sq, co, partials);
   return hipGetLastError();
 }
 

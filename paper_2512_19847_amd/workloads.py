@@ -130,6 +130,11 @@ def shear_layer(nx, ny=None, rho=math.pi / 15.0, delta=0.05):
     return equilibrium_state(u1, u2, pressure_poisson(u1, u2))
 
 
+def thin_shear_layer(nx, ny=None):
+    """Thin shear layer of Section 4.1: the thick layer with rho = pi / 50."""
+    return shear_layer(nx, ny, rho=math.pi / 50.0)
+
+
 def kelvin_helmholtz(nx, ny=None):
     ny = nx if ny is None else ny
     L = 2.0 * TWO_PI
@@ -229,6 +234,22 @@ def batched_256(count=256, seed=4, sides=(64, 96, 128, 192, 256, 384, 512)):
         cases.append(make_case(f"batch_{k}", st, float(epss[k]), float(machs[k]), "ars443",
                                cfl=CFL_ARS))
     return cases
+
+
+# Long runs of Section 4.1 and the Kelvin-Helmholtz test: (generator, box side, final
+# time).  eps = 1e-6; tau = 0 (incompressible Euler limit) or 0.05 (Navier-Stokes).
+FLOWS = {
+    "thick_shear_layer": (shear_layer, TWO_PI, {0.0: 6.0, 0.05: 9.5}),
+    "thin_shear_layer": (thin_shear_layer, TWO_PI, {0.0: 6.0, 0.05: 9.5}),
+    "kelvin_helmholtz": (kelvin_helmholtz, 2.0 * TWO_PI, {0.0: 45.0, 0.05: 45.0}),
+}
+
+
+def flow_case(kind, n, tau, eps=1e-6, tableau="ars443", cfl=CFL_ARS):
+    """One of FLOWS on an n x n grid with the time step of the rule above."""
+    gen, L, _ = FLOWS[kind]
+    return make_case(f"{kind}_{n}_tau{tau:g}", gen(n), eps, 1.0, tableau, cfl=cfl, tau=tau,
+                     lx=L, ly=L)
 
 
 def shear_layer_8192(n=8192):

@@ -11,10 +11,10 @@ from paper_2512_19847_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def _sim(n=64, eps=0.05, tau=0.3, dt=0.01, tab="ars443", count=1, stream=None, **kw):
+def _sim(n=64, eps=0.05, tau=0.3, dt=0.01, tab="ars443", count=1, stream=None, co=4, **kw):
     from paper_2512_19847_amd import apdvm
     return apdvm.Simulation([dict(nx=n, eps=eps, tau=tau, dt=dt, **kw)] * count, tableau=tab,
-                            stream=stream)
+                            stream=stream, weno_order=5 if co == 4 else 3, central_order=co)
 
 
 def _state(n=64, seed=5):
@@ -124,17 +124,19 @@ def test_errors_non_finite_and_order():
     sim.close()
 
 
-def test_diagnostics_match_host_values():
+@pytest.mark.parametrize("co", [4, 2])
+def test_diagnostics_match_host_values(co):
+    """Divergence and vorticity with the central differences of the context."""
     n = 64
     st = _state(n)
-    sim = _sim(n=n)
+    sim = _sim(n=n, co=co)
     sim.set_fields(0, *st)
     sim.step(2)
     f = sim.get_fields(0)
     d = sim.diagnostics(0)
     h = 2 * np.pi / n
-    div = central_d(f[0], 1, h) + central_d(f[1], 0, h)
-    vor = central_d(f[1], 1, h) - central_d(f[0], 0, h)
+    div = central_d(f[0], 1, h, co) + central_d(f[1], 0, h, co)
+    vor = central_d(f[1], 1, h, co) - central_d(f[0], 0, h, co)
     assert abs(d[0] - f[2].sum() * h * h) < 1e-12 * max(1.0, np.abs(f[2]).sum() * h * h)
     assert abs(d[1] - f[0].sum() * h * h) < 1e-12
     assert abs(d[2] - f[1].sum() * h * h) < 1e-12

@@ -219,3 +219,17 @@ def test_shear_layer_convergence_table_setting(tab):
     err = _relerr(got, ref)
     _say(f"  relerr {err}")
     assert max(err.values()) <= TOL, err
+
+
+@pytest.mark.parametrize("kind,tau", [("thin_shear_layer", 0.0), ("kelvin_helmholtz", 0.05)])
+def test_long_run_flows_match_oracle(kind, tau):
+    """The flows of the long runs (thin shear layer; Kelvin-Helmholtz on [0, 4 pi]^2),
+    eps = 1e-6, 64^2, ten steps of the production time step."""
+    case = wl.flow_case(kind, 64, tau)
+    _say(f"case {kind} tau={tau} dt={case.dt}")
+    c = dict(state=case.state, eps=case.eps, tau=case.tau, dt=case.dt, lx=case.lx, ly=case.ly)
+    got = _run_gpu([c], "ars443", 10)[0]
+    ref = _oracle(case.state, case.eps, case.tau, case.dt, "ars443", 10, case.lx, case.ly)
+    err = _relerr(got, ref)
+    _say(f"  relerr {err}")
+    assert max(err.values()) <= TOL, err
