@@ -66,9 +66,11 @@ typedef enum {
  * 4/tau, Section 2); tau >= 0 is used as given (the paper's tests use 0 and 0.05).
  *
  * Tableau: s stages (2 <= s <= 8), a_ex and a_im s x s row-major, b_ex and b_im of
- * length s (Section 3.1).  Must be globally stiffly accurate and of ARS type
- * (a_im[0][0] = 0 and a_im[i][0] = 0), a_ex strictly lower triangular, a_im lower
- * triangular with nonzero diagonal after the first stage; else APDVM_ERR_TABLEAU.
+ * length s (Section 3.1).  Must be globally stiffly accurate, a_ex strictly lower
+ * triangular and a_im lower triangular, and either of ARS type (a_im[0][0] = 0,
+ * a_im[i][0] = 0, nonzero diagonal after the first stage) or of type A (every diagonal
+ * entry nonzero, s <= 7; run internally as s + 1 stages whose first is the state at
+ * time n with zero coefficients); else APDVM_ERR_TABLEAU.
  *
  * dt > 0 is used as given.  dt <= 0 derives the largest dt with
  *   ct dt max(umax, 1, tau eps / (tau eps^2 + ct dt)) <= cfl h  and

@@ -15,6 +15,12 @@ Presets:
            (Section 4.1);
   ars443   third-order ARS(4,4,3) of Ascher, Ruuth and Spiteri (1997), cited by the
            paper but not printed in it: the paper prints no third-order tableau.
+Type-A presets (Theorem 3.4 covers type A without well-prepared data; the paper prints
+no type-A tableau, so these are constructed here from the order conditions):
+  typea1   first order: implicit A = I (2 x 2), explicit stage 2 from stage 1;
+  typea2   second order, four stages, diagonally implicit with a_ii = 1/4 and weights
+           b = (1/2, 0, 1/4, 1/4), explicit Heun-type part with weights (1/2, 1/2, 0, 0);
+           it meets sum b = sum bt = 1 and b.c = bt.ct = b.ct = bt.c = 1/2 exactly.
 Pins (tests/test_tableau.py): the printed coefficients (tests/golden/tableaux.json),
 structural properties, and observed order of accuracy on a partitioned test ODE
 against a high-accuracy reference.
@@ -102,9 +108,31 @@ def ars443_fractions():
     return At, list(At[4]), A, list(A[4])
 
 
+def typea1_fractions():
+    At = [[0, 0], [1, 0]]
+    bt = [1, 0]
+    A = [[1, 0], [0, 1]]
+    b = [0, 1]
+    return At, bt, A, b
+
+
+def typea2_fractions():
+    q, h = Fr(1, 4), Fr(1, 2)
+    A = [[q, 0, 0, 0],
+         [h, q, 0, 0],
+         [q, 0, q, 0],
+         [h, 0, q, q]]
+    At = [[0, 0, 0, 0],
+          [1, 0, 0, 0],
+          [h, h, 0, 0],
+          [h, h, 0, 0]]
+    return At, [h, h, 0, 0], A, [h, 0, q, q]
+
+
 def preset_fractions(name):
     return {"euler1": euler1_fractions, "paper2": paper2_fractions,
-            "ars443": ars443_fractions}[name]()
+            "ars443": ars443_fractions, "typea1": typea1_fractions,
+            "typea2": typea2_fractions}[name]()
 
 
 def preset(name):
@@ -114,3 +142,4 @@ def preset(name):
 
 
 PRESETS = ("euler1", "paper2", "ars443")
+TYPE_A_PRESETS = ("typea1", "typea2")

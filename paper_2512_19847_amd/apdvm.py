@@ -62,6 +62,12 @@ def _tableaux():
                    [[0, 0, 0, 0, 0], [0, 1 / 2, 0, 0, 0], [0, 1 / 6, 1 / 2, 0, 0],
                     [0, -1 / 2, 1 / 2, 1 / 2, 0], [0, 3 / 2, -3 / 2, 1 / 2, 1 / 2]],
                    [0, 3 / 2, -3 / 2, 1 / 2, 1 / 2]),
+        # type A (every stage implicit), first and second order
+        "typea1": ([[0, 0], [1, 0]], [1, 0], [[1, 0], [0, 1]], [0, 1]),
+        "typea2": ([[0, 0, 0, 0], [1, 0, 0, 0], [1 / 2, 1 / 2, 0, 0], [1 / 2, 1 / 2, 0, 0]],
+                   [1 / 2, 1 / 2, 0, 0],
+                   [[1 / 4, 0, 0, 0], [1 / 2, 1 / 4, 0, 0], [1 / 4, 0, 1 / 4, 0],
+                    [1 / 2, 0, 1 / 4, 1 / 4]], [1 / 2, 0, 1 / 4, 1 / 4]),
     }
     return {k: tuple(np.array(x, dtype=np.float64) for x in v) for k, v in t.items()}
 

@@ -69,6 +69,12 @@ apdvm_status check_velset(const apdvm_config &c) {
   return APDVM_OK;
 }
 
+// Type A (Section 3.1): every stage implicit.  Such a tableau runs as an (s+1)-stage
+// tableau of ARS form whose first stage is the state at time n with zero coefficients
+// in both parts, which evaluates the same sums stage by stage.
+bool is_type_a(const apdvm_config &c) { return c.a_im[0] != 0.0; }
+int internal_stages(const apdvm_config &c) { return c.s + (is_type_a(c) ? 1 : 0); }
+
 apdvm_status check_tableau(const apdvm_config &c) {
   const int s = c.s;
   if (s < 2 || s > kMaxStages) return APDVM_ERR_TABLEAU;
@@ -83,12 +89,18 @@ apdvm_status check_tableau(const apdvm_config &c) {
     }
     if (!std::isfinite(c.b_ex[i]) || !std::isfinite(c.b_im[i])) return APDVM_ERR_TABLEAU;
   }
-  // ARS type: the first stage is explicit and the first column of A vanishes
-  if (A(0, 0) != 0.0) return APDVM_ERR_TABLEAU;
-  for (int i = 0; i < s; ++i)
-    if (A(i, 0) != 0.0) return APDVM_ERR_TABLEAU;
-  for (int i = 1; i < s; ++i)
-    if (A(i, i) == 0.0) return APDVM_ERR_TABLEAU;
+  if (is_type_a(c)) {
+    // type A: every diagonal entry nonzero; one extra internal stage must fit
+    if (s + 1 > kMaxStages) return APDVM_ERR_TABLEAU;
+    for (int i = 0; i < s; ++i)
+      if (A(i, i) == 0.0) return APDVM_ERR_TABLEAU;
+  } else {
+    // ARS type: the first stage is explicit and the first column of A vanishes
+    for (int i = 0; i < s; ++i)
+      if (A(i, 0) != 0.0) return APDVM_ERR_TABLEAU;
+    for (int i = 1; i < s; ++i)
+      if (A(i, i) == 0.0) return APDVM_ERR_TABLEAU;
+  }
   // globally stiffly accurate: the last stage is the new time level
   for (int j = 0; j < s; ++j)
     if (A(s - 1, j) != c.b_im[j]) return APDVM_ERR_TABLEAU;
@@ -318,7 +330,7 @@ size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
 }
 
 size_t workspace_bytes(int n, const apdvm_config *cfgs) {
-  const Layout L = make_layout(cfgs[0].s);
+  const Layout L = make_layout(internal_stages(cfgs[0]));
   const bool split = cfgs[0].precision == APDVM_FP32_SPLIT;
   const size_t tsize = split ? sizeof(float) : sizeof(double);
   size_t b = align_up(n * sizeof(Inst));
@@ -860,7 +872,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   apdvm_ctx *c = new (std::nothrow) apdvm_ctx;
   if (!c) return APDVM_ERR_NOMEM;
   c->n = n;
-  c->s = cfgs[0].s;
+  c->s = internal_stages(cfgs[0]);
   c->split = cfgs[0].precision == APDVM_FP32_SPLIT;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->cfg.assign(cfgs, cfgs + n);
@@ -868,11 +880,16 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
     c->cfg[k].cx = c->cfg[k].cy = nullptr;
   }
-  for (int i = 0; i < c->s; ++i)
-    for (int j = 0; j < c->s; ++j) {
-      c->At[i][j] = cfgs[0].a_ex[i * c->s + j];
-      c->A[i][j] = cfgs[0].a_im[i * c->s + j];
-    }
+  {
+    const int s0 = cfgs[0].s, off = c->s - s0;  // off = 1: type A behind a zero stage
+    for (int i = 0; i < c->s; ++i)
+      for (int j = 0; j < c->s; ++j) c->At[i][j] = c->A[i][j] = 0.0;
+    for (int i = 0; i < s0; ++i)
+      for (int j = 0; j < s0; ++j) {
+        c->At[i + off][j + off] = cfgs[0].a_ex[i * s0 + j];
+        c->A[i + off][j + off] = cfgs[0].a_im[i * s0 + j];
+      }
+  }
   c->L = make_layout(c->s);
   c->has_fields.assign(n, 0);
   c->umax.assign(n, 0.0);

@@ -130,6 +130,29 @@ def shear_layer(nx, ny=None, rho=math.pi / 15.0, delta=0.05):
     return equilibrium_state(u1, u2, pressure_poisson(u1, u2))
 
 
+def ill_prepared(nx, ny=None, kmax=4, rms=0.1, grad_rms=0.05, seed=0):
+    """A divergence-free random field plus the gradient of a random potential (rms
+    speeds rms and grad_rms, modes 1 <= |k| <= kmax, default_rng(seed) and seed + 1):
+    initial data that is not well prepared for the incompressible limit (div u = O(1),
+    Theorem 3.4 against Theorem 3.5), with theta from the pressure equation of the
+    whole field and the kinetic moments at local equilibrium."""
+    ny = nx if ny is None else ny
+    u1, u2 = random_divfree(nx, ny, kmax=kmax, rms=rms, seed=seed)[:2]
+    rng = np.random.default_rng(seed + 1)
+    kx = np.fft.fftfreq(nx, d=1.0 / nx)
+    ky = np.fft.fftfreq(ny, d=1.0 / ny)
+    KX, KY = np.meshgrid(kx, ky)
+    kk = np.sqrt(KX ** 2 + KY ** 2)
+    amp = np.where((kk >= 1) & (kk <= kmax),
+                   rng.standard_normal(kk.shape) + 1j * rng.standard_normal(kk.shape), 0.0)
+    phi_h = np.fft.fft2(np.real(np.fft.ifft2(amp)))
+    g1 = np.real(np.fft.ifft2(1j * KX * phi_h))
+    g2 = np.real(np.fft.ifft2(1j * KY * phi_h))
+    scale = grad_rms / math.sqrt(np.mean(g1 * g1 + g2 * g2))
+    w1, w2 = u1 + scale * g1, u2 + scale * g2
+    return equilibrium_state(w1, w2, pressure_poisson(w1, w2))
+
+
 def thin_shear_layer(nx, ny=None):
     """Thin shear layer of Section 4.1: the thick layer with rho = pi / 50."""
     return shear_layer(nx, ny, rho=math.pi / 50.0)

@@ -92,10 +92,14 @@ def test_rejects_bad_tableaux():
     b2 = b.copy()
     b2[1] += 0.1
     assert _code(_with_tableau(At, bt, A, b2, keep)) == 3
-    # type A (first stage implicit) is outside the ARS family handled on the device
+    # type A (every stage implicit) is accepted; a first implicit stage followed by a
+    # zero diagonal entry is neither type A nor ARS
     A2 = A.copy()
     A2[0, 0] = 0.5
-    assert _code(_with_tableau(At, bt, A2, b, keep)) == 3
+    assert _ws(_with_tableau(At, bt, A2, b, keep)) > 0
+    A4 = A2.copy()
+    A4[1, 1] = 0.0
+    assert _code(_with_tableau(At, bt, A4, b, keep)) == 3
     # explicit part not strictly lower triangular
     At2 = At.copy()
     At2[1, 1] = 0.2
@@ -138,8 +142,15 @@ def test_binding_tableaux_match_golden():
     import json
     import os
 
+    from oracle import tableau as otab
+
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tableaux.json")))
     for name, (At, bt, A, b) in apdvm.TABLEAUX.items():
-        g = gold[name]
+        # the paper's tableaux against the printed coefficients, the constructed type-A
+        # ones against the oracle's exact fractions
+        g = gold[name] if name in gold else dict(zip(("At", "bt", "A", "b"),
+                                                     otab.preset_fractions(name)))
         for got, key in ((At, "At"), (bt, "bt"), (A, "A"), (b, "b")):
-            assert np.allclose(got, np.array(g[key], dtype=float), atol=1e-15, rtol=0)
+            want = np.array([[float(x) for x in r] for r in g[key]] if np.ndim(g[key]) == 2
+                            else [float(x) for x in g[key]], dtype=float)
+            assert np.allclose(got, want, atol=1e-15, rtol=0), (name, key)

@@ -68,3 +68,30 @@ def test_observed_order(name):
         errs.append(np.max(np.abs(_imex_integrate(t, fE, M, y0, T / n, n) - ref)))
     orders = [np.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
     assert abs(orders[-1] - GOLD[name]["order"]) < 0.2, (errs, orders)
+
+
+@pytest.mark.parametrize("name,order", [("typea1", 1), ("typea2", 2)])
+def test_type_a_presets(name, order):
+    """The constructed type-A tableaux: structure, the order conditions in exact
+    arithmetic, and the observed order on the partitioned test problem."""
+    t = tb.preset(name)
+    assert t.is_explicit_part_ok() and t.is_dirk() and t.is_gsa()
+    assert t.is_type_a() and not t.is_type_ck()
+    At, bt, A, b = tb.preset_fractions(name)
+    s = len(b)
+    c = [sum(A[i]) for i in range(s)]
+    ct = [sum(At[i]) for i in range(s)]
+    assert sum(b) == 1 and sum(bt) == 1
+    if order >= 2:
+        half = tb.Fr(1, 2)
+        for w, x in ((b, c), (bt, ct), (b, ct), (bt, c)):
+            assert sum(wi * xi for wi, xi in zip(w, x)) == half
+    M = np.array([[-1.0, 0.5], [-0.3, -2.0]])
+    fE = lambda y: np.array([np.sin(y[1]) - 0.5 * y[0] * y[1], y[0] ** 2 - np.cos(y[0])])
+    y0 = np.array([0.7, -0.4])
+    ref = solve_ivp(lambda _t, y: fE(y) + M @ y, (0, 1.0), y0, method="DOP853",
+                    rtol=1e-13, atol=1e-14).y[:, -1]
+    errs = [np.max(np.abs(_imex_integrate(t, fE, M, y0, 1.0 / n, n) - ref))
+            for n in (20, 40, 80, 160)]
+    obs = np.log2(errs[-2] / errs[-1])
+    assert abs(obs - order) < 0.2, (errs, obs)
