@@ -218,8 +218,8 @@ def main():
         "dtype": "f64" if prec == apdvm.FP64 else "f32+f64",
         "data": "synthetic",
         "config": dict(cfg, precision=args.precision,
-                       tile_rows={k: tiles[k] for k in ("helmholtz_rhs", "update_uq",
-                                                        "stage_terms_relax_v")}),
+                       tile_rows={k: tiles[k] for k in apdvm.TUNED_STENCIL},
+                       threads={k: tiles["threads_" + k] for k in apdvm.TUNED_STENCIL}),
         "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

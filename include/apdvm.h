@@ -200,22 +200,29 @@ apdvm_status apdvm_timing_read(apdvm_ctx *ctx, int64_t *launches, double *total_
 apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
                            int32_t *launches_per_step);
 
-/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each candidate
- * tile height (8 or 16 rows of 64 cells), and for the Helmholtz columns the four-step
- * form (classes 2-4) against the single pass (class 8, only when every ny <= 2048), are
- * timed with HIP events over steps_per_trial steps of the live simulation; the fastest
- * is kept.  The state, the step counter
- * and the launch mode are restored afterwards (this call allocates a temporary device
- * copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a
- * previous choice for the same context shape is read from it and no trial runs; new
- * choices are appended to it.  choice (may be NULL, else APDVM_NUM_KERNEL_CLASSES
- * entries) receives the tile height of the stencil classes and 1 / 0 for the FFT column
- * classes in use / not in use.  Needs fields on every instance. */
+/* Launch-shape choices as apdvm_autotune reports them and apdvm_set_tuning takes them
+ * (APDVM_TUNING_LEN entries): entries 0..8 per kernel class, with the tile height (8 or
+ * 16 rows of 64 cells) for the stencil classes 0, 6 and 7 and 1 / 0 for the FFT column
+ * classes in use / not in use (the other entries read 1); entries 9, 10 and 11 the
+ * workgroup threads (256 or 512) of classes 0, 6 and 7.  Shapes: 64 x 8 on 256 threads,
+ * 64 x 16 on 256, 64 x 16 on 512. */
+#define APDVM_TUNING_LEN 12
+
+/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each shape, and
+ * for the Helmholtz columns the four-step form (classes 2-4) against the single pass
+ * (class 8, only when every ny <= 2048), are timed with HIP events over steps_per_trial
+ * steps of the live simulation; the fastest is kept.  The state, the step counter and
+ * the launch mode are restored afterwards (this call allocates a temporary device copy
+ * of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
+ * choice for the same context shape is read from it and no trial runs; new choices are
+ * appended to it.  choice (NULL, or APDVM_TUNING_LEN entries) receives the choice.
+ * Needs fields on every instance. */
 apdvm_status apdvm_autotune(apdvm_ctx *ctx, int32_t steps_per_trial, int32_t *choice);
 
-/* Set the launch shapes directly, in the format apdvm_autotune reports: tile height 8
- * or 16 for classes 0, 6 and 7, and choice[8] != 0 for the single-pass Helmholtz
- * columns (needs every ny <= 2048); other entries are ignored.  Host-only. */
+/* Set the launch shapes directly (APDVM_TUNING_LEN entries, the format apdvm_autotune
+ * reports): a (tile height, threads) pair among the shapes above for classes 0, 6 and 7,
+ * and choice[8] != 0 for the single-pass Helmholtz columns (needs every ny <= 2048); the
+ * other entries are ignored.  APDVM_ERR_ARG for any other pair.  Host-only. */
 apdvm_status apdvm_set_tuning(apdvm_ctx *ctx, const int32_t *choice);
 
 /* Release the context (and the workspace if the library allocated it).  NULL ok. */

@@ -28,6 +28,10 @@ FP64, FP32_SPLIT = 0, 1
 KERNEL_CLASSES = ("helmholtz_rhs", "fft_rows_forward", "fft_columns_a", "fft_columns_b",
                   "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
                   "stage_terms_relax_v", "fft_columns_single_pass")
+# Entries of the launch-shape choice array: one per kernel class, then the workgroup
+# threads of the three stencil classes.
+TUNED_STENCIL = ("helmholtz_rhs", "update_uq", "stage_terms_relax_v")
+TUNING_KEYS = KERNEL_CLASSES + tuple("threads_" + k for k in TUNED_STENCIL)
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_VELSET", 3: "ERR_TABLEAU", 4: "ERR_NOMEM",
           5: "ERR_HIP", 6: "ERR_NONFINITE", 7: "ERR_STATE"}
 
@@ -308,24 +312,28 @@ class Simulation:
         return b.value, n.value
 
     def autotune(self, steps_per_trial=3):
-        """Pick the tile height of each stencil kernel class by timing; returns a dict
-        class name -> tile rows."""
-        arr = (c_int32 * len(KERNEL_CLASSES))()
+        """Pick the launch shapes by timing; returns a dict over TUNING_KEYS: tile rows of
+        each stencil class, 1 / 0 for the FFT column forms in use, and the workgroup
+        threads of each stencil class."""
+        arr = (c_int32 * len(TUNING_KEYS))()
         _check(lib().apdvm_autotune(self.ctx, int(steps_per_trial), arr), "autotune")
-        return dict(zip(KERNEL_CLASSES, list(arr)))
+        return dict(zip(TUNING_KEYS, list(arr)))
 
-    def set_tuning(self, tile_rows=16, single_pass_columns=False):
-        """Force the launch shapes: tile_rows is one tile height for every stencil class
-        or a dict in the format autotune() returns (then single_pass_columns is read from
-        it); single_pass_columns selects the form of the Helmholtz column FFT."""
-        arr = (c_int32 * len(KERNEL_CLASSES))()
+    def set_tuning(self, tile_rows=16, single_pass_columns=False, threads=256):
+        """Force the launch shapes: tile_rows (8 or 16) and threads (256, or 512 with 16
+        rows) for every stencil class, or a dict in the format autotune() returns (then
+        the other arguments are read from it); single_pass_columns selects the form of
+        the Helmholtz column FFT."""
+        arr = (c_int32 * len(TUNING_KEYS))()
         if isinstance(tile_rows, dict):
-            for k, name in enumerate(KERNEL_CLASSES):
-                arr[k] = int(tile_rows[name])
+            for k, name in enumerate(TUNING_KEYS):
+                arr[k] = int(tile_rows.get(name, 256 if name.startswith("threads_") else 1))
             single_pass_columns = bool(tile_rows["fft_columns_single_pass"])
         else:
             for k in range(len(KERNEL_CLASSES)):
                 arr[k] = int(tile_rows)
+            for k in range(len(KERNEL_CLASSES), len(TUNING_KEYS)):
+                arr[k] = int(threads)
         arr[KERNEL_CLASSES.index("fft_columns_single_pass")] = 1 if single_pass_columns else 0
         _check(lib().apdvm_set_tuning(self.ctx, arr), "set_tuning")
 

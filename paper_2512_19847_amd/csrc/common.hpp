@@ -34,10 +34,9 @@ constexpr int kMaxStages = 8;
 constexpr int kMaxPasses = 16;
 constexpr int kNoSlot = -1;
 
-// Stencil tiles: TX x TY interior cells, halo kHalo (WENO5 needs 3 on each side).
+// Stencil tiles: kTileX x TY interior cells, halo kHalo (WENO5 needs 3 on each side).
 constexpr int kTileX = 64;
 constexpr int kHalo = 3;
-constexpr int kStencilThreads = 256;
 
 // FFT row workgroups: capacity in complex float64 values held in LDS, and threads.
 // The large form takes rows longer than kRowSmallCap.

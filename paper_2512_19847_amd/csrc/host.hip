@@ -28,6 +28,17 @@ hipError_t launch_stage_terms(int, int, int, const Inst *, const Work *, int, co
 
 // Tile heights the stencil kernels are built for; the autotuner picks one per class.
 constexpr int kTileRows[2] = {8, 16};
+// Launch shapes of the stencil classes: tile rows and workgroup threads; the tile table
+// of a shape is the one of its tile height.
+constexpr int kNumShapes = 3;
+constexpr int kShapeRows[kNumShapes] = {8, 16, 16};
+constexpr int kShapeThreads[kNumShapes] = {256, 256, 512};
+inline int shape_table(int si) { return kShapeRows[si] == kTileRows[0] ? 0 : 1; }
+inline int shape_of(int rows, int threads) {
+  for (int si = 0; si < kNumShapes; ++si)
+    if (kShapeRows[si] == rows && kShapeThreads[si] == threads) return si;
+  return -1;
+}
 hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
                              int, const Work *, int, const ArgsSolve &, hipStream_t);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
@@ -396,7 +407,7 @@ struct apdvm_ctx {
   int col_mode = 0;        // 0: four-step column FFT (3 launches), 1: single pass
   bool col_full_ok = false;  // every instance has columns short enough for one pass
   bool big_rows = false;
-  int ty_index[apdvm::kNumClasses];  // tile table used by each stencil class
+  int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
   std::vector<int> tile_first, tile_count;
@@ -608,13 +619,13 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
 template <typename T>
 hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
   hipStream_t st = c->stream;
-  const int ti = c->ty_index[l.cls];
-  const int ty = kTileRows[ti];
+  const int si = c->shape[l.cls];
+  const int ti = shape_table(si);
   Work *tiles = c->d_tiles[ti];
   const int nt = c->ntiles[ti];
   switch (l.cls) {
     case kHelmRhs:
-      return launch_helmholtz_rhs<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.r, st);
+      return launch_helmholtz_rhs<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.r, st);
     case kColsFull:
       return launch_solve_part(5, c->big_rows, c->d_inst, c->d_rows, c->nrows, c->d_colf,
                                c->ncolf, c->d_colb, c->ncolb, l.sv, st);
@@ -626,9 +637,9 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
       return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
                                c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
     case kUpdateUQ:
-      return launch_update_uq<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st);
+      return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st);
     default:
-      return launch_stage_terms<T>(ty, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st);
+      return launch_stage_terms<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st);
   }
 }
 
@@ -912,7 +923,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   // carve the workspace
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
   c->big_rows = big_rows(n, cfgs);
-  for (int k = 0; k < kNumClasses; ++k) c->ty_index[k] = 1;
+  for (int k = 0; k < kNumClasses; ++k) c->shape[k] = 1;
   c->wo = weno_order_of(cfgs[0]);
   c->co = central_order_of(cfgs[0]);
   std::vector<Work> tiles8;
@@ -1340,7 +1351,7 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
 
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes3 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
@@ -1364,8 +1375,9 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
           line[key.size()] == '|') {
         std::istringstream rest(line.substr(key.size() + 1));
         int t[3], mode = 0;
-        if (rest >> t[0] >> t[1] >> t[2] >> mode) {
-          for (int m = 0; m < 3; ++m) c->ty_index[classes[m]] = t[m] == kTileRows[0] ? 0 : 1;
+        if (rest >> t[0] >> t[1] >> t[2] >> mode && t[0] >= 0 && t[0] < kNumShapes &&
+            t[1] >= 0 && t[1] < kNumShapes && t[2] >= 0 && t[2] < kNumShapes) {
+          for (int m = 0; m < 3; ++m) c->shape[classes[m]] = t[m];
           set_col_mode(c, (mode && c->col_full_ok) ? 1 : 0);
           cached = true;
         }
@@ -1407,9 +1419,9 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     for (int m = 0; ok && m < 3; ++m) {
       const int cls = classes[m];
       double best = 1e300;
-      int best_ti = 1;
-      for (int ti = 0; ok && ti < 2; ++ti) {
-        c->ty_index[cls] = ti;
+      int best_si = 1;
+      for (int si = 0; ok && si < kNumShapes; ++si) {
+        c->shape[cls] = si;
         ok = apdvm_step(c, 1) == APDVM_OK;  // warm-up with this choice
         ok = ok && apdvm_timing_enable(c, cls) == APDVM_OK;
         ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
@@ -1418,10 +1430,10 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
         ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
         if (ok && ms < best) {
           best = ms;
-          best_ti = ti;
+          best_si = si;
         }
       }
-      c->ty_index[cls] = best_ti;
+      c->shape[cls] = best_si;
     }
     if (ok && c->col_full_ok) {
       double tmode[2] = {0.0, 0.0};
@@ -1451,9 +1463,8 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     if (!ok) return APDVM_ERR_HIP;
     if (cache) {
       std::ofstream out(cache, std::ios::app);
-      out << key << "|" << kTileRows[c->ty_index[classes[0]]] << " "
-          << kTileRows[c->ty_index[classes[1]]] << " " << kTileRows[c->ty_index[classes[2]]]
-          << " " << c->col_mode << "\n";
+      out << key << "|" << c->shape[classes[0]] << " " << c->shape[classes[1]] << " "
+          << c->shape[classes[2]] << " " << c->col_mode << "\n";
     }
   }
   // the graphs captured the old launch shapes
@@ -1463,10 +1474,14 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       c->graph_exec[p] = nullptr;
     }
   if (choice) {
-    for (int k = 0; k < kNumClasses; ++k) choice[k] = kTileRows[c->ty_index[k]];
+    for (int k = 0; k < kNumClasses; ++k) choice[k] = 1;
     // for the FFT column classes report which form runs: 1 used, 0 not used
     choice[kColsA] = choice[kColsB] = choice[kColsAInv] = c->col_mode ? 0 : 1;
     choice[kColsFull] = c->col_mode ? 1 : 0;
+    for (int m = 0; m < 3; ++m) {
+      choice[classes[m]] = kShapeRows[c->shape[classes[m]]];
+      choice[kNumClasses + m] = kShapeThreads[c->shape[classes[m]]];
+    }
   }
   return APDVM_OK;
 }
@@ -1474,13 +1489,14 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
 apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
   if (!c || !choice) return APDVM_ERR_ARG;
   const int classes[3] = {kHelmRhs, kUpdateUQ, kStageTerms};
-  for (int m = 0; m < 3; ++m)
-    if (choice[classes[m]] != kTileRows[0] && choice[classes[m]] != kTileRows[1])
-      return APDVM_ERR_ARG;
+  int si[3];
+  for (int m = 0; m < 3; ++m) {
+    si[m] = shape_of(choice[classes[m]], choice[kNumClasses + m]);
+    if (si[m] < 0) return APDVM_ERR_ARG;
+  }
   const int mode = choice[kColsFull] ? 1 : 0;
   if (mode && !c->col_full_ok) return APDVM_ERR_ARG;
-  for (int m = 0; m < 3; ++m)
-    c->ty_index[classes[m]] = choice[classes[m]] == kTileRows[0] ? 0 : 1;
+  for (int m = 0; m < 3; ++m) c->shape[classes[m]] = si[m];
   set_col_mode(c, mode);
   for (int p = 0; p < 2; ++p)
     if (c->graph_exec[p]) {

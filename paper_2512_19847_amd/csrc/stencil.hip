@@ -3,16 +3,17 @@
 // space discretisation of Section 3.2: WENO5 (Jiang-Shu) reconstruction of the
 // Lax-Friedrichs split fluxes and fourth-order central differences.
 //
-// Tiling: a workgroup of 256 threads owns a 64 x TY tile of one instance (TY = 8 or 16,
-// chosen per kernel class by the host autotuner).  Every input plane is staged once in
-// LDS with a 3-cell periodic halo (WENO5 reads 3 cells on each side of a cell; the
-// central operators 2, corners included for the mixed derivative).  Planes that only
-// feed WENO fluxes are staged multiplied by 1/2, which is exact in binary floating point,
-// so the split fluxes (f +- w)/2 cost one add per cell and round exactly like
-// (f +- w) * 0.5.  WENO numerical fluxes are computed once per face into LDS; the x and
-// y faces of one divergence share one balanced index space.  Thread t owns column
-// t % 64 and rows t / 64 + 4 k of the tile: every wavefront covers full 64-cell row
-// segments, so all global loads and stores are row-contiguous.
+// Tiling: a workgroup of NT threads owns a 64 x TY tile of one instance (64 x 8 on 256
+// threads, 64 x 16 on 256 or 512, chosen per kernel class by the host autotuner).  Every
+// input plane is staged once in LDS with a 3-cell periodic halo (WENO5 reads 3 cells on
+// each side of a cell; the central operators 2, corners included for the mixed
+// derivative).  Planes that only feed WENO fluxes are staged multiplied by 1/2, which is
+// exact in binary floating point, so the split fluxes (f +- w)/2 cost one add per cell
+// and round exactly like (f +- w) * 0.5.  WENO numerical fluxes are computed once per
+// face into LDS; the x and y faces of one divergence share one balanced index space.
+// Thread t owns column t % 64 and rows t / 64 + (NT / 64) k of the tile: every
+// wavefront covers full 64-cell row segments, so all global loads and stores are
+// row-contiguous.
 //
 // Precision: T is the transport type (double or float).  theta, the Helmholtz
 // right-hand side and every history sum feeding an implicit relaxation or the
@@ -229,8 +230,9 @@ __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf)
   return sf * flux3_sym(f[stride], f[2 * stride], f[3 * stride], f[4 * stride]);
 }
 
-// LDS tile geometry for a 64 x TY tile with a 3-cell halo.
-template <int TY>
+// LDS tile geometry for a 64 x TY tile with a 3-cell halo, worked on by NT threads
+// (NT / 64 wavefronts; thread t owns column t % 64 and rows t / 64 + (NT / 64) k).
+template <int TY, int NT>
 struct Geo {
   static constexpr int W = kTileX + 2 * kHalo;
   static constexpr int HT = TY + 2 * kHalo;
@@ -238,7 +240,9 @@ struct Geo {
   static constexpr int FXN = TY * (kTileX + 1);       // x faces
   static constexpr int FXP = (FXN + 63) / 64 * 64;    // x faces padded to whole waves
   static constexpr int FYN = (TY + 1) * kTileX;       // y faces
-  static constexpr int ROWS = TY / 4;                 // rows per thread
+  static constexpr int WV = NT / 64;                  // wavefronts
+  static constexpr int ROWS = TY / WV;                // rows per thread
+  static_assert(ROWS * WV == TY, "tile rows must split evenly over the wavefronts");
   __device__ static int at(int lx, int ly) { return (ly + kHalo) * W + lx + kHalo; }
 };
 
@@ -246,17 +250,17 @@ struct Geo {
 // global load of the thread into registers, store() converts, scales and writes them to
 // LDS.  Loads of several planes (and of later phases) are thus in flight together
 // instead of each waiting for the one before.
-template <int TY, int NP, typename G>
+template <int TY, int NT, int NP, typename G>
 struct Stage {
-  using Gm = Geo<TY>;
-  static constexpr int IT = (Gm::PL + kStencilThreads - 1) / kStencilThreads;
+  using Gm = Geo<TY, NT>;
+  static constexpr int IT = (Gm::PL + NT - 1) / NT;
   G v[NP][IT];
   __device__ __forceinline__ void load(const Gp<const G> *plane, int nx, int ny, int x0, int y0) {
     const bool inner = x0 >= kHalo && x0 + kTileX + kHalo <= nx && y0 >= kHalo &&
                        y0 + TY + kHalo <= ny;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * kStencilThreads;
+      const int idx = threadIdx.x + it * NT;
       const int ly = idx / Gm::W;
       const int lx = idx - ly * Gm::W;
       int gx = x0 + lx - kHalo, gy = y0 + ly - kHalo;
@@ -275,7 +279,7 @@ struct Stage {
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
-        const int idx = threadIdx.x + it * kStencilThreads;
+        const int idx = threadIdx.x + it * NT;
         if (idx < Gm::PL) lds[p][idx] = sc * (S)v[p][it];
       }
   }
@@ -283,11 +287,11 @@ struct Stage {
 
 // x faces (TY rows x 65) and y faces (TY + 1 rows x 64) of two fluxes in one index
 // space; the x part is padded to whole wavefronts so no wavefront mixes the two.
-template <int TY, int WO, typename T, bool DX, bool DY>
+template <int TY, int NT, int WO, typename T, bool DX, bool DY>
 __device__ __forceinline__ void faces(T *fx, T *fy, const T *fxf, const T *fxw, T sx,
                                       const T *fyf, const T *fyw, T sy) {
-  using Gm = Geo<TY>;
-  for (int idx = threadIdx.x; idx < Gm::FXP + Gm::FYN; idx += kStencilThreads) {
+  using Gm = Geo<TY, NT>;
+  for (int idx = threadIdx.x; idx < Gm::FXP + Gm::FYN; idx += NT) {
     if (idx < Gm::FXP) {
       if (idx < Gm::FXN) {
         const int ly = idx / (kTileX + 1);
@@ -382,15 +386,15 @@ __device__ __forceinline__ Gp<double> dplane(const Inst &I, int slot) {
 
 // ------------------------------------------------------------------ step 2 RHS
 
-template <typename T, int TY, int CO>
-__global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *__restrict__ insts,
+template <typename T, int TY, int NT, int CO>
+__global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ insts,
                                                                    const Work *__restrict__ work,
                                                                    int nwork, ArgsR a) {
-  using Gm = Geo<TY>;
+  using Gm = Geo<TY, NT>;
   __shared__ T sV1[Gm::PL], sV2[Gm::PL];
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
-  Stage<TY, 2, T> st;
+  Stage<TY, NT, 2, T> st;
   {
     const Gp<const T> g[2] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
     st.load(g, I.nx, I.ny, wk.a, wk.b);
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
   double base[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int gy = wk.b + ty0 + 4 * r;
+    const int gy = wk.b + ty0 + Gm::WV * r;
     base[r] = 0.0;
     if (col && gy < I.ny) {
       const long long g = (long long)gy * I.nx + gx;
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
   const T ihx2 = T(C::f2(I.ihx)), ihy2 = T(C::f2(I.ihy));
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + 4 * r;
+    const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= I.ny) break;
     const int c = Gm::at(tx, ly);
@@ -441,11 +445,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_helmholtz_rhs(const Inst *_
 
 // ------------------------------------------------------------------ steps 3 and 4
 
-template <typename T, int TY, int WO, int CO>
-__global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__restrict__ insts,
+template <typename T, int TY, int NT, int WO, int CO>
+__global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
-  using Gm = Geo<TY>;
+  using Gm = Geo<TY, NT>;
   // v1, v2 and the partner velocity (halved for the fluxes); theta reuses the partner
   // planes once the fluxes that need them are done.
   __shared__ T sV1[Gm::PL], sV2[Gm::PL];
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
   {
-    Stage<TY, 4, T> st;
+    Stage<TY, NT, 4, T> st;
     const Gp<const T> g[4] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0]),
                      tplane<T>(I, a.partner[1])};
     st.load(g, nx, ny, wk.a, wk.b);
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   double un1[Gm::ROWS], un2[Gm::ROWS], qn[Gm::ROWS], h1[Gm::ROWS], h2[Gm::ROWS], hg[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int gy = wk.b + ty0 + 4 * r;
+    const int gy = wk.b + ty0 + Gm::WV * r;
     un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
     if (col && gy < ny) {
       const long long g = (long long)gy * nx + gx;
@@ -490,26 +494,26 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   T hu1[Gm::ROWS], hu2[Gm::ROWS], dv[Gm::ROWS];
   // first row of B(v) = (-v1, v2), dissipation on u1
-  faces<TY, WO, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
+  faces<TY, NT, WO, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
-    hu1[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
+    hu1[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
   __syncthreads();
   // second row of B(v) = (v2, v1), dissipation on u2
-  faces<TY, WO, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
+  faces<TY, NT, WO, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
-    hu2[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
+    hu2[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
   __syncthreads();
   // div v without dissipation; theta (float64) loaded meanwhile into the partner planes
-  Stage<TY, 1, double> sth;
+  Stage<TY, NT, 1, double> sth;
   {
     const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
-  faces<TY, WO, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
+  faces<TY, NT, WO, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
   double *sTh = reinterpret_cast<double *>(sP);
   {
     double *l[1] = {sTh};
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
-    dv[r] = face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy);
+    dv[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
 
   if (!col) return;
   using C = Central<CO>;
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
   const double htau = 0.5 * I.tau;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + 4 * r;
+    const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= ny) break;
     const int c = Gm::at(tx, ly);
@@ -554,11 +558,11 @@ __global__ __launch_bounds__(kStencilThreads) void k_update_uq(const Inst *__res
 
 // E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u), D0.u and Ltheta of a known stage, and,
 // fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
-template <typename T, int TY, int WO, int CO>
-__global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__restrict__ insts,
+template <typename T, int TY, int NT, int WO, int CO>
+__global__ __launch_bounds__(NT) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
-  using Gm = Geo<TY>;
+  using Gm = Geo<TY, NT>;
   // sU1 and sU2 are contiguous so that theta (float64) can reuse them at the end.
   __shared__ __align__(16) T sU[2 * Gm::PL];
   __shared__ T sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
   {
-    Stage<TY, 5, T> st;
+    Stage<TY, NT, 5, T> st;
     const Gp<const T> g[5] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1]), tplane<T>(I, a.q),
                      tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
     st.load(g, nx, ny, wk.a, wk.b);
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   double ddb[Gm::ROWS], rv1[Gm::ROWS], rv2[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int gy = wk.b + ty0 + 4 * r;
+    const int gy = wk.b + ty0 + Gm::WV * r;
     ddb[r] = rv1[r] = rv2[r] = 0.0;
     if (col && gy < ny) {
       const long long g = (long long)gy * nx + gx;
@@ -615,18 +619,18 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
   T e1[Gm::ROWS], e2[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
-  faces<TY, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
+  faces<TY, NT, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
-    e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + 4 * r, ihx) + face_dy<TY>(fy, tx, ty0 + 4 * r, ihy));
+    e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy));
   __syncthreads();
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
-  faces<TY, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
+  faces<TY, NT, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + 4 * r;
+    const int ly = ty0 + Gm::WV * r;
     const int c = Gm::at(tx, ly);
     const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
     e1[r] -= T(0.5) * (u2 * u2 - u1 * u1);
@@ -638,12 +642,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   }
   __syncthreads();
   // grad q with dissipation on v1 (x) and v2 (y); theta loaded meanwhile
-  Stage<TY, 1, double> sth;
+  Stage<TY, NT, 1, double> sth;
   if (want_lt) {
     const Gp<const double> g[1] = {dplane(I, a.th)};
     sth.load(g, nx, ny, wk.a, wk.b);
   }
-  faces<TY, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
+  faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
   double *sTh = reinterpret_cast<double *>(sU);
   if (want_lt) {
     double *l[1] = {sTh};
@@ -655,7 +659,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
   const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + 4 * r;
+    const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= ny) break;
     const long long g = (long long)gy * nx + gx;
@@ -683,53 +687,62 @@ __global__ __launch_bounds__(kStencilThreads) void k_stage_terms(const Inst *__r
 
 // ------------------------------------------------------------------ launchers
 
-// Dispatch on the tile height (8 or 16), the WENO order (5 or 3) and the central order
-// (4 or 2); the right-hand side kernel has no WENO flux.
+// Launch shapes (shape index si): 0 = 64 x 8 tiles on 256 threads, 1 = 64 x 16 on 256,
+// 2 = 64 x 16 on 512; then the WENO order (5 or 3) and the central order (4 or 2).  The
+// right-hand side kernel has no WENO flux.
 template <typename T>
-hipError_t launch_helmholtz_rhs(int ty, int wo, int co, const Inst *insts, const Work *work,
+hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const Work *work,
                                 int nwork, const ArgsR &a, hipStream_t st) {
   (void)wo;
-  const dim3 g(nwork), b(kStencilThreads);
-  if (ty == 8 && co == 4)
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 4>), g, b, 0, st, insts, work, nwork, a);
-  else if (ty == 8)
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 2>), g, b, 0, st, insts, work, nwork, a);
-  else if (co == 4)
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 4>), g, b, 0, st, insts, work, nwork, a);
-  else
-    hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 2>), g, b, 0, st, insts, work, nwork, a);
+  const dim3 g(nwork);
+  const int key = si * 2 + (co == 4 ? 0 : 1);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 256, 4>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 1: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 256, 2>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 2: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 4>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 3: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 2>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 4: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 4>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    default: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+  }
   return hipGetLastError();
 }
 
-#define APDVM_DISPATCH(KERNEL, ...)                                                        \
-  do {                                                                                     \
-    const dim3 g(nwork), b(kStencilThreads);                                               \
-    const int key = (ty == 8 ? 0 : 4) + (wo == 5 ? 0 : 2) + (co == 4 ? 0 : 1);              \
-    switch (key) {                                                                         \
-      case 0: hipLaunchKernelGGL((KERNEL<T, 8, 5, 4>), g, b, 0, st, __VA_ARGS__); break;    \
-      case 1: hipLaunchKernelGGL((KERNEL<T, 8, 5, 2>), g, b, 0, st, __VA_ARGS__); break;    \
-      case 2: hipLaunchKernelGGL((KERNEL<T, 8, 3, 4>), g, b, 0, st, __VA_ARGS__); break;    \
-      case 3: hipLaunchKernelGGL((KERNEL<T, 8, 3, 2>), g, b, 0, st, __VA_ARGS__); break;    \
-      case 4: hipLaunchKernelGGL((KERNEL<T, 16, 5, 4>), g, b, 0, st, __VA_ARGS__); break;   \
-      case 5: hipLaunchKernelGGL((KERNEL<T, 16, 5, 2>), g, b, 0, st, __VA_ARGS__); break;   \
-      case 6: hipLaunchKernelGGL((KERNEL<T, 16, 3, 4>), g, b, 0, st, __VA_ARGS__); break;   \
-      default: hipLaunchKernelGGL((KERNEL<T, 16, 3, 2>), g, b, 0, st, __VA_ARGS__); break;  \
-    }                                                                                      \
+#define APDVM_ONE(KERNEL, TY, NT, WO, CO, ...) \
+  hipLaunchKernelGGL((KERNEL<T, TY, NT, WO, CO>), g, dim3(NT), 0, st, __VA_ARGS__)
+#define APDVM_DISPATCH(KERNEL, ...)                                                       \
+  do {                                                                                    \
+    const dim3 g(nwork);                                                                  \
+    const int key = si * 4 + (wo == 5 ? 0 : 2) + (co == 4 ? 0 : 1);                        \
+    switch (key) {                                                                        \
+      case 0: APDVM_ONE(KERNEL, 8, 256, 5, 4, __VA_ARGS__); break;                         \
+      case 1: APDVM_ONE(KERNEL, 8, 256, 5, 2, __VA_ARGS__); break;                         \
+      case 2: APDVM_ONE(KERNEL, 8, 256, 3, 4, __VA_ARGS__); break;                         \
+      case 3: APDVM_ONE(KERNEL, 8, 256, 3, 2, __VA_ARGS__); break;                         \
+      case 4: APDVM_ONE(KERNEL, 16, 256, 5, 4, __VA_ARGS__); break;                        \
+      case 5: APDVM_ONE(KERNEL, 16, 256, 5, 2, __VA_ARGS__); break;                        \
+      case 6: APDVM_ONE(KERNEL, 16, 256, 3, 4, __VA_ARGS__); break;                        \
+      case 7: APDVM_ONE(KERNEL, 16, 256, 3, 2, __VA_ARGS__); break;                        \
+      case 8: APDVM_ONE(KERNEL, 16, 512, 5, 4, __VA_ARGS__); break;                        \
+      case 9: APDVM_ONE(KERNEL, 16, 512, 5, 2, __VA_ARGS__); break;                        \
+      case 10: APDVM_ONE(KERNEL, 16, 512, 3, 4, __VA_ARGS__); break;                       \
+      default: APDVM_ONE(KERNEL, 16, 512, 3, 2, __VA_ARGS__); break;                       \
+    }                                                                                     \
   } while (0)
 
 template <typename T>
-hipError_t launch_update_uq(int ty, int wo, int co, const Inst *insts, const Work *work,
+hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Work *work,
                             int nwork, const ArgsUQ &a, hipStream_t st) {
   APDVM_DISPATCH(k_update_uq, insts, work, nwork, a);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_stage_terms(int ty, int wo, int co, const Inst *insts, const Work *work,
+hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const Work *work,
                               int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st) {
   APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
   return hipGetLastError();
 }
 #undef APDVM_DISPATCH
+#undef APDVM_ONE
 
 #define APDVM_INST(T)                                                                           \
   template hipError_t launch_helmholtz_rhs<T>(int, int, int, const Inst *, const Work *, int,  \
