@@ -12,6 +12,10 @@ value = 6 * sum(nx * ny) * K / seconds   (cell-population updates/s, Q = 6)
 roofline: the kernel class with the largest share of step time is bracketed by HIP
 events on the library's stream during the timed region; achieved = its algorithmic
 bytes per launch (every plane it must read or write, once) / its mean duration.
+roofline.traffic: HBM bytes per launch of that kernel from the rocprofv3 FETCH_SIZE and
+WRITE_SIZE runs recorded under profiles/ (each scaled by what the counter reads for a
+device copy of known size), reported only for the workload, precision and kernel they
+were taken on and while the kernel sources still hash to the recorded value; else null.
 cpu_baseline: the FP64 NumPy oracle on a bounded sample of the same workload, on the
 host (one core: NumPy's elementwise kernels and pocketfft are single-threaded).
 """
@@ -30,6 +34,27 @@ sys.path.insert(0, ROOT)
 METRIC = "IMEX-RK cell-pop updates/s + %HBM roofline; FP32-split/batched vs FP64"
 UNIT = "cell-population updates/s"
 HBM_PEAK_GBS = 8000.0
+
+
+def recorded_traffic(kernel_class, workload_name, precision):
+    """HBM bytes per launch from the recorded counter runs, or None when they do not
+    apply to this kernel and workload or the kernel sources changed since."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_counters_*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if (rec.get("kernel_class") != kernel_class or rec.get("workload") != workload_name
+                or rec.get("precision") != precision):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["source_sha256"]:
+            return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def workload(name):
@@ -140,7 +165,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is a design note, not part of this build", file=sys.stderr)
+              "decomposition is documented as a design and not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -222,7 +247,9 @@ def main():
                        threads={k: tiles["threads_" + k] for k in apdvm.TUNED_STENCIL}),
         "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(apdvm.KERNEL_CLASSES[dom], cfg["workload"],
+                                                 args.precision),
                      "bytes_per_launch": per_launch, "mean_launch_us": mean_s * 1e6,
                      "launches_timed": n_dom},
         "finite": finite,
