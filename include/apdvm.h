@@ -204,8 +204,8 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
  * (APDVM_TUNING_LEN entries): entries 0..8 per kernel class, with the tile height (8 or
  * 16 rows of 64 cells) for the stencil classes 0, 6 and 7 and 1 / 0 for the FFT column
  * classes in use / not in use (the other entries read 1); entries 9, 10 and 11 the
- * workgroup threads (256 or 512) of classes 0, 6 and 7.  Shapes: 64 x 8 on 256 threads,
- * 64 x 16 on 256, 64 x 16 on 512. */
+ * workgroup threads (256 or 512) of classes 0, 6 and 7.  Shapes: 64 x 8 or 64 x 16
+ * tiles on 256 or 512 threads. */
 #define APDVM_TUNING_LEN 12
 
 /* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each shape, and

@@ -320,8 +320,8 @@ class Simulation:
         return dict(zip(TUNING_KEYS, list(arr)))
 
     def set_tuning(self, tile_rows=16, single_pass_columns=False, threads=256):
-        """Force the launch shapes: tile_rows (8 or 16) and threads (256, or 512 with 16
-        rows) for every stencil class, or a dict in the format autotune() returns (then
+        """Force the launch shapes: tile_rows (8 or 16) and threads (256 or 512) for every
+        stencil class, or a dict in the format autotune() returns (then
         the other arguments are read from it); single_pass_columns selects the form of
         the Helmholtz column FFT."""
         arr = (c_int32 * len(TUNING_KEYS))()

@@ -30,9 +30,9 @@ hipError_t launch_stage_terms(int, int, int, const Inst *, const Work *, int, co
 constexpr int kTileRows[2] = {8, 16};
 // Launch shapes of the stencil classes: tile rows and workgroup threads; the tile table
 // of a shape is the one of its tile height.
-constexpr int kNumShapes = 3;
-constexpr int kShapeRows[kNumShapes] = {8, 16, 16};
-constexpr int kShapeThreads[kNumShapes] = {256, 256, 512};
+constexpr int kNumShapes = 4;
+constexpr int kShapeRows[kNumShapes] = {8, 16, 16, 8};
+constexpr int kShapeThreads[kNumShapes] = {256, 256, 512, 512};
 inline int shape_table(int si) { return kShapeRows[si] == kTileRows[0] ? 0 : 1; }
 inline int shape_of(int rows, int threads) {
   for (int si = 0; si < kNumShapes; ++si)
@@ -1351,7 +1351,7 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
 
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 shapes3 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes4 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;

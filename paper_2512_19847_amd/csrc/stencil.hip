@@ -3,8 +3,8 @@
 // space discretisation of Section 3.2: WENO5 (Jiang-Shu) reconstruction of the
 // Lax-Friedrichs split fluxes and fourth-order central differences.
 //
-// Tiling: a workgroup of NT threads owns a 64 x TY tile of one instance (64 x 8 on 256
-// threads, 64 x 16 on 256 or 512, chosen per kernel class by the host autotuner).  Every
+// Tiling: a workgroup of NT threads owns a 64 x TY tile of one instance (64 x 8 or
+// 64 x 16 on 256 or 512 threads, chosen per kernel class by the host autotuner).  Every
 // input plane is staged once in LDS with a 3-cell periodic halo (WENO5 reads 3 cells on
 // each side of a cell; the central operators 2, corners included for the mixed
 // derivative).  Planes that only feed WENO fluxes are staged multiplied by 1/2, which is
@@ -688,7 +688,8 @@ __global__ __launch_bounds__(NT) void k_stage_terms(const Inst *__restrict__ ins
 // ------------------------------------------------------------------ launchers
 
 // Launch shapes (shape index si): 0 = 64 x 8 tiles on 256 threads, 1 = 64 x 16 on 256,
-// 2 = 64 x 16 on 512; then the WENO order (5 or 3) and the central order (4 or 2).  The
+// 2 = 64 x 16 on 512, 3 = 64 x 8 on 512; then the WENO order (5 or 3) and the central
+// order (4 or 2).  The
 // right-hand side kernel has no WENO flux.
 template <typename T>
 hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const Work *work,
@@ -702,7 +703,9 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
     case 2: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 4>), g, dim3(256), 0, st, insts, work, nwork, a); break;
     case 3: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 2>), g, dim3(256), 0, st, insts, work, nwork, a); break;
     case 4: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 4>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    default: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 5: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 6: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 512, 4>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    default: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
   }
   return hipGetLastError();
 }
@@ -725,7 +728,11 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
       case 8: APDVM_ONE(KERNEL, 16, 512, 5, 4, __VA_ARGS__); break;                        \
       case 9: APDVM_ONE(KERNEL, 16, 512, 5, 2, __VA_ARGS__); break;                        \
       case 10: APDVM_ONE(KERNEL, 16, 512, 3, 4, __VA_ARGS__); break;                       \
-      default: APDVM_ONE(KERNEL, 16, 512, 3, 2, __VA_ARGS__); break;                       \
+      case 11: APDVM_ONE(KERNEL, 16, 512, 3, 2, __VA_ARGS__); break;                       \
+      case 12: APDVM_ONE(KERNEL, 8, 512, 5, 4, __VA_ARGS__); break;                        \
+      case 13: APDVM_ONE(KERNEL, 8, 512, 5, 2, __VA_ARGS__); break;                        \
+      case 14: APDVM_ONE(KERNEL, 8, 512, 3, 4, __VA_ARGS__); break;                        \
+      default: APDVM_ONE(KERNEL, 8, 512, 3, 2, __VA_ARGS__); break;                        \
     }                                                                                     \
   } while (0)
 

@@ -100,10 +100,10 @@ def test_ragged_nonsquare(eps, tau):
 
 
 @pytest.mark.parametrize("shape", [(8, False), (8, True), (16, True), (16, False, 512),
-                                   (16, True, 512)])
+                                   (16, True, 512), (8, True, 512)])
 def test_every_launch_shape_matches_oracle(shape):
-    """The shapes the autotuner can pick: 64 x 8 tiles on 256 threads, 64 x 16 on 256 or
-    512, four-step or single-pass column FFT; ragged non-square grid, two instances."""
+    """The shapes the autotuner can pick: 64 x 8 or 64 x 16 tiles on 256 or 512 threads,
+    four-step or single-pass column FFT; ragged non-square grid, two instances."""
     cases = [dict(state=wl.random_divfree(96, 72, kmax=4, rms=0.1, seed=31), eps=0.05, tau=0.3,
                   dt=0.01),
              dict(state=wl.random_divfree(48, 36, kmax=4, rms=0.1, seed=32), eps=1e-5, tau=0.05,
