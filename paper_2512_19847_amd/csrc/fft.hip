@@ -123,6 +123,11 @@ __device__ __forceinline__ void stc(Gp<dv2> p, double2 v) {
   *p = t;
 }
 
+// LDS layout of the FFT buffers: one padding element after every 8, so the strided
+// writes of the early Stockham passes (stride R Ns elements of 16 bytes) spread over the
+// banks instead of hitting the same few.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 3); }
+
 // exp(-2 pi i m / n) from the two-level table staged in LDS (lo at t, hi at t + 2^lb).
 __device__ __forceinline__ double2 tw_at(const double2 *t, int lb, int m) {
   return cmul(t[(1 << lb) + (m >> lb)], t[m & ((1 << lb) - 1)]);
@@ -179,7 +184,7 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
       }
       const int jq = dns.q(j), k = j - jq * Ns;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[(j + r * nbf) * es + b * bs];
+      for (int r = 0; r < R; ++r) v[p][r] = buf[lp((j + r * nbf) * es + b * bs)];
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -197,7 +202,7 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
   for (int p = 0; p < NPER; ++p) {
     if (dst[p] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[p] + r * Ns * es] = v[p][r];
+      for (int r = 0; r < R; ++r) buf[lp(dst[p] + r * Ns * es)] = v[p][r];
     }
   }
   __syncthreads();
@@ -238,7 +243,7 @@ template <int CAP, int NT>
 __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
-  __shared__ double2 buf[CAP];
+  __shared__ double2 buf[CAP + CAP / 8];
   __shared__ double2 tws[kTwCap];
   constexpr int E = CAP / NT;
   const Work wk = work[xcd_item_fft(nwork)];
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) buf[idx] = make_double2(ra[e], rb[e]);
+    if (idx < cnt) buf[lp(idx)] = make_double2(ra[e], rb[e]);
   }
   __syncthreads();
   fft_lds<-1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
@@ -273,8 +278,9 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
   const Div dk(K);
   for (int idx = threadIdx.x; idx < np * K; idx += NT) {
     const int p = dk.q(idx), k = idx - p * K;
-    const double2 Z = buf[p * n + (k == h ? h : k)];
-    const double2 W = buf[p * n + (k == 0 ? 0 : n - k)];  // Z[n-k]; its conjugate pairs with Z[k]
+    const double2 Z = buf[lp(p * n + (k == h ? h : k))];
+    // Z[n-k]; its conjugate pairs with Z[k]
+    const double2 W = buf[lp(p * n + (k == 0 ? 0 : n - k))];
     // A = (Z + conj W) / 2, B = (Z - conj W) / 2i: the spectra of the two real rows
     const double2 A = make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
     const double2 B = make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x));
@@ -296,7 +302,7 @@ template <int DIR>
 __global__ __launch_bounds__(kColThreads) void k_cols_a(const Inst *__restrict__ insts,
                                                         const Work *__restrict__ work,
                                                         int nwork, ArgsSolve a) {
-  __shared__ double2 buf[kColCap];
+  __shared__ double2 buf[kColCap + kColCap / 8];
   __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_a(const Inst *__restrict__
 #pragma unroll
   for (int e = 0; e < kColPer; ++e) {
     const int idx = threadIdx.x + e * kColThreads;
-    if (idx < cnt) buf[idx] = make_double2(v[e].x, v[e].y);
+    if (idx < cnt) buf[lp(idx)] = make_double2(v[e].x, v[e].y);
   }
   __syncthreads();
   fft_lds<DIR, true, kColCap, kColThreads>(buf, I.f1, C, C, 1, tws);
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_a(const Inst *__restrict__
     const int idx = threadIdx.x + e * kColThreads;
     if (idx < cnt) {
       const int m = dc.q(idx), c = idx - m * C;
-      stc(S + m * stride + c, buf[idx]);
+      stc(S + m * stride + c, buf[lp(idx)]);
     }
   }
 }
@@ -347,7 +353,7 @@ __device__ __forceinline__ double mode_scale(const Inst &I, double sig, int kx, 
 __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__ insts,
                                                         const Work *__restrict__ work, int nwork,
                                                         ArgsSolve a) {
-  __shared__ double2 buf[kColCap];
+  __shared__ double2 buf[kColCap + kColCap / 8];
   __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
@@ -386,15 +392,15 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
   tw.store(tws, I.f2);
 #pragma unroll
   for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) buf[threadIdx.x + e * kColThreads] = cmul(v[e], w[e]);
+    if (off[e] >= 0) buf[lp(threadIdx.x + e * kColThreads)] = cmul(v[e], w[e]);
   __syncthreads();
   fft_lds<-1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1, tws);
 #pragma unroll
   for (int e = 0; e < kColPer; ++e) {
     const int idx = threadIdx.x + e * kColThreads;
     if (off[e] >= 0) {
-      const double2 z = buf[idx];
-      buf[idx] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
+      const double2 z = buf[lp(idx)];
+      buf[lp(idx)] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
                              : make_double2(z.x * d[e], z.y * d[e]);
     }
   }
@@ -404,7 +410,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
   for (int e = 0; e < kColPer; ++e) {
     if (off[e] >= 0) {
       const double2 c = make_double2(w[e].x, -w[e].y);
-      stc(S + off[e], cmul(buf[threadIdx.x + e * kColThreads], c));
+      stc(S + off[e], cmul(buf[lp(threadIdx.x + e * kColThreads)], c));
     }
   }
 }
@@ -416,7 +422,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__
 __global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restrict__ insts,
                                                            const Work *__restrict__ work,
                                                            int nwork, ArgsSolve a) {
-  __shared__ double2 buf[kColCap];
+  __shared__ double2 buf[kColCap + kColCap / 8];
   __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
@@ -446,15 +452,15 @@ __global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restric
   tw.store(tws, I.fy);
 #pragma unroll
   for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) buf[threadIdx.x + e * kColThreads] = make_double2(v[e].x, v[e].y);
+    if (off[e] >= 0) buf[lp(threadIdx.x + e * kColThreads)] = make_double2(v[e].x, v[e].y);
   __syncthreads();
   fft_lds<-1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
 #pragma unroll
   for (int e = 0; e < kColPer; ++e) {
     const int idx = threadIdx.x + e * kColThreads;
     if (off[e] >= 0) {
-      const double2 z = buf[idx];
-      buf[idx] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
+      const double2 z = buf[lp(idx)];
+      buf[lp(idx)] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
                              : make_double2(z.x * d[e], z.y * d[e]);
     }
   }
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restric
   fft_lds<1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
 #pragma unroll
   for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) stc(S + off[e], buf[threadIdx.x + e * kColThreads]);
+    if (off[e] >= 0) stc(S + off[e], buf[lp(threadIdx.x + e * kColThreads)]);
 }
 
 // ------------------------------------------------------------------ rows inverse
@@ -471,7 +477,7 @@ template <int CAP, int NT>
 __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
-  __shared__ double2 buf[CAP];
+  __shared__ double2 buf[CAP + CAP / 8];
   __shared__ double2 tws[kTwCap];
   constexpr int E = CAP / (2 * NT);
   const Work wk = work[xcd_item_fft(nwork)];
@@ -508,14 +514,14 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
       const int p = dh.q(idx), k = idx - p * h;
       if (k == 0) {
         // kx = 0 and kx = nx/2 are real for a real row
-        buf[p * n] = make_double2(A[e].x, B[e].x);
+        buf[lp(p * n)] = make_double2(A[e].x, B[e].x);
       } else {
-        buf[p * n + k] = make_double2(A[e].x - B[e].y, A[e].y + B[e].x);      // A + i B
-        buf[p * n + n - k] = make_double2(A[e].x + B[e].y, B[e].x - A[e].y);  // conj A + i conj B
+        buf[lp(p * n + k)] = make_double2(A[e].x - B[e].y, A[e].y + B[e].x);      // A + i B
+        buf[lp(p * n + n - k)] = make_double2(A[e].x + B[e].y, B[e].x - A[e].y);  // conj A + i conj B
       }
     }
   }
-  if (pn < np) buf[pn * n + h] = make_double2(AN.x, BN.x);
+  if (pn < np) buf[lp(pn * n + h)] = make_double2(AN.x, BN.x);
   __syncthreads();
   fft_lds<1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
@@ -525,7 +531,7 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
     const int idx = threadIdx.x + e * NT;
     if (idx < np * n) {
       const int o = idx + dn.q(idx) * n;
-      const double2 z = buf[idx];
+      const double2 z = buf[lp(idx)];
       T[o] = z.x;
       T[o + n] = z.y;
     }
