@@ -190,6 +190,12 @@ apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
  * timed.  Synchronises the stream and clears earlier timings. */
 apdvm_status apdvm_timing_enable(apdvm_ctx *ctx, int32_t cls);
 
+/* Bracket the timed class only in every stride-th step (stride >= 1, default 1; every
+ * launch of the class within such a step), counted from apdvm_timing_enable: the events
+ * cost a little time themselves, so a throughput run can sample the class instead of
+ * timing each launch.  Host-only. */
+apdvm_status apdvm_timing_stride(apdvm_ctx *ctx, int32_t stride);
+
 /* Synchronise, then return the number of timed launches since apdvm_timing_enable and
  * the sum of their durations in milliseconds. */
 apdvm_status apdvm_timing_read(apdvm_ctx *ctx, int64_t *launches, double *total_ms);

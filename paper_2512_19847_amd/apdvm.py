@@ -103,6 +103,7 @@ def _declare(L):
     L.apdvm_set_graph.argtypes = [P, c_int32]
     L.apdvm_timing_enable.argtypes = [P, c_int32]
     L.apdvm_timing_read.argtypes = [P, POINTER(c_int64), POINTER(c_double)]
+    L.apdvm_timing_stride.argtypes = [P, c_int32]
     L.apdvm_traffic.argtypes = [P, c_int32, POINTER(c_double), POINTER(c_int32)]
     L.apdvm_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
     L.apdvm_set_tuning.argtypes = [P, POINTER(c_int32)]
@@ -113,7 +114,7 @@ def _declare(L):
                  "apdvm_get_fields", "apdvm_get_fields_device", "apdvm_get_moments",
                  "apdvm_get_populations", "apdvm_get_info", "apdvm_set_step",
                  "apdvm_diagnostics", "apdvm_launches_per_step", "apdvm_set_graph",
-                 "apdvm_timing_enable", "apdvm_timing_read", "apdvm_traffic",
+                 "apdvm_timing_enable", "apdvm_timing_read", "apdvm_timing_stride", "apdvm_traffic",
                  "apdvm_autotune", "apdvm_set_tuning"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -298,6 +299,9 @@ class Simulation:
 
     def timing_enable(self, cls):
         _check(lib().apdvm_timing_enable(self.ctx, int(cls)), "timing_enable")
+
+    def timing_stride(self, stride):
+        _check(lib().apdvm_timing_stride(self.ctx, int(stride)), "timing_stride")
 
     def timing_read(self):
         n, ms = c_int64(), c_double()

@@ -425,6 +425,8 @@ struct apdvm_ctx {
   int timed_class = -1;               // kernel class bracketed by events, -1 none
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t ev_used = 0;
+  int timed_stride = 1;               // bracket the timed class in every timed_stride-th step
+  int64_t timed_steps = 0;            // steps enqueued since apdvm_timing_enable
 };
 
 namespace {
@@ -651,9 +653,9 @@ apdvm_status stage0_terms(apdvm_ctx *c) {
 }
 
 template <typename T>
-apdvm_status run_plan_direct(apdvm_ctx *c, const std::vector<Launch> &plan) {
+apdvm_status run_plan_direct(apdvm_ctx *c, const std::vector<Launch> &plan, bool sample) {
   for (const Launch &l : plan) {
-    const bool timed = c->timed_class == l.cls;
+    const bool timed = sample && c->timed_class == l.cls;
     if (timed) {
       if (c->ev_used == c->events.size()) {
         hipEvent_t a, b;
@@ -708,8 +710,10 @@ apdvm_status enqueue_step(apdvm_ctx *c) {
     if (st != APDVM_OK) return st;
     if (hipGraphLaunch(c->graph_exec[P], c->stream) != hipSuccess) return APDVM_ERR_HIP;
   } else {
-    const apdvm_status st = run_plan_direct<T>(c, c->plan[P]);
+    const bool sample = c->timed_class >= 0 && c->timed_steps % c->timed_stride == 0;
+    const apdvm_status st = run_plan_direct<T>(c, c->plan[P], sample);
     if (st != APDVM_OK) return st;
+    ++c->timed_steps;
   }
   c->parity = 1 - P;
   return APDVM_OK;
@@ -1299,6 +1303,13 @@ apdvm_status apdvm_timing_enable(apdvm_ctx *c, int32_t cls) {
   if (hipStreamSynchronize(c->stream) != hipSuccess) return APDVM_ERR_HIP;
   c->timed_class = cls;
   c->ev_used = 0;
+  c->timed_steps = 0;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_timing_stride(apdvm_ctx *c, int32_t stride) {
+  if (!c || stride < 1) return APDVM_ERR_ARG;
+  c->timed_stride = stride;
   return APDVM_OK;
 }
 
@@ -1414,7 +1425,9 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     };
     const int64_t step0 = c->step;
     const bool graph = c->use_graph;
+    const int stride = c->timed_stride;
     c->use_graph = false;
+    c->timed_stride = 1;
     bool ok = copy_state(true);
     for (int m = 0; ok && m < 3; ++m) {
       const int cls = classes[m];
@@ -1460,6 +1473,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     c->terms_ready = false;
     c->step = step0;
     c->use_graph = graph;
+    c->timed_stride = stride;
     if (!ok) return APDVM_ERR_HIP;
     if (cache) {
       std::ofstream out(cache, std::ios::app);

@@ -166,6 +166,14 @@ def test_timing_hooks_and_traffic():
         n, ms = sim.timing_read()
         assert n == 2 * nl and ms > 0.0
         per[cls] = ms
+    # sampling: with stride 2 only the launches of every second step are bracketed
+    cls2 = max(per, key=per.get)
+    sim.timing_enable(cls2)
+    sim.timing_stride(2)
+    sim.step(4)
+    n2, _ = sim.timing_read()
+    assert n2 == 2 * sim.traffic(cls2)[1]
+    sim.timing_stride(1)
     sim.timing_enable(-1)
     b_all, n_all = sim.traffic(-1)
     assert abs(b_all - total) < 1e-6 * b_all and n_all == sim.launches_per_step() == 8 * 4
