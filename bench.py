@@ -257,7 +257,10 @@ def main():
                      "traffic": recorded_traffic(apdvm.KERNEL_CLASSES[dom], cfg["workload"],
                                                  args.precision),
                      "bytes_per_launch": per_launch, "mean_launch_us": mean_s * 1e6,
-                     "launches_timed": n_dom},
+                     "launches_timed": n_dom,
+                     # every kernel of the step: algorithmic bytes / step time
+                     "step_gbs": total_bytes / (sec / args.steps) / 1e9,
+                     "step_frac": total_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS},
         "finite": finite,
     }
     if args.compare_fp64 and prec != apdvm.FP64:

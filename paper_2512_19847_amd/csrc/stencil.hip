@@ -24,6 +24,22 @@ namespace apdvm {
 
 // ------------------------------------------------------------------ helpers
 
+// Materialises x at this point: left alone, the compiler sinks the arithmetic of x past
+// the next flux round and keeps the LDS values it is made of live instead (more
+// registers, fewer resident waves).
+template <typename T>
+__device__ __forceinline__ void keep(T &x) {
+  asm volatile("" : "+v"(x));
+}
+
+// Resident waves per SIMD the WENO kernels ask the register allocator for.  The 64 x 8
+// tiles on 512 threads leave LDS for three workgroups per CU (six waves per SIMD) when a
+// thread stays within 80 VGPRs; the other shapes are bounded by LDS before registers.
+template <int TY, int NT>
+constexpr int weno_waves_per_eu() {
+  return NT == 512 && TY == 8 ? 6 : 1;
+}
+
 // Work item of this workgroup.  The hardware hands consecutive workgroups to the 8
 // XCDs in turn; this remap gives each XCD a contiguous run of work items so tiles
 // sharing halo rows meet in the same L2.
@@ -446,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
 // ------------------------------------------------------------------ steps 3 and 4
 
 template <typename T, int TY, int NT, int WO, int CO>
-__global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
   using Gm = Geo<TY, NT>;
@@ -471,25 +487,6 @@ __global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = wk.a + tx;
   const bool col = gx < nx;
-  // pointwise inputs of the updates (state n and the stage history), loaded early;
-  // the float64 history sums are formed before the fluxes
-  double un1[Gm::ROWS], un2[Gm::ROWS], qn[Gm::ROWS], h1[Gm::ROWS], h2[Gm::ROWS], hg[Gm::ROWS];
-#pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r) {
-    const int gy = wk.b + ty0 + Gm::WV * r;
-    un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
-    if (col && gy < ny) {
-      const long long g = (long long)gy * nx + gx;
-      un1[r] = (double)tplane<T>(I, a.un[0])[g];
-      un2[r] = (double)tplane<T>(I, a.un[1])[g];
-      qn[r] = (double)tplane<T>(I, a.qn)[g];
-      for (int j = 0; j < a.nH; ++j) {
-        h1[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][0])[g];
-        h2[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][1])[g];
-      }
-      for (int j = 0; j < a.nG; ++j) hg[r] += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
-    }
-  }
   __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   T hu1[Gm::ROWS], hu2[Gm::ROWS], dv[Gm::ROWS];
@@ -497,15 +494,19 @@ __global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts
   faces<TY, NT, WO, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r)
+  for (int r = 0; r < Gm::ROWS; ++r) {
     hu1[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
+    keep(hu1[r]);
+  }
   __syncthreads();
   // second row of B(v) = (v2, v1), dissipation on u2
   faces<TY, NT, WO, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r)
+  for (int r = 0; r < Gm::ROWS; ++r) {
     hu2[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
+    keep(hu2[r]);
+  }
   __syncthreads();
   // div v without dissipation; theta (float64) loaded meanwhile into the partner planes
   Stage<TY, NT, 1, double> sth;
@@ -524,6 +525,25 @@ __global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts
   for (int r = 0; r < Gm::ROWS; ++r)
     dv[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
 
+  // pointwise inputs of the updates (state n and the stage history), loaded after the
+  // fluxes so that they hold no registers through them; float64 history sums
+  double un1[Gm::ROWS], un2[Gm::ROWS], qn[Gm::ROWS], h1[Gm::ROWS], h2[Gm::ROWS], hg[Gm::ROWS];
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int gy = wk.b + ty0 + Gm::WV * r;
+    un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
+    if (col && gy < ny) {
+      const long long g = (long long)gy * nx + gx;
+      un1[r] = (double)tplane<T>(I, a.un[0])[g];
+      un2[r] = (double)tplane<T>(I, a.un[1])[g];
+      qn[r] = (double)tplane<T>(I, a.qn)[g];
+      for (int j = 0; j < a.nH; ++j) {
+        h1[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][0])[g];
+        h2[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][1])[g];
+      }
+      for (int j = 0; j < a.nG; ++j) hg[r] += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
+    }
+  }
   if (!col) return;
   using C = Central<CO>;
   const double ihx12 = C::f1(I.ihx), ihy12 = C::f1(I.ihy);
@@ -559,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_update_uq(const Inst *__restrict__ insts
 // E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u), D0.u and Ltheta of a known stage, and,
 // fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
 template <typename T, int TY, int NT, int WO, int CO>
-__global__ __launch_bounds__(NT) void k_stage_terms(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
   using Gm = Geo<TY, NT>;
@@ -584,8 +604,54 @@ __global__ __launch_bounds__(NT) void k_stage_terms(const Inst *__restrict__ ins
   const int gx = wk.a + tx;
   const bool col = gx < nx;
   const bool want_lt = a.out_lt != kNoSlot;
-  // pointwise inputs, loaded early: D0^2:B(v) for Ltheta, and for the fused step 1
-  // rv = te2 v^n - dt * (its history), formed in float64 now
+  __syncthreads();
+  const T ihx = T(I.ihx), ihy = T(I.ihy);
+  // the staged u is halved: its central derivative carries a factor 2
+  using C = Central<CO>;
+  const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
+  const T qt = T(0.25 * I.tau), te2 = T(I.te2);
+  // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
+  T e1[Gm::ROWS], e2[Gm::ROWS];
+  // first row of B(u) = (-u1, u2), no dissipation
+  faces<TY, NT, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy));
+    keep(e1[r]);
+  }
+  __syncthreads();
+  // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
+  faces<TY, NT, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int ly = ty0 + Gm::WV * r;
+    const int c = Gm::at(tx, ly);
+    const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
+    e1[r] -= T(0.5) * (u2 * u2 - u1 * u1);
+    e2[r] = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2;
+    keep(e1[r]);
+    keep(e2[r]);
+    const int gy = wk.b + ly;
+    if (col && gy < ny)
+      tplane<T>(I, a.out_du)[(long long)gy * nx + gx] =
+          C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
+  }
+  __syncthreads();
+  // grad q with dissipation on v1 (x) and v2 (y); then theta (float64) into the u planes
+  faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
+  double *sTh = reinterpret_cast<double *>(sU);
+  if (want_lt) {
+    Stage<TY, NT, 1, double> sth;
+    const Gp<const double> g[1] = {dplane(I, a.th)};
+    sth.load(g, nx, ny, wk.a, wk.b);
+    double *l[1] = {sTh};
+    sth.store(l, 1.0);
+  }
+  __syncthreads();
+  // pointwise inputs, loaded after the fluxes: D0^2:B(v) for Ltheta, and for the fused
+  // step 1 rv = te2 v^n - dt * (its history), formed in float64
   const double dt = I.dt, te2d = I.te2;
   double ddb[Gm::ROWS], rv1[Gm::ROWS], rv2[Gm::ROWS];
 #pragma unroll
@@ -610,50 +676,6 @@ __global__ __launch_bounds__(NT) void k_stage_terms(const Inst *__restrict__ ins
       }
     }
   }
-  __syncthreads();
-  const T ihx = T(I.ihx), ihy = T(I.ihy);
-  // the staged u is halved: its central derivative carries a factor 2
-  using C = Central<CO>;
-  const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
-  const T qt = T(0.25 * I.tau), te2 = T(I.te2);
-  // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
-  T e1[Gm::ROWS], e2[Gm::ROWS];
-  // first row of B(u) = (-u1, u2), no dissipation
-  faces<TY, NT, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r)
-    e1[r] = qt * (face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy));
-  __syncthreads();
-  // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
-  faces<TY, NT, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + Gm::WV * r;
-    const int c = Gm::at(tx, ly);
-    const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
-    e1[r] -= T(0.5) * (u2 * u2 - u1 * u1);
-    e2[r] = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2;
-    const int gy = wk.b + ly;
-    if (col && gy < ny)
-      tplane<T>(I, a.out_du)[(long long)gy * nx + gx] =
-          C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
-  }
-  __syncthreads();
-  // grad q with dissipation on v1 (x) and v2 (y); theta loaded meanwhile
-  Stage<TY, NT, 1, double> sth;
-  if (want_lt) {
-    const Gp<const double> g[1] = {dplane(I, a.th)};
-    sth.load(g, nx, ny, wk.a, wk.b);
-  }
-  faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
-  double *sTh = reinterpret_cast<double *>(sU);
-  if (want_lt) {
-    double *l[1] = {sTh};
-    sth.store(l, 1.0);
-  }
-  __syncthreads();
   if (!col) return;
   const double ihx2 = C::f2(I.ihx), ihy2 = C::f2(I.ihy);
   const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
