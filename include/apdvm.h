@@ -20,7 +20,10 @@
  *  - Every call returns an apdvm_status.  A call that fails validation changes
  *    nothing.  No entry point throws or aborts.
  *  - Work is enqueued on the stream given at creation.  apdvm_step only enqueues;
- *    the get_* calls synchronise that stream before returning.
+ *    the get_* calls synchronise that stream before returning.  Within a step the
+ *    library may run part of each stage on a second stream of its own, forked from and
+ *    joined back to the creation stream inside the step (see apdvm_set_overlap), so
+ *    ordering against the creation stream is as if every launch were on it.
  *  - A context is not thread-safe: calls on one context must not overlap.
  */
 #ifndef APDVM_H
@@ -133,7 +136,11 @@ apdvm_status apdvm_set_fields_device(apdvm_ctx *ctx, int32_t k, const double *co
  * c_x (c_y^2 - 1/4).  Needs eps > 0. */
 apdvm_status apdvm_set_populations(apdvm_ctx *ctx, int32_t k, const double *F);
 
-/* Enqueue nsteps >= 0 time steps of every instance on the context's stream. */
+/* Enqueue nsteps >= 0 time steps of every instance on the context's stream.  Per
+ * implicit stage: step 1 (fused into the previous stage's terms), then the right-hand
+ * side and the Helmholtz solve of step 2 beside the parts of steps 3 and 4 that do not
+ * involve theta(i) (q(i), and u(i) short of its dt a_ii D0 theta(i) term), then the
+ * completion of u(i) with the stage's reusable terms. */
 apdvm_status apdvm_step(apdvm_ctx *ctx, int64_t nsteps);
 
 /* Copy the six fields of instance k to host arrays (any pointer may be NULL to skip
@@ -172,22 +179,36 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *ctx, int32_t k, double out[8]);
 apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
 
 /* Launch mode.  on = 0 (default): every kernel of a step is launched on its own.
- * on = 1: each step replays a HIP graph of the step's launches, captured on first use;
- * needs a created (non-NULL) stream at apdvm_create, else APDVM_ERR_ARG. */
+ * on = 1: each step replays a HIP graph of the step's launches (with the fork and join
+ * of the second stream as graph dependencies), captured on first use; needs a created
+ * (non-NULL) stream at apdvm_create, else APDVM_ERR_ARG. */
 apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
+
+/* Stream structure of a step.  on = 1 (default): per stage, the Helmholtz right-hand
+ * side and solve run on the context's second stream while the theta-free part of steps 3
+ * and 4 (class 6) runs on the creation stream; the stage-terms launch (class 7) waits for
+ * both.  on = 0: every launch on the creation stream, in the same order.  Results are
+ * identical either way.  apdvm_autotune picks the faster.  Synchronises both streams
+ * when the setting changes. */
+apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
+
+/* Current stream structure (1: solve beside steps 3 and 4, 0: one stream).  Host-only. */
+apdvm_status apdvm_get_overlap(apdvm_ctx *ctx, int32_t *on);
 
 /* Kernel classes of a step, used by the profiling and tuning calls below:
  * 0 step-2 right-hand side, 1 Helmholtz rows forward FFT, 2 Helmholtz column FFT first
  * factor, 3 Helmholtz column FFT second factor with the symbol divide and its inverse,
  * 4 inverse column FFT first factor, 5 Helmholtz rows inverse FFT, 6 steps 3 and 4
- * (u and q updates), 7 stage terms reused by later stages together with step 1 (the
- * relaxation of v) of the next stage, 8 single-pass Helmholtz columns (FFT, symbol
- * divide, inverse FFT; replaces 2-4 when the autotuner picks it). */
+ * short of theta (q, and u without its theta gradient), 7 completion of u with theta and
+ * the stage terms reused by later stages, together with step 1 (the relaxation of v) of
+ * the next stage, 8 single-pass Helmholtz columns (FFT, symbol divide, inverse FFT;
+ * replaces 2-4 when the autotuner picks it). */
 #define APDVM_NUM_KERNEL_CLASSES 9
 
 /* From now on bracket every launch of kernel class cls with a pair of HIP events on
- * the context's stream (cls = -1 stops); graph replay is bypassed while a class is
- * timed.  Synchronises the stream and clears earlier timings. */
+ * the stream the launch runs on (cls = -1 stops); a step whose launches are bracketed
+ * runs launch by launch, other steps replay the graph when graphs are on.  Synchronises
+ * the stream and clears earlier timings. */
 apdvm_status apdvm_timing_enable(apdvm_ctx *ctx, int32_t cls);
 
 /* Bracket the timed class only in every stride-th step (stride >= 1, default 1; every
@@ -217,7 +238,8 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
 /* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each shape, and
  * for the Helmholtz columns the four-step form (classes 2-4) against the single pass
  * (class 8, only when every ny <= 2048), are timed with HIP events over steps_per_trial
- * steps of the live simulation; the fastest is kept.  The state, the step counter and
+ * steps of the live simulation; the fastest is kept.  Then whole steps with and without
+ * the second stream (apdvm_set_overlap) are timed and the faster kept.  The state, the step counter and
  * the launch mode are restored afterwards (this call allocates a temporary device copy
  * of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
  * choice for the same context shape is read from it and no trial runs; new choices are

@@ -101,6 +101,8 @@ def _declare(L):
     L.apdvm_diagnostics.argtypes = [P, c_int32, P]
     L.apdvm_launches_per_step.argtypes = [P, POINTER(c_int32)]
     L.apdvm_set_graph.argtypes = [P, c_int32]
+    L.apdvm_set_overlap.argtypes = [P, c_int32]
+    L.apdvm_get_overlap.argtypes = [P, POINTER(c_int32)]
     L.apdvm_timing_enable.argtypes = [P, c_int32]
     L.apdvm_timing_read.argtypes = [P, POINTER(c_int64), POINTER(c_double)]
     L.apdvm_timing_stride.argtypes = [P, c_int32]
@@ -114,6 +116,7 @@ def _declare(L):
                  "apdvm_get_fields", "apdvm_get_fields_device", "apdvm_get_moments",
                  "apdvm_get_populations", "apdvm_get_info", "apdvm_set_step",
                  "apdvm_diagnostics", "apdvm_launches_per_step", "apdvm_set_graph",
+                 "apdvm_set_overlap", "apdvm_get_overlap",
                  "apdvm_timing_enable", "apdvm_timing_read", "apdvm_timing_stride", "apdvm_traffic",
                  "apdvm_autotune", "apdvm_set_tuning"):
         getattr(L, name).restype = ctypes.c_int
@@ -296,6 +299,15 @@ class Simulation:
 
     def set_graph(self, on):
         _check(lib().apdvm_set_graph(self.ctx, 1 if on else 0), "set_graph")
+
+    def set_overlap(self, on):
+        """Helmholtz solve on a second stream beside the theta-free part of steps 3-4."""
+        _check(lib().apdvm_set_overlap(self.ctx, 1 if on else 0), "set_overlap")
+
+    def overlap(self):
+        on = c_int32()
+        _check(lib().apdvm_get_overlap(self.ctx, ctypes.byref(on)), "get_overlap")
+        return bool(on.value)
 
     def timing_enable(self, cls):
         _check(lib().apdvm_timing_enable(self.ctx, int(cls)), "timing_enable")

@@ -124,37 +124,47 @@ struct ArgsR {
   int out_ddb;    // D0^2:B(v(i))
 };
 
-// Steps 3 and 4:
-// Hu = D_W.B(v(i))[dissipation on u(i-1)] + D0 theta(i)
-// u(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii Hu
+// Steps 3 and 4 short of theta(i), which the Helmholtz solve of the same stage is still
+// producing when this runs:
+// hu = D_W.B(v(i))[dissipation on u(i-1)]
+// u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii hu            (float64 slots)
 // Hq = (tau/2) D0_W.v(i)
 // q(i) = [te2 q^n - dt a_ii Hq - dt sum_j cG_j Gq(j)] kinv,   Gq(j) = Hq(j) + q(j)
+// The stage-terms launch of the stage completes u(i) = u*(i) - dt a_ii D0 theta(i) and
+// Hu(i) = hu + D0 theta(i).
 struct ArgsUQ {
   int stage;
   double aii;
   int v[2];       // v(i), halo 3
   int partner[2]; // u(i-1), halo 3
-  int th;         // theta(i) (float64 slot), halo 2
   int un[2], qn;  // state at time n
   int nH, H[kMaxStages][2];
   double cH[kMaxStages];
   int nG, G[kMaxStages];
   double cG[kMaxStages];
-  int out_u[2], out_q;
-  int out_hu[2], out_gq;  // kNoSlot when no later stage needs them
+  int out_us[2];  // u*(i), float64 slots
+  int out_q;
+  int out_hu[2], out_gq;  // hu and Gq; kNoSlot when no later stage needs them
 };
 
-// Terms of a known stage that later stages reuse:
+// Completion of a stage and its terms that later stages reuse:
+// u(i) = u*(i) - dt a_ii D0 theta(i), Hu(i) = hu + D0 theta(i) (in place),
 // E = (tau/4) D0_W.B(u) + te2 D_W q[dissipation on v] - F(u), D0.u,
-// Ltheta = D0^2:B(v) + D_Delta theta.  The same launch performs step 1 of the next
-// stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients of this
-// stage's E and v in that step (at_{k,j} and a_{k,j}), which stay in registers.
+// Ltheta = D0^2:B(v) + D_Delta theta.  With us[0] == kNoSlot (the terms of a state set)
+// u is read from u[] and nothing of theta is used.  The same launch performs step 1 of
+// the next stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients
+// of this stage's E and v in that step (at_{k,j} and a_{k,j}), which stay in registers.
 struct ArgsE {
-  int u[2], q, v[2];  // halo 3
-  int th;             // float64 slot, halo 2 (only when out_lt != kNoSlot)
+  int us[2];          // u*(i) (float64 slots, halo 3) or kNoSlot
+  int u[2];           // u of a state set (halo 3), when us[0] == kNoSlot
+  int q, v[2];        // halo 3
+  int th;             // theta(i), float64 slot, halo 3 + reach of D0 (with us)
+  double aii;         // a_ii of the stage (with us)
+  int out_u[2];       // u(i) (with us)
+  int hu[2];          // hu in, Hu out, or kNoSlot (with us)
   int ddb;            // D0^2:B(v) of this stage (only when out_lt != kNoSlot)
   int out_e[2];       // kNoSlot when only the fused next step reads E
-  int out_du, out_lt;
+  int out_du, out_lt; // out_lt only with us
   double c_e_next, c_v_next;
 };
 

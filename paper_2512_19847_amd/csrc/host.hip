@@ -179,7 +179,7 @@ struct Layout {
   int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
   int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
   int ddb;
-  int Th[kMaxStages], R, spec;  // float64
+  int Th[kMaxStages], Us[2], R, spec;  // float64
   int ntrans, ndbl;
 };
 
@@ -210,6 +210,8 @@ Layout make_layout(int s) {
     L.Th[j] = d++;
   }
   L.ddb = t++;
+  L.Us[0] = d++;
+  L.Us[1] = d++;
   L.R = d++;
   L.spec = d++;
   L.ntrans = t;
@@ -372,8 +374,15 @@ enum LaunchClass {
   kUpdateUQ = 6, kStageTerms = 7, kColsFull = 8, kNumClasses = 9
 };
 
+// Stream synchronisation entries of a plan (cls = kSync): a fork makes the solve stream
+// wait for the work enqueued so far on the main stream, a join the reverse.
+constexpr int kSync = -1;
+enum SyncKind { kNoSync = 0, kFork = 1, kJoin = 2 };
+
 struct Launch {
   int cls;
+  int sync;   // SyncKind of a kSync entry
+  bool side;  // runs on the solve stream (when the two streams overlap)
   ArgsV v;  // step 1 of the next stage, fused into a stage-terms launch
   ArgsR r;
   ArgsUQ uq;
@@ -427,6 +436,11 @@ struct apdvm_ctx {
   size_t ev_used = 0;
   int timed_stride = 1;               // bracket the timed class in every timed_stride-th step
   int64_t timed_steps = 0;            // steps enqueued since apdvm_timing_enable
+  // Second stream for the Helmholtz solve, forked from and joined to the main stream
+  // once per stage; with overlap off every launch goes to the main stream.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
 };
 
 namespace {
@@ -516,8 +530,10 @@ Launch stage0_launch(const apdvm_ctx *c, int P) {
   Launch l{};
   l.cls = kStageTerms;
   ArgsE &a = l.e;
+  a.us[0] = a.us[1] = kNoSlot;
   a.u[0] = L.st[P][0]; a.u[1] = L.st[P][1]; a.v[0] = L.st[P][2]; a.v[1] = L.st[P][3];
-  a.q = L.st[P][4]; a.th = L.th[P]; a.ddb = kNoSlot;
+  a.q = L.st[P][4]; a.th = kNoSlot; a.ddb = kNoSlot;
+  a.out_u[0] = a.out_u[1] = a.hu[0] = a.hu[1] = kNoSlot;
   a.out_e[0] = e_stored(c, 0) ? L.E[0][0] : kNoSlot;
   a.out_e[1] = e_stored(c, 0) ? L.E[0][1] : kNoSlot;
   a.out_du = L.Du[0];
@@ -527,12 +543,21 @@ Launch stage0_launch(const apdvm_ctx *c, int P) {
   return l;
 }
 
-// Launch list of one step starting from state set P.
+// Launch list of one step starting from state set P.  Per stage: the right-hand side and
+// the Helmholtz solve go to the solve stream while the theta-free part of steps 3 and 4
+// runs on the main stream; the stage-terms launch, which completes u(i) with theta(i),
+// joins the two.
 std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const int s = c->s, Q = 1 - P;
   const double pt = c->cells * (c->split ? 4.0 : 8.0), pd = c->cells * 8.0;
   std::vector<Launch> plan;
+  auto sync = [&](int kind) {
+    Launch l{};
+    l.cls = kSync;
+    l.sync = kind;
+    plan.push_back(l);
+  };
   for (int i = 1; i < s; ++i) {
     const bool last = i == s - 1;
     const int v1 = last ? L.st[Q][2] : L.V[i][0], v2 = last ? L.st[Q][3] : L.V[i][1];
@@ -540,9 +565,12 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const int qi = last ? L.st[Q][4] : L.Q[i];
     const int th = last ? L.th[Q] : L.Th[i];
     const double aii = c->A[i][i];
+    const bool keep = !last && implicit_stored(c, i);
+    sync(kFork);
     // step 2 right-hand side (v(i) comes from the previous stage-terms launch)
     Launch l{};
     l.cls = kHelmRhs;
+    l.side = true;
     ArgsR &ar = l.r;
     ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P]; ar.du0 = L.Du[0];
     for (int j = 1; j < i; ++j) {
@@ -566,26 +594,26 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
       const int k = parts[m];
       l = Launch{};
       l.cls = k;
+      l.side = true;
       l.sv = as;
       l.bytes = (k == kRowsFwd || k == kRowsInv) ? pd + c->spec_bytes : 2 * c->spec_bytes;
       plan.push_back(l);
     }
-    // steps 3 and 4
+    // steps 3 and 4 short of theta(i), beside the solve
     l = Launch{};
     l.cls = kUpdateUQ;
     ArgsUQ &au = l.uq;
     au.stage = i; au.aii = aii; au.v[0] = v1; au.v[1] = v2;
     au.partner[0] = i == 1 ? L.st[P][0] : L.U[i - 1][0];
     au.partner[1] = i == 1 ? L.st[P][1] : L.U[i - 1][1];
-    au.th = th; au.un[0] = L.st[P][0]; au.un[1] = L.st[P][1]; au.qn = L.st[P][4];
+    au.un[0] = L.st[P][0]; au.un[1] = L.st[P][1]; au.qn = L.st[P][4];
     for (int j = 1; j < i; ++j) {
       if (c->A[i][j] != 0.0) {
         au.H[au.nH][0] = L.Hu[j][0]; au.H[au.nH][1] = L.Hu[j][1]; au.cH[au.nH++] = c->A[i][j];
         au.G[au.nG] = L.Gq[j]; au.cG[au.nG++] = c->A[i][j];
       }
     }
-    au.out_u[0] = u1; au.out_u[1] = u2; au.out_q = qi;
-    const bool keep = !last && implicit_stored(c, i);
+    au.out_us[0] = L.Us[0]; au.out_us[1] = L.Us[1]; au.out_q = qi;
     if (keep) {
       au.out_hu[0] = L.Hu[i][0]; au.out_hu[1] = L.Hu[i][1]; au.out_gq = L.Gq[i];
     } else {
@@ -593,22 +621,28 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     }
     // the partner is u^n for the first stage: read once with u^n
     const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
-    l.bytes = (reads + 3 + (keep ? 3 : 0)) * pt + pd;
+    l.bytes = (reads + 1 + (keep ? 3 : 0)) * pt + 2 * pd;
     plan.push_back(l);
-    // terms of this stage for later stages, and step 1 of the next stage; the last
-    // stage's terms are the next step's stage-0 terms
+    sync(kJoin);
+    // u(i) from theta(i), terms of this stage for later stages, and step 1 of the next
+    // stage; the last stage's terms are the next step's stage-0 terms
     l = Launch{};
     l.cls = kStageTerms;
     ArgsE &ae = l.e;
-    ae.u[0] = u1; ae.u[1] = u2; ae.q = qi; ae.v[0] = v1; ae.v[1] = v2; ae.th = th;
-    ae.ddb = L.ddb;
+    ae.us[0] = L.Us[0]; ae.us[1] = L.Us[1]; ae.u[0] = ae.u[1] = kNoSlot;
+    ae.q = qi; ae.v[0] = v1; ae.v[1] = v2; ae.th = th; ae.aii = aii;
+    ae.out_u[0] = u1; ae.out_u[1] = u2;
+    ae.hu[0] = keep ? L.Hu[i][0] : kNoSlot;
+    ae.hu[1] = keep ? L.Hu[i][1] : kNoSlot;
+    ae.ddb = keep ? L.ddb : kNoSlot;
     const int ej = last ? 0 : i;  // stage index of these terms in the step that reads them
     const bool est = e_stored(c, ej);
     ae.out_e[0] = est ? L.E[ej][0] : kNoSlot;
     ae.out_e[1] = est ? L.E[ej][1] : kNoSlot;
     ae.out_du = L.Du[ej];
     ae.out_lt = keep ? L.Lt[i] : kNoSlot;
-    l.bytes = (5 + 1 + (est ? 2 : 0) + (keep ? 2 : 0)) * pt + (keep ? pd : 0.0);
+    // u*, theta; q, v; u, D0.u, E; with keep hu and ddb in, Hu and Ltheta out
+    l.bytes = 3 * pd + (3 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
     if (last)
       fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
     else
@@ -618,9 +652,21 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
   return plan;
 }
 
+hipStream_t stream_of(const apdvm_ctx *c, const Launch &l) {
+  return l.side && c->overlap ? c->side : c->stream;
+}
+
 template <typename T>
 hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
-  hipStream_t st = c->stream;
+  if (l.cls == kSync) {
+    if (!c->overlap) return hipSuccess;
+    hipStream_t from = l.sync == kFork ? c->stream : c->side;
+    hipStream_t to = l.sync == kFork ? c->side : c->stream;
+    hipEvent_t ev = l.sync == kFork ? c->ev_fork : c->ev_join;
+    const hipError_t e = hipEventRecord(ev, from);
+    return e != hipSuccess ? e : hipStreamWaitEvent(to, ev, 0);
+  }
+  hipStream_t st = stream_of(c, l);
   const int si = c->shape[l.cls];
   const int ti = shape_table(si);
   Work *tiles = c->d_tiles[ti];
@@ -663,12 +709,12 @@ apdvm_status run_plan_direct(apdvm_ctx *c, const std::vector<Launch> &plan, bool
           return APDVM_ERR_HIP;
         c->events.push_back({a, b});
       }
-      if (hipEventRecord(c->events[c->ev_used].first, c->stream) != hipSuccess)
+      if (hipEventRecord(c->events[c->ev_used].first, stream_of(c, l)) != hipSuccess)
         return APDVM_ERR_HIP;
     }
     if (run_launch<T>(c, l) != hipSuccess) return APDVM_ERR_HIP;
     if (timed) {
-      if (hipEventRecord(c->events[c->ev_used].second, c->stream) != hipSuccess)
+      if (hipEventRecord(c->events[c->ev_used].second, stream_of(c, l)) != hipSuccess)
         return APDVM_ERR_HIP;
       ++c->ev_used;
     }
@@ -705,16 +751,18 @@ apdvm_status enqueue_step(apdvm_ctx *c) {
     if (st != APDVM_OK) return st;
   }
   const int P = c->parity;
-  if (c->use_graph && c->timed_class < 0) {
+  // a step whose launches of the timed class are bracketed by events runs launch by
+  // launch; every other step replays the graph when graphs are on
+  const bool sample = c->timed_class >= 0 && c->timed_steps % c->timed_stride == 0;
+  if (c->use_graph && !sample) {
     apdvm_status st = ensure_graph<T>(c, P);
     if (st != APDVM_OK) return st;
     if (hipGraphLaunch(c->graph_exec[P], c->stream) != hipSuccess) return APDVM_ERR_HIP;
   } else {
-    const bool sample = c->timed_class >= 0 && c->timed_steps % c->timed_stride == 0;
     const apdvm_status st = run_plan_direct<T>(c, c->plan[P], sample);
     if (st != APDVM_OK) return st;
-    ++c->timed_steps;
   }
+  if (c->timed_class >= 0) ++c->timed_steps;
   c->parity = 1 - P;
   return APDVM_OK;
 }
@@ -908,8 +956,11 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->L = make_layout(c->s);
   c->has_fields.assign(n, 0);
   c->umax.assign(n, 0.0);
-  if (hipGetDevice(&c->device) != hipSuccess) {
-    delete c;
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    apdvm_destroy(c);
     return APDVM_ERR_HIP;
   }
   if (dev_ws) {
@@ -917,7 +968,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     c->ws_bytes = ws_bytes;
   } else {
     if (hipMalloc(&c->ws, need) != hipSuccess) {
-      delete c;
+      apdvm_destroy(c);
       return APDVM_ERR_NOMEM;
     }
     c->own_ws = true;
@@ -1287,7 +1338,9 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
 
 apdvm_status apdvm_launches_per_step(apdvm_ctx *c, int32_t *count) {
   if (!c || !count) return APDVM_ERR_ARG;
-  *count = (int32_t)c->plan[0].size();
+  int32_t n = 0;
+  for (const Launch &l : c->plan[0]) n += l.cls != kSync;
+  *count = n;
   return APDVM_OK;
 }
 
@@ -1295,6 +1348,27 @@ apdvm_status apdvm_set_graph(apdvm_ctx *c, int32_t on) {
   if (!c || (on != 0 && on != 1)) return APDVM_ERR_ARG;
   if (on && c->stream == nullptr) return APDVM_ERR_ARG;  // capture needs a created stream
   c->use_graph = on != 0;
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_set_overlap(apdvm_ctx *c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return APDVM_ERR_ARG;
+  if (c->overlap == (on != 0)) return APDVM_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->side) != hipSuccess)
+    return APDVM_ERR_HIP;
+  c->overlap = on != 0;
+  for (int p = 0; p < 2; ++p)  // the graphs captured the other stream structure
+    if (c->graph_exec[p]) {
+      (void)hipGraphExecDestroy(c->graph_exec[p]);
+      c->graph_exec[p] = nullptr;
+    }
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_get_overlap(apdvm_ctx *c, int32_t *on) {
+  if (!c || !on) return APDVM_ERR_ARG;
+  *on = c->overlap ? 1 : 0;
   return APDVM_OK;
 }
 
@@ -1335,7 +1409,7 @@ apdvm_status apdvm_traffic(apdvm_ctx *c, int32_t cls, double *bytes_per_step,
   double b = 0.0;
   int n = 0;
   for (const Launch &l : c->plan[0]) {
-    if (cls >= 0 && l.cls != cls) continue;
+    if (l.cls == kSync || (cls >= 0 && l.cls != cls)) continue;
     b += l.bytes;
     ++n;
   }
@@ -1362,7 +1436,7 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
 
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 shapes4 prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes4 overlap prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
@@ -1385,11 +1459,12 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() &&
           line[key.size()] == '|') {
         std::istringstream rest(line.substr(key.size() + 1));
-        int t[3], mode = 0;
-        if (rest >> t[0] >> t[1] >> t[2] >> mode && t[0] >= 0 && t[0] < kNumShapes &&
+        int t[3], mode = 0, ov = 1;
+        if (rest >> t[0] >> t[1] >> t[2] >> mode >> ov && t[0] >= 0 && t[0] < kNumShapes &&
             t[1] >= 0 && t[1] < kNumShapes && t[2] >= 0 && t[2] < kNumShapes) {
           for (int m = 0; m < 3; ++m) c->shape[classes[m]] = t[m];
           set_col_mode(c, (mode && c->col_full_ok) ? 1 : 0);
+          if (apdvm_set_overlap(c, ov ? 1 : 0) != APDVM_OK) return APDVM_ERR_HIP;
           cached = true;
         }
       }
@@ -1466,7 +1541,32 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       }
       set_col_mode(c, tmode[1] < tmode[0] ? 1 : 0);
     }
+    // the solve beside steps 3 and 4 or after them: whole steps timed on the main stream
     ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
+    c->use_graph = graph;  // the stream structures compete in the caller's launch mode
+    for (int p = 0; p < 2; ++p)  // graphs of earlier launch shapes
+      if (c->graph_exec[p]) {
+        (void)hipGraphExecDestroy(c->graph_exec[p]);
+        c->graph_exec[p] = nullptr;
+      }
+    if (ok) {
+      double tov[2] = {0.0, 0.0};
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+      for (int on = 0; ok && on < 2; ++on) {
+        ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 1) == APDVM_OK;
+        ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
+        ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
+        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        tov[on] = ms;
+      }
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      ok = ok && apdvm_set_overlap(c, tov[1] <= tov[0] ? 1 : 0) == APDVM_OK;
+    }
     c->parity = P;
     ok = ok && copy_state(false) && hipStreamSynchronize(c->stream) == hipSuccess;
     (void)hipFree(snap);
@@ -1478,7 +1578,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     if (cache) {
       std::ofstream out(cache, std::ios::app);
       out << key << "|" << c->shape[classes[0]] << " " << c->shape[classes[1]] << " "
-          << c->shape[classes[2]] << " " << c->col_mode << "\n";
+          << c->shape[classes[2]] << " " << c->col_mode << " " << (c->overlap ? 1 : 0) << "\n";
     }
   }
   // the graphs captured the old launch shapes
@@ -1523,6 +1623,12 @@ apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
 void apdvm_destroy(apdvm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (int p = 0; p < 2; ++p)
     if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
   for (auto &e : c->events) {

@@ -262,29 +262,30 @@ struct Geo {
   __device__ static int at(int lx, int ly) { return (ly + kHalo) * W + lx + kHalo; }
 };
 
-// Staging of NP planes (with periodic halo) into LDS in two phases: load() issues every
-// global load of the thread into registers, store() converts, scales and writes them to
-// LDS.  Loads of several planes (and of later phases) are thus in flight together
-// instead of each waiting for the one before.
-template <int TY, int NT, int NP, typename G>
+// Staging of NP planes (with periodic halo H) into LDS in two phases: load() issues
+// every global load of the thread into registers, store() converts, scales and writes
+// them to LDS.  Loads of several planes (and of later phases) are thus in flight
+// together instead of each waiting for the one before.  Element idx of the staged
+// (TY + 2H) x (64 + 2H) region is held by thread idx % NT in slot idx / NT.
+template <int TY, int NT, int NP, typename G, int H = kHalo>
 struct Stage {
-  using Gm = Geo<TY, NT>;
-  static constexpr int IT = (Gm::PL + NT - 1) / NT;
+  static constexpr int W = kTileX + 2 * H;
+  static constexpr int PL = W * (TY + 2 * H);
+  static constexpr int IT = (PL + NT - 1) / NT;
   G v[NP][IT];
   __device__ __forceinline__ void load(const Gp<const G> *plane, int nx, int ny, int x0, int y0) {
-    const bool inner = x0 >= kHalo && x0 + kTileX + kHalo <= nx && y0 >= kHalo &&
-                       y0 + TY + kHalo <= ny;
+    const bool inner = x0 >= H && x0 + kTileX + H <= nx && y0 >= H && y0 + TY + H <= ny;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * NT;
-      const int ly = idx / Gm::W;
-      const int lx = idx - ly * Gm::W;
-      int gx = x0 + lx - kHalo, gy = y0 + ly - kHalo;
+      const int ly = idx / W;
+      const int lx = idx - ly * W;
+      int gx = x0 + lx - H, gy = y0 + ly - H;
       if (!inner) {
         gx = wrap(gx, nx);
         gy = wrap(gy, ny);
       }
-      const long long off = idx < Gm::PL ? (long long)gy * nx + gx : 0;
+      const long long off = idx < PL ? (long long)gy * nx + gx : 0;
 #pragma unroll
       for (int p = 0; p < NP; ++p) v[p][it] = plane[p][off];
     }
@@ -296,7 +297,7 @@ struct Stage {
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int idx = threadIdx.x + it * NT;
-        if (idx < Gm::PL) lds[p][idx] = sc * (S)v[p][it];
+        if (idx < PL) lds[p][idx] = sc * (S)v[p][it];
       }
   }
 };
@@ -461,18 +462,19 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
 
 // ------------------------------------------------------------------ steps 3 and 4
 
-template <typename T, int TY, int NT, int WO, int CO>
+// Everything of steps 3 and 4 that does not involve theta(i): q(i) in full, and u(i)
+// short of its theta gradient,
+//   u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii D_W.B(v(i)),
+// so this kernel can run while the Helmholtz solve of the same stage produces theta(i).
+// The stage-terms kernel of the stage subtracts dt a_ii D0 theta(i) from u*(i).
+template <typename T, int TY, int NT, int WO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
   using Gm = Geo<TY, NT>;
-  // v1, v2 and the partner velocity (halved for the fluxes); theta reuses the partner
-  // planes once the fluxes that need them are done.
-  __shared__ T sV1[Gm::PL], sV2[Gm::PL];
-  __shared__ __align__(16) T sP[2 * Gm::PL];
+  // v1, v2 and the partner velocity, halved for the fluxes
+  __shared__ T sV1[Gm::PL], sV2[Gm::PL], sP1[Gm::PL], sP2[Gm::PL];
   __shared__ T fx[Gm::FXN], fy[Gm::FYN];
-  static_assert(sizeof(T) * 2 * Gm::PL >= sizeof(double) * Gm::PL, "theta reuse");
-  T *sP1 = sP, *sP2 = sP + Gm::PL;
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
@@ -508,23 +510,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     keep(hu2[r]);
   }
   __syncthreads();
-  // div v without dissipation; theta (float64) loaded meanwhile into the partner planes
-  Stage<TY, NT, 1, double> sth;
-  {
-    const Gp<const double> g[1] = {dplane(I, a.th)};
-    sth.load(g, nx, ny, wk.a, wk.b);
-  }
+  // div v without dissipation
   faces<TY, NT, WO, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
-  double *sTh = reinterpret_cast<double *>(sP);
-  {
-    double *l[1] = {sTh};
-    sth.store(l, 1.0);
-  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     dv[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
 
+  if (!col) return;
   // pointwise inputs of the updates (state n and the stage history), loaded after the
   // fluxes so that they hold no registers through them; float64 history sums
   double un1[Gm::ROWS], un2[Gm::ROWS], qn[Gm::ROWS], h1[Gm::ROWS], h2[Gm::ROWS], hg[Gm::ROWS];
@@ -532,7 +525,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int gy = wk.b + ty0 + Gm::WV * r;
     un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
-    if (col && gy < ny) {
+    if (gy < ny) {
       const long long g = (long long)gy * nx + gx;
       un1[r] = (double)tplane<T>(I, a.un[0])[g];
       un2[r] = (double)tplane<T>(I, a.un[1])[g];
@@ -544,31 +537,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       for (int j = 0; j < a.nG; ++j) hg[r] += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
     }
   }
-  if (!col) return;
-  using C = Central<CO>;
-  const double ihx12 = C::f1(I.ihx), ihy12 = C::f1(I.ihy);
   const double dt = I.dt, te2 = I.te2, kinv = I.kinv[a.stage], aii = a.aii;
   const double htau = 0.5 * I.tau;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + Gm::WV * r;
-    const int gy = wk.b + ly;
+    const int gy = wk.b + ty0 + Gm::WV * r;
     if (gy >= ny) break;
-    const int c = Gm::at(tx, ly);
     const long long g = (long long)gy * nx + gx;
-    // implicit velocity terms: D_W.B(v) + D0 theta (theta float64)
-    const double Hu1 = (double)hu1[r] + C::d1(sTh, c, 1, ihx12);
-    const double Hu2 = (double)hu2[r] + C::d1(sTh, c, Gm::W, ihy12);
-    const double u1 = un1[r] - dt * (h1[r] + aii * Hu1);
-    const double u2 = un2[r] - dt * (h2[r] + aii * Hu2);
     const double Hq = htau * (double)dv[r];
     const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
-    tplane<T>(I, a.out_u[0])[g] = (T)u1;
-    tplane<T>(I, a.out_u[1])[g] = (T)u2;
+    dplane(I, a.out_us[0])[g] = un1[r] - dt * (h1[r] + aii * (double)hu1[r]);
+    dplane(I, a.out_us[1])[g] = un2[r] - dt * (h2[r] + aii * (double)hu2[r]);
     tplane<T>(I, a.out_q)[g] = (T)q;
     if (a.out_hu[0] != kNoSlot) {
-      tplane<T>(I, a.out_hu[0])[g] = (T)Hu1;
-      tplane<T>(I, a.out_hu[1])[g] = (T)Hu2;
+      tplane<T>(I, a.out_hu[0])[g] = hu1[r];
+      tplane<T>(I, a.out_hu[1])[g] = hu2[r];
       tplane<T>(I, a.out_gq)[g] = (T)(Hq + q);
     }
   }
@@ -576,38 +559,112 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
 
 // ------------------------------------------------------------------ stage terms
 
-// E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u), D0.u and Ltheta of a known stage, and,
-// fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
+// Completion of a stage and the terms of it that later stages reuse:
+//   u(i) = u*(i) - dt a_ii D0 theta(i)          (the theta part of step 3),
+//   Hu(i) = D_W.B(v(i)) + D0 theta(i),  Ltheta = D0^2:B(v) + D_Delta theta,
+//   E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u),  D0.u,
+// and, fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
+// Without u* (a.us[0] == kNoSlot: the terms of a given state) u is read as it is.
+//
+// theta(i) is staged with a halo of 3 + reach, so that D0 theta is known on the whole
+// WENO-staged region: every thread completes u on the cells it stages (the halo ones
+// redundantly, in the same arithmetic as their owner) and writes u, Hu and Ltheta on its
+// interior cells.  theta uses the face buffers, which the flux rounds only need later.
 template <typename T, int TY, int NT, int WO, int CO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
   using Gm = Geo<TY, NT>;
-  // sU1 and sU2 are contiguous so that theta (float64) can reuse them at the end.
-  __shared__ __align__(16) T sU[2 * Gm::PL];
-  __shared__ T sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
-  __shared__ T fx[Gm::FXN], fy[Gm::FYN];
-  static_assert(sizeof(T) * 2 * Gm::PL >= sizeof(double) * Gm::PL, "theta reuse");
-  T *sU1 = sU, *sU2 = sU + Gm::PL;
+  using C = Central<CO>;
+  using SU = Stage<TY, NT, 2, double>;             // u*, float64
+  using SW = Stage<TY, NT, 1, double, kHalo + C::R>;  // theta(i), wide halo
+  constexpr int FN = Gm::FXN + Gm::FYN;
+  constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(T));
+  __shared__ T sU1[Gm::PL], sU2[Gm::PL], sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
+  __shared__ __align__(16) T sF[FN > FT ? FN : FT];
+  T *fx = sF, *fy = sF + Gm::FXN;
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
   {
-    Stage<TY, NT, 5, T> st;
-    const Gp<const T> g[5] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1]), tplane<T>(I, a.q),
-                     tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
-    st.load(g, nx, ny, wk.a, wk.b);
-    T *l[5] = {sU1, sU2, sQ, sV1, sV2};
-    st.store(l, T(0.5));
+    Stage<TY, NT, 3, T> sqv;
+    const Gp<const T> g3[3] = {tplane<T>(I, a.q), tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    sqv.load(g3, nx, ny, wk.a, wk.b);
+    T *l3[3] = {sQ, sV1, sV2};
+    if (a.us[0] != kNoSlot) {
+      SU su;
+      const Gp<const double> g2[2] = {dplane(I, a.us[0]), dplane(I, a.us[1])};
+      su.load(g2, nx, ny, wk.a, wk.b);
+      SW sw;
+      const Gp<const double> gt[1] = {dplane(I, a.th)};
+      sw.load(gt, nx, ny, wk.a, wk.b);
+      const bool want_hu = a.hu[0] != kNoSlot, want_lt = a.out_lt != kNoSlot;
+      // pointwise inputs of the interior cells among the staged ones
+      long long go[SU::IT];
+      T hv1[SU::IT], hv2[SU::IT], dd[SU::IT];
+#pragma unroll
+      for (int it = 0; it < SU::IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+        const int gx = wk.a + lx - kHalo, gy = wk.b + ly - kHalo;
+        const bool in = idx < Gm::PL && lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo &&
+                        ly < kHalo + TY && gx < nx && gy < ny;
+        go[it] = in ? (long long)gy * nx + gx : -1;
+        hv1[it] = hv2[it] = dd[it] = T(0);
+        if (in && want_hu) {
+          hv1[it] = tplane<T>(I, a.hu[0])[go[it]];
+          hv2[it] = tplane<T>(I, a.hu[1])[go[it]];
+        }
+        if (in && want_lt) dd[it] = tplane<T>(I, a.ddb)[go[it]];
+      }
+      sqv.store(l3, T(0.5));
+      double *sT = reinterpret_cast<double *>(sF);
+      {
+        double *lt[1] = {sT};
+        sw.store(lt, 1.0);
+      }
+      __syncthreads();
+      const double cth = I.dt * a.aii;
+      const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+      const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+#pragma unroll
+      for (int it = 0; it < SU::IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        if (idx >= Gm::PL) break;
+        const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+        const int c = (ly + C::R) * SW::W + lx + C::R;
+        const double dx = C::d1(sT, c, 1, f1x), dy = C::d1(sT, c, SW::W, f1y);
+        const double u1 = su.v[0][it] - cth * dx, u2 = su.v[1][it] - cth * dy;
+        sU1[idx] = T(0.5) * (T)u1;
+        sU2[idx] = T(0.5) * (T)u2;
+        if (go[it] >= 0) {
+          tplane<T>(I, a.out_u[0])[go[it]] = (T)u1;
+          tplane<T>(I, a.out_u[1])[go[it]] = (T)u2;
+          if (want_hu) {
+            tplane<T>(I, a.hu[0])[go[it]] = (T)((double)hv1[it] + dx);
+            tplane<T>(I, a.hu[1])[go[it]] = (T)((double)hv2[it] + dy);
+          }
+          if (want_lt) {
+            const double lap = C::d2(sT, c, 1, f2x) + C::d2(sT, c, SW::W, f2y);
+            tplane<T>(I, a.out_lt)[go[it]] = (T)((double)dd[it] + lap);
+          }
+        }
+      }
+    } else {
+      Stage<TY, NT, 2, T> su;
+      const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};
+      su.load(g2, nx, ny, wk.a, wk.b);
+      sqv.store(l3, T(0.5));
+      T *l2[2] = {sU1, sU2};
+      su.store(l2, T(0.5));
+    }
   }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = wk.a + tx;
   const bool col = gx < nx;
-  const bool want_lt = a.out_lt != kNoSlot;
   __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
-  using C = Central<CO>;
   const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
   const T qt = T(0.25 * I.tau), te2 = T(I.te2);
   // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
@@ -639,45 +696,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
           C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
   }
   __syncthreads();
-  // grad q with dissipation on v1 (x) and v2 (y); then theta (float64) into the u planes
+  // grad q with dissipation on v1 (x) and v2 (y)
   faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
-  double *sTh = reinterpret_cast<double *>(sU);
-  if (want_lt) {
-    Stage<TY, NT, 1, double> sth;
-    const Gp<const double> g[1] = {dplane(I, a.th)};
-    sth.load(g, nx, ny, wk.a, wk.b);
-    double *l[1] = {sTh};
-    sth.store(l, 1.0);
-  }
   __syncthreads();
-  // pointwise inputs, loaded after the fluxes: D0^2:B(v) for Ltheta, and for the fused
-  // step 1 rv = te2 v^n - dt * (its history), formed in float64
+  if (!col) return;
+  // pointwise inputs of the fused step 1, loaded after the fluxes:
+  // rv = te2 v^n - dt * (its history), formed in float64
   const double dt = I.dt, te2d = I.te2;
-  double ddb[Gm::ROWS], rv1[Gm::ROWS], rv2[Gm::ROWS];
+  double rv1[Gm::ROWS], rv2[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int gy = wk.b + ty0 + Gm::WV * r;
-    ddb[r] = rv1[r] = rv2[r] = 0.0;
-    if (col && gy < ny) {
+    rv1[r] = rv2[r] = 0.0;
+    if (gy < ny && nv.stage > 0) {
       const long long g = (long long)gy * nx + gx;
-      if (want_lt) ddb[r] = (double)tplane<T>(I, a.ddb)[g];
-      if (nv.stage > 0) {
-        double h1 = 0.0, h2 = 0.0;
-        for (int j = 0; j < nv.nE; ++j) {
-          h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
-          h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
-        }
-        for (int j = 0; j < nv.nV; ++j) {
-          h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
-          h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
-        }
-        rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
-        rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
+      double h1 = 0.0, h2 = 0.0;
+      for (int j = 0; j < nv.nE; ++j) {
+        h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
+        h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
       }
+      for (int j = 0; j < nv.nV; ++j) {
+        h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
+        h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
+      }
+      rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
+      rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
     }
   }
-  if (!col) return;
-  const double ihx2 = C::f2(I.ihx), ihy2 = C::f2(I.ihy);
   const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -691,10 +736,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     if (a.out_e[0] != kNoSlot) {
       tplane<T>(I, a.out_e[0])[g] = E1;
       tplane<T>(I, a.out_e[1])[g] = E2;
-    }
-    if (want_lt) {
-      const double lap = C::d2(sTh, c, 1, ihx2) + C::d2(sTh, c, Gm::W, ihy2);
-      tplane<T>(I, a.out_lt)[g] = (T)(ddb[r] + lap);
     }
     if (nv.stage > 0) {
       // step 1 of the next stage; its newest history terms are this E and this v
@@ -711,8 +752,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
 
 // Launch shapes (shape index si): 0 = 64 x 8 tiles on 256 threads, 1 = 64 x 16 on 256,
 // 2 = 64 x 16 on 512, 3 = 64 x 8 on 512; then the WENO order (5 or 3) and the central
-// order (4 or 2).  The
-// right-hand side kernel has no WENO flux.
+// order (4 or 2).  The right-hand side kernel has no WENO flux, the update kernel no
+// central difference.
 template <typename T>
 hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const Work *work,
                                 int nwork, const ArgsR &a, hipStream_t st) {
@@ -761,7 +802,19 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
 template <typename T>
 hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Work *work,
                             int nwork, const ArgsUQ &a, hipStream_t st) {
-  APDVM_DISPATCH(k_update_uq, insts, work, nwork, a);
+  (void)co;  // no central difference in this kernel
+  const dim3 g(nwork);
+  const int key = si * 2 + (wo == 5 ? 0 : 1);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_update_uq<T, 8, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 1: hipLaunchKernelGGL((k_update_uq<T, 8, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 2: hipLaunchKernelGGL((k_update_uq<T, 16, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 3: hipLaunchKernelGGL((k_update_uq<T, 16, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 4: hipLaunchKernelGGL((k_update_uq<T, 16, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 5: hipLaunchKernelGGL((k_update_uq<T, 16, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 6: hipLaunchKernelGGL((k_update_uq<T, 8, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    default: hipLaunchKernelGGL((k_update_uq<T, 8, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+  }
   return hipGetLastError();
 }
 template <typename T>

@@ -40,6 +40,64 @@ def test_graph_replay_matches_direct_launches_bitwise():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_solve_beside_updates_matches_one_stream_bitwise(graph):
+    """The Helmholtz solve on the second stream beside the theta-free updates gives the
+    same bits as every launch on one stream (two instances of different sizes, a
+    ragged tile width, direct launches and graph replay)."""
+    import torch
+
+    from paper_2512_19847_amd import apdvm
+
+    outs = []
+    for on in (0, 1):
+        sim = apdvm.Simulation([dict(nx=96, ny=64, eps=0.05, tau=0.3, dt=0.01),
+                                dict(nx=64, ny=72, eps=1.0, tau=0.3, dt=0.01)],
+                               tableau="ars443", stream=torch.cuda.Stream())
+        sim.set_overlap(on)
+        assert sim.overlap() == bool(on)
+        sim.set_graph(graph)
+        sim.set_fields(0, *wl.random_divfree(96, 64, kmax=4, rms=0.1, seed=3))
+        sim.set_fields(1, *wl.random_divfree(64, 72, kmax=4, rms=0.1, seed=4))
+        for _ in range(3):
+            sim.step(2)
+            sim.get_fields(0)
+        outs.append([sim.get_fields(k) for k in range(2)])
+        sim.close()
+    for fa, fb in zip(*outs):
+        for a, b in zip(fa, fb):
+            assert np.array_equal(a, b)
+
+
+def test_sampled_timing_between_graph_replays():
+    """With graphs on, the steps whose launches are timed run launch by launch and the
+    others replay the graph: the events count only the sampled steps and the result is
+    bitwise the untimed run."""
+    import torch
+
+    from paper_2512_19847_amd import apdvm
+
+    st = _state()
+    cls = apdvm.KERNEL_CLASSES.index("stage_terms_relax_v")
+    outs = []
+    for timed in (False, True):
+        sim = _sim(stream=torch.cuda.Stream())
+        sim.set_graph(True)
+        sim.set_fields(0, *st)
+        if timed:
+            sim.timing_enable(cls)
+            sim.timing_stride(3)
+        sim.step(6)
+        if timed:
+            n, ms = sim.timing_read()
+            assert n == 2 * sim.traffic(cls)[1] and ms > 0.0
+            sim.timing_enable(-1)
+        outs.append(sim.get_fields(0))
+        sim.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_runs_are_deterministic():
     st = _state()
     outs = []
