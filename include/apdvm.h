@@ -202,8 +202,9 @@ apdvm_status apdvm_get_overlap(apdvm_ctx *ctx, int32_t *on);
  * short of theta (q, and u without its theta gradient), 7 completion of u with theta and
  * the stage terms reused by later stages, together with step 1 (the relaxation of v) of
  * the next stage, 8 single-pass Helmholtz columns (FFT, symbol divide, inverse FFT;
- * replaces 2-4 when the autotuner picks it). */
-#define APDVM_NUM_KERNEL_CLASSES 9
+ * replaces 2-4 when the autotuner picks it), 9 the q part te2 D_W q of the stage terms
+ * (WENO of q +- v, before theta is known). */
+#define APDVM_NUM_KERNEL_CLASSES 10
 
 /* From now on bracket every launch of kernel class cls with a pair of HIP events on
  * the stream the launch runs on (cls = -1 stops); a step whose launches are bracketed
@@ -228,28 +229,28 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
                            int32_t *launches_per_step);
 
 /* Launch-shape choices as apdvm_autotune reports them and apdvm_set_tuning takes them
- * (APDVM_TUNING_LEN entries): entries 0..8 per kernel class, with the tile height (8 or
- * 16 rows of 64 cells) for the stencil classes 0, 6 and 7 and 1 / 0 for the FFT column
- * classes in use / not in use (the other entries read 1); entries 9, 10 and 11 the
- * workgroup threads (256 or 512) of classes 0, 6 and 7.  Shapes: 64 x 8 or 64 x 16
- * tiles on 256 or 512 threads. */
-#define APDVM_TUNING_LEN 12
+ * (APDVM_TUNING_LEN entries): entries 0..9 per kernel class, with the tile height (8 or
+ * 16 rows of 64 cells) for the stencil classes 0, 6, 7 and 9 and 1 / 0 for the FFT
+ * column classes in use / not in use (the other entries read 1); entries 10, 11, 12 and
+ * 13 the workgroup threads (256 or 512) of classes 0, 6, 7 and 9.  Shapes: 64 x 8 or
+ * 64 x 16 tiles on 256 or 512 threads. */
+#define APDVM_TUNING_LEN 14
 
-/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7) each shape, and
- * for the Helmholtz columns the four-step form (classes 2-4) against the single pass
+/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7, 9) each shape,
+ * and for the Helmholtz columns the four-step form (classes 2-4) against the single pass
  * (class 8, only when every ny <= 2048), are timed with HIP events over steps_per_trial
  * steps of the live simulation; the fastest is kept.  Then whole steps with and without
- * the second stream (apdvm_set_overlap) are timed and the faster kept.  The state, the step counter and
- * the launch mode are restored afterwards (this call allocates a temporary device copy
- * of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
+ * the second stream (apdvm_set_overlap) are timed in the context's launch mode and the
+ * faster kept.  The state, the step counter and the launch mode are restored afterwards
+ * (this call allocates a temporary device copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
  * choice for the same context shape is read from it and no trial runs; new choices are
  * appended to it.  choice (NULL, or APDVM_TUNING_LEN entries) receives the choice.
  * Needs fields on every instance. */
 apdvm_status apdvm_autotune(apdvm_ctx *ctx, int32_t steps_per_trial, int32_t *choice);
 
 /* Set the launch shapes directly (APDVM_TUNING_LEN entries, the format apdvm_autotune
- * reports): a (tile height, threads) pair among the shapes above for classes 0, 6 and 7,
- * and choice[8] != 0 for the single-pass Helmholtz columns (needs every ny <= 2048); the
+ * reports): a (tile height, threads) pair among the shapes above for classes 0, 6, 7 and
+ * 9, and choice[8] != 0 for the single-pass Helmholtz columns (needs every ny <= 2048); the
  * other entries are ignored.  APDVM_ERR_ARG for any other pair.  Host-only. */
 apdvm_status apdvm_set_tuning(apdvm_ctx *ctx, const int32_t *choice);
 

@@ -27,10 +27,10 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "apdvm.h")
 FP64, FP32_SPLIT = 0, 1
 KERNEL_CLASSES = ("helmholtz_rhs", "fft_rows_forward", "fft_columns_a", "fft_columns_b",
                   "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
-                  "stage_terms_relax_v", "fft_columns_single_pass")
+                  "stage_terms_relax_v", "fft_columns_single_pass", "grad_q")
 # Entries of the launch-shape choice array: one per kernel class, then the workgroup
-# threads of the three stencil classes.
-TUNED_STENCIL = ("helmholtz_rhs", "update_uq", "stage_terms_relax_v")
+# threads of the four stencil classes.
+TUNED_STENCIL = ("helmholtz_rhs", "update_uq", "stage_terms_relax_v", "grad_q")
 TUNING_KEYS = KERNEL_CLASSES + tuple("threads_" + k for k in TUNED_STENCIL)
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_VELSET", 3: "ERR_TABLEAU", 4: "ERR_NOMEM",
           5: "ERR_HIP", 6: "ERR_NONFINITE", 7: "ERR_STATE"}

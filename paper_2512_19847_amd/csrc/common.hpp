@@ -147,9 +147,17 @@ struct ArgsUQ {
   int out_hu[2], out_gq;  // hu and Gq; kNoSlot when no later stage needs them
 };
 
+// The q part of the stage terms E (it needs q(i) and v(i) only, so it runs before
+// theta(i) is known): G = te2 D_W q[dissipation on v], x component from the x faces with
+// the split fluxes q +- v1, y component from the y faces with q +- v2.
+struct ArgsG {
+  int q, v[2];  // halo 3
+  int out_g[2];
+};
+
 // Completion of a stage and its terms that later stages reuse:
 // u(i) = u*(i) - dt a_ii D0 theta(i), Hu(i) = hu + D0 theta(i) (in place),
-// E = (tau/4) D0_W.B(u) + te2 D_W q[dissipation on v] - F(u), D0.u,
+// E = (tau/4) D0_W.B(u) + G - F(u) with G from ArgsG, D0.u,
 // Ltheta = D0^2:B(v) + D_Delta theta.  With us[0] == kNoSlot (the terms of a state set)
 // u is read from u[] and nothing of theta is used.  The same launch performs step 1 of
 // the next stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients
@@ -157,7 +165,8 @@ struct ArgsUQ {
 struct ArgsE {
   int us[2];          // u*(i) (float64 slots, halo 3) or kNoSlot
   int u[2];           // u of a state set (halo 3), when us[0] == kNoSlot
-  int q, v[2];        // halo 3
+  int g[2];           // G of this stage (pointwise)
+  int v[2];           // v of this stage (pointwise, for the fused step 1)
   int th;             // theta(i), float64 slot, halo 3 + reach of D0 (with us)
   double aii;         // a_ii of the stage (with us)
   int out_u[2];       // u(i) (with us)

@@ -25,6 +25,8 @@ hipError_t launch_update_uq(int, int, int, const Inst *, const Work *, int, cons
 template <typename T>
 hipError_t launch_stage_terms(int, int, int, const Inst *, const Work *, int, const ArgsE &,
                               const ArgsV &, hipStream_t);
+template <typename T>
+hipError_t launch_grad_q(int, int, const Inst *, const Work *, int, const ArgsG &, hipStream_t);
 
 // Tile heights the stencil kernels are built for; the autotuner picks one per class.
 constexpr int kTileRows[2] = {8, 16};
@@ -178,7 +180,7 @@ struct Layout {
   int th[2];     // float64: theta of each state set
   int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
   int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
-  int ddb;
+  int ddb, G[2];
   int Th[kMaxStages], Us[2], R, spec;  // float64
   int ntrans, ndbl;
 };
@@ -210,6 +212,8 @@ Layout make_layout(int s) {
     L.Th[j] = d++;
   }
   L.ddb = t++;
+  L.G[0] = t++;
+  L.G[1] = t++;
   L.Us[0] = d++;
   L.Us[1] = d++;
   L.R = d++;
@@ -371,8 +375,11 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
 // plane it must read and write, counted once).
 enum LaunchClass {
   kHelmRhs = 0, kRowsFwd = 1, kColsA = 2, kColsB = 3, kColsAInv = 4, kRowsInv = 5,
-  kUpdateUQ = 6, kStageTerms = 7, kColsFull = 8, kNumClasses = 9
+  kUpdateUQ = 6, kStageTerms = 7, kColsFull = 8, kGradQ = 9, kNumClasses = 10
 };
+// Stencil classes with a tuned launch shape, in the order of the tuning array.
+constexpr int kNumTuned = 4;
+constexpr int kTunedClasses[kNumTuned] = {kHelmRhs, kUpdateUQ, kStageTerms, kGradQ};
 
 // Stream synchronisation entries of a plan (cls = kSync): a fork makes the solve stream
 // wait for the work enqueued so far on the main stream, a join the reverse.
@@ -388,6 +395,7 @@ struct Launch {
   ArgsUQ uq;
   ArgsE e;
   ArgsSolve sv;
+  ArgsG g;
   double bytes;
 };
 
@@ -523,8 +531,19 @@ bool implicit_stored(const apdvm_ctx *c, int j) {
   return false;
 }
 
-// Stage-terms launch for the state set P itself (stage 0), used after new fields.
-Launch stage0_launch(const apdvm_ctx *c, int P) {
+// Launch of G = te2 D_W q[v] from q and v, into the G slots.
+Launch grad_q_launch(const apdvm_ctx *c, int q, int v1, int v2) {
+  const Layout &L = c->L;
+  Launch l{};
+  l.cls = kGradQ;
+  l.g.q = q; l.g.v[0] = v1; l.g.v[1] = v2;
+  l.g.out_g[0] = L.G[0]; l.g.out_g[1] = L.G[1];
+  l.bytes = 5 * c->cells * (c->split ? 4.0 : 8.0);  // q, v in; G out
+  return l;
+}
+
+// Stage-terms launches for the state set P itself (stage 0), used after new fields.
+std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const double pt = c->cells * (c->split ? 4.0 : 8.0);
   Launch l{};
@@ -532,21 +551,22 @@ Launch stage0_launch(const apdvm_ctx *c, int P) {
   ArgsE &a = l.e;
   a.us[0] = a.us[1] = kNoSlot;
   a.u[0] = L.st[P][0]; a.u[1] = L.st[P][1]; a.v[0] = L.st[P][2]; a.v[1] = L.st[P][3];
-  a.q = L.st[P][4]; a.th = kNoSlot; a.ddb = kNoSlot;
+  a.g[0] = L.G[0]; a.g[1] = L.G[1];
+  a.th = kNoSlot; a.ddb = kNoSlot;
   a.out_u[0] = a.out_u[1] = a.hu[0] = a.hu[1] = kNoSlot;
   a.out_e[0] = e_stored(c, 0) ? L.E[0][0] : kNoSlot;
   a.out_e[1] = e_stored(c, 0) ? L.E[0][1] : kNoSlot;
   a.out_du = L.Du[0];
   a.out_lt = kNoSlot;
-  l.bytes = (5 + 1 + (e_stored(c, 0) ? 2 : 0)) * pt;
+  l.bytes = (2 + 2 + 2 + 1 + (e_stored(c, 0) ? 2 : 0)) * pt;  // u, G, v in; D0.u, E out
   fill_relax(c, 1, P, l.v, a, pt, l.bytes);
-  return l;
+  return {grad_q_launch(c, L.st[P][4], L.st[P][2], L.st[P][3]), l};
 }
 
 // Launch list of one step starting from state set P.  Per stage: the right-hand side and
 // the Helmholtz solve go to the solve stream while the theta-free part of steps 3 and 4
-// runs on the main stream; the stage-terms launch, which completes u(i) with theta(i),
-// joins the two.
+// and the q part of the stage terms run on the main stream; the stage-terms launch,
+// which completes u(i) with theta(i), joins the two.
 std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const int s = c->s, Q = 1 - P;
@@ -623,6 +643,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
     l.bytes = (reads + 1 + (keep ? 3 : 0)) * pt + 2 * pd;
     plan.push_back(l);
+    plan.push_back(grad_q_launch(c, qi, v1, v2));
     sync(kJoin);
     // u(i) from theta(i), terms of this stage for later stages, and step 1 of the next
     // stage; the last stage's terms are the next step's stage-0 terms
@@ -630,7 +651,8 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     l.cls = kStageTerms;
     ArgsE &ae = l.e;
     ae.us[0] = L.Us[0]; ae.us[1] = L.Us[1]; ae.u[0] = ae.u[1] = kNoSlot;
-    ae.q = qi; ae.v[0] = v1; ae.v[1] = v2; ae.th = th; ae.aii = aii;
+    ae.g[0] = L.G[0]; ae.g[1] = L.G[1];
+    ae.v[0] = v1; ae.v[1] = v2; ae.th = th; ae.aii = aii;
     ae.out_u[0] = u1; ae.out_u[1] = u2;
     ae.hu[0] = keep ? L.Hu[i][0] : kNoSlot;
     ae.hu[1] = keep ? L.Hu[i][1] : kNoSlot;
@@ -641,8 +663,8 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ae.out_e[1] = est ? L.E[ej][1] : kNoSlot;
     ae.out_du = L.Du[ej];
     ae.out_lt = keep ? L.Lt[i] : kNoSlot;
-    // u*, theta; q, v; u, D0.u, E; with keep hu and ddb in, Hu and Ltheta out
-    l.bytes = 3 * pd + (3 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
+    // u*, theta, G, v in; u, D0.u, E out; with keep hu and ddb in, Hu and Ltheta out
+    l.bytes = 3 * pd + (2 + 2 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
     if (last)
       fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
     else
@@ -686,6 +708,8 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
                                c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
     case kUpdateUQ:
       return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st);
+    case kGradQ:
+      return launch_grad_q<T>(si, c->wo, c->d_inst, tiles, nt, l.g, st);
     default:
       return launch_stage_terms<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st);
   }
@@ -693,7 +717,8 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
 
 template <typename T>
 apdvm_status stage0_terms(apdvm_ctx *c) {
-  if (run_launch<T>(c, stage0_launch(c, c->parity)) != hipSuccess) return APDVM_ERR_HIP;
+  for (const Launch &l : stage0_launches(c, c->parity))
+    if (run_launch<T>(c, l) != hipSuccess) return APDVM_ERR_HIP;
   c->terms_ready = true;
   return APDVM_OK;
 }
@@ -1436,7 +1461,7 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
 
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 shapes4 overlap prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes4 overlap gradq prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
@@ -1448,7 +1473,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
   if (!c || steps_per_trial < 1) return APDVM_ERR_ARG;
   for (int k = 0; k < c->n; ++k)
     if (!c->has_fields[k]) return APDVM_ERR_STATE;
-  const int classes[3] = {kHelmRhs, kUpdateUQ, kStageTerms};
+  const int *classes = kTunedClasses;
   const char *cache = std::getenv("APDVM_TUNE_CACHE");
   const std::string key = tune_key(c);
   bool cached = false;
@@ -1459,10 +1484,11 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() &&
           line[key.size()] == '|') {
         std::istringstream rest(line.substr(key.size() + 1));
-        int t[3], mode = 0, ov = 1;
-        if (rest >> t[0] >> t[1] >> t[2] >> mode >> ov && t[0] >= 0 && t[0] < kNumShapes &&
-            t[1] >= 0 && t[1] < kNumShapes && t[2] >= 0 && t[2] < kNumShapes) {
-          for (int m = 0; m < 3; ++m) c->shape[classes[m]] = t[m];
+        int t[kNumTuned], mode = 0, ov = 1;
+        bool good = true;
+        for (int m = 0; m < kNumTuned; ++m) good = good && (rest >> t[m]) && t[m] >= 0 && t[m] < kNumShapes;
+        if (good && rest >> mode >> ov) {
+          for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = t[m];
           set_col_mode(c, (mode && c->col_full_ok) ? 1 : 0);
           if (apdvm_set_overlap(c, ov ? 1 : 0) != APDVM_OK) return APDVM_ERR_HIP;
           cached = true;
@@ -1504,7 +1530,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     c->use_graph = false;
     c->timed_stride = 1;
     bool ok = copy_state(true);
-    for (int m = 0; ok && m < 3; ++m) {
+    for (int m = 0; ok && m < kNumTuned; ++m) {
       const int cls = classes[m];
       double best = 1e300;
       int best_si = 1;
@@ -1577,8 +1603,9 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     if (!ok) return APDVM_ERR_HIP;
     if (cache) {
       std::ofstream out(cache, std::ios::app);
-      out << key << "|" << c->shape[classes[0]] << " " << c->shape[classes[1]] << " "
-          << c->shape[classes[2]] << " " << c->col_mode << " " << (c->overlap ? 1 : 0) << "\n";
+      out << key << "|";
+      for (int m = 0; m < kNumTuned; ++m) out << c->shape[classes[m]] << " ";
+      out << c->col_mode << " " << (c->overlap ? 1 : 0) << "\n";
     }
   }
   // the graphs captured the old launch shapes
@@ -1592,7 +1619,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     // for the FFT column classes report which form runs: 1 used, 0 not used
     choice[kColsA] = choice[kColsB] = choice[kColsAInv] = c->col_mode ? 0 : 1;
     choice[kColsFull] = c->col_mode ? 1 : 0;
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < kNumTuned; ++m) {
       choice[classes[m]] = kShapeRows[c->shape[classes[m]]];
       choice[kNumClasses + m] = kShapeThreads[c->shape[classes[m]]];
     }
@@ -1602,15 +1629,15 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
 
 apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
   if (!c || !choice) return APDVM_ERR_ARG;
-  const int classes[3] = {kHelmRhs, kUpdateUQ, kStageTerms};
-  int si[3];
-  for (int m = 0; m < 3; ++m) {
+  const int *classes = kTunedClasses;
+  int si[kNumTuned];
+  for (int m = 0; m < kNumTuned; ++m) {
     si[m] = shape_of(choice[classes[m]], choice[kNumClasses + m]);
     if (si[m] < 0) return APDVM_ERR_ARG;
   }
   const int mode = choice[kColsFull] ? 1 : 0;
   if (mode && !c->col_full_ok) return APDVM_ERR_ARG;
-  for (int m = 0; m < 3; ++m) c->shape[classes[m]] = si[m];
+  for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = si[m];
   set_col_mode(c, mode);
   for (int p = 0; p < 2; ++p)
     if (c->graph_exec[p]) {

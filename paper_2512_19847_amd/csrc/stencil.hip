@@ -557,12 +557,51 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
 }
 
+// ------------------------------------------------------------------ grad q
+
+// G = te2 D_W q[dissipation on v] of a stage: the part of its terms E that needs q(i)
+// and v(i) only, so it runs beside the Helmholtz solve of the stage.
+template <typename T, int TY, int NT, int WO>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_grad_q(const Inst *__restrict__ insts,
+                                                              const Work *__restrict__ work,
+                                                              int nwork, ArgsG a) {
+  using Gm = Geo<TY, NT>;
+  __shared__ T sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
+  __shared__ T fx[Gm::FXN], fy[Gm::FYN];
+  const Work wk = work[xcd_item(nwork)];
+  const Inst &I = insts[wk.inst];
+  const int nx = I.nx, ny = I.ny;
+  {
+    Stage<TY, NT, 3, T> st;
+    const Gp<const T> g[3] = {tplane<T>(I, a.q), tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    st.load(g, nx, ny, wk.a, wk.b);
+    T *l[3] = {sQ, sV1, sV2};
+    st.store(l, T(0.5));
+  }
+  __syncthreads();
+  faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  if (gx >= nx) return;
+  const T ihx = T(I.ihx), ihy = T(I.ihy), te2 = T(I.te2);
+#pragma unroll
+  for (int r = 0; r < Gm::ROWS; ++r) {
+    const int ly = ty0 + Gm::WV * r;
+    const int gy = wk.b + ly;
+    if (gy >= ny) break;
+    const long long g = (long long)gy * nx + gx;
+    tplane<T>(I, a.out_g[0])[g] = te2 * face_dx<TY>(fx, tx, ly, ihx);
+    tplane<T>(I, a.out_g[1])[g] = te2 * face_dy<TY>(fy, tx, ly, ihy);
+  }
+}
+
 // ------------------------------------------------------------------ stage terms
 
 // Completion of a stage and the terms of it that later stages reuse:
 //   u(i) = u*(i) - dt a_ii D0 theta(i)          (the theta part of step 3),
 //   Hu(i) = D_W.B(v(i)) + D0 theta(i),  Ltheta = D0^2:B(v) + D_Delta theta,
-//   E = (tau/4) D0_W.B(u) + te2 D_W q[v] - F(u),  D0.u,
+//   E = (tau/4) D0_W.B(u) + G - F(u),  D0.u    (G = te2 D_W q[v] from k_grad_q),
 // and, fused, step 1 of the next stage: v(next) from v^n, the history and this E and v.
 // Without u* (a.us[0] == kNoSlot: the terms of a given state) u is read as it is.
 //
@@ -580,84 +619,76 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   using SW = Stage<TY, NT, 1, double, kHalo + C::R>;  // theta(i), wide halo
   constexpr int FN = Gm::FXN + Gm::FYN;
   constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(T));
-  __shared__ T sU1[Gm::PL], sU2[Gm::PL], sQ[Gm::PL], sV1[Gm::PL], sV2[Gm::PL];
+  __shared__ T sU1[Gm::PL], sU2[Gm::PL];
   __shared__ __align__(16) T sF[FN > FT ? FN : FT];
   T *fx = sF, *fy = sF + Gm::FXN;
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
-  {
-    Stage<TY, NT, 3, T> sqv;
-    const Gp<const T> g3[3] = {tplane<T>(I, a.q), tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
-    sqv.load(g3, nx, ny, wk.a, wk.b);
-    T *l3[3] = {sQ, sV1, sV2};
-    if (a.us[0] != kNoSlot) {
-      SU su;
-      const Gp<const double> g2[2] = {dplane(I, a.us[0]), dplane(I, a.us[1])};
-      su.load(g2, nx, ny, wk.a, wk.b);
-      SW sw;
-      const Gp<const double> gt[1] = {dplane(I, a.th)};
-      sw.load(gt, nx, ny, wk.a, wk.b);
-      const bool want_hu = a.hu[0] != kNoSlot, want_lt = a.out_lt != kNoSlot;
-      // pointwise inputs of the interior cells among the staged ones
-      long long go[SU::IT];
-      T hv1[SU::IT], hv2[SU::IT], dd[SU::IT];
+  if (a.us[0] != kNoSlot) {
+    SU su;
+    const Gp<const double> g2[2] = {dplane(I, a.us[0]), dplane(I, a.us[1])};
+    su.load(g2, nx, ny, wk.a, wk.b);
+    SW sw;
+    const Gp<const double> gt[1] = {dplane(I, a.th)};
+    sw.load(gt, nx, ny, wk.a, wk.b);
+    const bool want_hu = a.hu[0] != kNoSlot, want_lt = a.out_lt != kNoSlot;
+    // pointwise inputs of the interior cells among the staged ones
+    long long go[SU::IT];
+    T hv1[SU::IT], hv2[SU::IT], dd[SU::IT];
 #pragma unroll
-      for (int it = 0; it < SU::IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
-        const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
-        const int gx = wk.a + lx - kHalo, gy = wk.b + ly - kHalo;
-        const bool in = idx < Gm::PL && lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo &&
-                        ly < kHalo + TY && gx < nx && gy < ny;
-        go[it] = in ? (long long)gy * nx + gx : -1;
-        hv1[it] = hv2[it] = dd[it] = T(0);
-        if (in && want_hu) {
-          hv1[it] = tplane<T>(I, a.hu[0])[go[it]];
-          hv2[it] = tplane<T>(I, a.hu[1])[go[it]];
-        }
-        if (in && want_lt) dd[it] = tplane<T>(I, a.ddb)[go[it]];
+    for (int it = 0; it < SU::IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+      const int gx = wk.a + lx - kHalo, gy = wk.b + ly - kHalo;
+      const bool in = idx < Gm::PL && lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo &&
+                      ly < kHalo + TY && gx < nx && gy < ny;
+      go[it] = in ? (long long)gy * nx + gx : -1;
+      hv1[it] = hv2[it] = dd[it] = T(0);
+      if (in && want_hu) {
+        hv1[it] = tplane<T>(I, a.hu[0])[go[it]];
+        hv2[it] = tplane<T>(I, a.hu[1])[go[it]];
       }
-      sqv.store(l3, T(0.5));
-      double *sT = reinterpret_cast<double *>(sF);
-      {
-        double *lt[1] = {sT};
-        sw.store(lt, 1.0);
-      }
-      __syncthreads();
-      const double cth = I.dt * a.aii;
-      const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
-      const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
-#pragma unroll
-      for (int it = 0; it < SU::IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
-        if (idx >= Gm::PL) break;
-        const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
-        const int c = (ly + C::R) * SW::W + lx + C::R;
-        const double dx = C::d1(sT, c, 1, f1x), dy = C::d1(sT, c, SW::W, f1y);
-        const double u1 = su.v[0][it] - cth * dx, u2 = su.v[1][it] - cth * dy;
-        sU1[idx] = T(0.5) * (T)u1;
-        sU2[idx] = T(0.5) * (T)u2;
-        if (go[it] >= 0) {
-          tplane<T>(I, a.out_u[0])[go[it]] = (T)u1;
-          tplane<T>(I, a.out_u[1])[go[it]] = (T)u2;
-          if (want_hu) {
-            tplane<T>(I, a.hu[0])[go[it]] = (T)((double)hv1[it] + dx);
-            tplane<T>(I, a.hu[1])[go[it]] = (T)((double)hv2[it] + dy);
-          }
-          if (want_lt) {
-            const double lap = C::d2(sT, c, 1, f2x) + C::d2(sT, c, SW::W, f2y);
-            tplane<T>(I, a.out_lt)[go[it]] = (T)((double)dd[it] + lap);
-          }
-        }
-      }
-    } else {
-      Stage<TY, NT, 2, T> su;
-      const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};
-      su.load(g2, nx, ny, wk.a, wk.b);
-      sqv.store(l3, T(0.5));
-      T *l2[2] = {sU1, sU2};
-      su.store(l2, T(0.5));
+      if (in && want_lt) dd[it] = tplane<T>(I, a.ddb)[go[it]];
     }
+    double *sT = reinterpret_cast<double *>(sF);
+    {
+      double *lt[1] = {sT};
+      sw.store(lt, 1.0);
+    }
+    __syncthreads();
+    const double cth = I.dt * a.aii;
+    const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+    const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+#pragma unroll
+    for (int it = 0; it < SU::IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx >= Gm::PL) break;
+      const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+      const int c = (ly + C::R) * SW::W + lx + C::R;
+      const double dx = C::d1(sT, c, 1, f1x), dy = C::d1(sT, c, SW::W, f1y);
+      const double u1 = su.v[0][it] - cth * dx, u2 = su.v[1][it] - cth * dy;
+      sU1[idx] = T(0.5) * (T)u1;
+      sU2[idx] = T(0.5) * (T)u2;
+      if (go[it] >= 0) {
+        tplane<T>(I, a.out_u[0])[go[it]] = (T)u1;
+        tplane<T>(I, a.out_u[1])[go[it]] = (T)u2;
+        if (want_hu) {
+          tplane<T>(I, a.hu[0])[go[it]] = (T)((double)hv1[it] + dx);
+          tplane<T>(I, a.hu[1])[go[it]] = (T)((double)hv2[it] + dy);
+        }
+        if (want_lt) {
+          const double lap = C::d2(sT, c, 1, f2x) + C::d2(sT, c, SW::W, f2y);
+          tplane<T>(I, a.out_lt)[go[it]] = (T)((double)dd[it] + lap);
+        }
+      }
+    }
+  } else {
+    Stage<TY, NT, 2, T> su;
+    const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};
+    su.load(g2, nx, ny, wk.a, wk.b);
+    T *l2[2] = {sU1, sU2};
+    su.store(l2, T(0.5));
   }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = wk.a + tx;
@@ -666,9 +697,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
   const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
-  const T qt = T(0.25 * I.tau), te2 = T(I.te2);
-  // e = (tau/4) D0_W.B(u) - F(u), completed by te2 D_W q after the third round
-  T e1[Gm::ROWS], e2[Gm::ROWS];
+  const T qt = T(0.25 * I.tau);
+  // first component of (tau/4) D0_W.B(u); E is assembled at the end
+  T e1[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
   faces<TY, NT, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
   __syncthreads();
@@ -681,46 +712,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
   faces<TY, NT, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < Gm::ROWS; ++r) {
-    const int ly = ty0 + Gm::WV * r;
-    const int c = Gm::at(tx, ly);
-    const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
-    e1[r] -= T(0.5) * (u2 * u2 - u1 * u1);
-    e2[r] = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2;
-    keep(e1[r]);
-    keep(e2[r]);
-    const int gy = wk.b + ly;
-    if (col && gy < ny)
-      tplane<T>(I, a.out_du)[(long long)gy * nx + gx] =
-          C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
-  }
-  __syncthreads();
-  // grad q with dissipation on v1 (x) and v2 (y)
-  faces<TY, NT, WO, T, true, true>(fx, fy, sQ, sV1, T(1), sQ, sV2, T(1));
-  __syncthreads();
   if (!col) return;
-  // pointwise inputs of the fused step 1, loaded after the fluxes:
+  // pointwise inputs of E and of the fused step 1: G, v, and
   // rv = te2 v^n - dt * (its history), formed in float64
   const double dt = I.dt, te2d = I.te2;
+  T g1[Gm::ROWS], g2[Gm::ROWS], w1[Gm::ROWS], w2[Gm::ROWS];
   double rv1[Gm::ROWS], rv2[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int gy = wk.b + ty0 + Gm::WV * r;
+    g1[r] = g2[r] = w1[r] = w2[r] = T(0);
     rv1[r] = rv2[r] = 0.0;
-    if (gy < ny && nv.stage > 0) {
+    if (gy < ny) {
       const long long g = (long long)gy * nx + gx;
-      double h1 = 0.0, h2 = 0.0;
-      for (int j = 0; j < nv.nE; ++j) {
-        h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
-        h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
+      g1[r] = tplane<T>(I, a.g[0])[g];
+      g2[r] = tplane<T>(I, a.g[1])[g];
+      if (nv.stage > 0) {
+        w1[r] = tplane<T>(I, a.v[0])[g];
+        w2[r] = tplane<T>(I, a.v[1])[g];
+        double h1 = 0.0, h2 = 0.0;
+        for (int j = 0; j < nv.nE; ++j) {
+          h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
+          h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
+        }
+        for (int j = 0; j < nv.nV; ++j) {
+          h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
+          h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
+        }
+        rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
+        rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
       }
-      for (int j = 0; j < nv.nV; ++j) {
-        h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
-        h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
-      }
-      rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
-      rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
     }
   }
   const double kinv = nv.stage > 0 ? I.kinv[nv.stage] : 0.0;
@@ -731,15 +752,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     if (gy >= ny) break;
     const long long g = (long long)gy * nx + gx;
     const int c = Gm::at(tx, ly);
-    const T E1 = e1[r] + te2 * face_dx<TY>(fx, tx, ly, ihx);
-    const T E2 = e2[r] + te2 * face_dy<TY>(fy, tx, ly, ihy);
+    const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
+    const T E1 = (e1[r] - T(0.5) * (u2 * u2 - u1 * u1)) + g1[r];
+    const T E2 = (qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2) +
+                 g2[r];
+    tplane<T>(I, a.out_du)[g] = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
     if (a.out_e[0] != kNoSlot) {
       tplane<T>(I, a.out_e[0])[g] = E1;
       tplane<T>(I, a.out_e[1])[g] = E2;
     }
     if (nv.stage > 0) {
       // step 1 of the next stage; its newest history terms are this E and this v
-      const double v1 = 2.0 * (double)sV1[c], v2 = 2.0 * (double)sV2[c];
+      const double v1 = (double)w1[r], v2 = (double)w2[r];
       const double s1 = a.c_e_next * (double)E1 + a.c_v_next * v1;
       const double s2 = a.c_e_next * (double)E2 + a.c_v_next * v2;
       tplane<T>(I, nv.out[0])[g] = (T)((rv1[r] - dt * s1) * kinv);
@@ -818,6 +842,23 @@ hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Wor
   return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_grad_q(int si, int wo, const Inst *insts, const Work *work, int nwork,
+                         const ArgsG &a, hipStream_t st) {
+  const dim3 g(nwork);
+  const int key = si * 2 + (wo == 5 ? 0 : 1);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_grad_q<T, 8, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 1: hipLaunchKernelGGL((k_grad_q<T, 8, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 2: hipLaunchKernelGGL((k_grad_q<T, 16, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 3: hipLaunchKernelGGL((k_grad_q<T, 16, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
+    case 4: hipLaunchKernelGGL((k_grad_q<T, 16, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 5: hipLaunchKernelGGL((k_grad_q<T, 16, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 6: hipLaunchKernelGGL((k_grad_q<T, 8, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    default: hipLaunchKernelGGL((k_grad_q<T, 8, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+  }
+  return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const Work *work,
                               int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st) {
   APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
@@ -832,7 +873,9 @@ hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const W
   template hipError_t launch_update_uq<T>(int, int, int, const Inst *, const Work *, int,      \
                                           const ArgsUQ &, hipStream_t);                        \
   template hipError_t launch_stage_terms<T>(int, int, int, const Inst *, const Work *, int,    \
-                                            const ArgsE &, const ArgsV &, hipStream_t);
+                                            const ArgsE &, const ArgsV &, hipStream_t);        \
+  template hipError_t launch_grad_q<T>(int, int, const Inst *, const Work *, int,              \
+                                       const ArgsG &, hipStream_t);
 APDVM_INST(double)
 APDVM_INST(float)
 #undef APDVM_INST
