@@ -14,10 +14,10 @@ the launch shapes and whether the Helmholtz solve runs on a second stream beside
 theta-free update kernel.
 
 roofline: the kernel class with the largest share of step time is bracketed by HIP
-events on the stream it runs on during the timed region (its launches in every
-TIMING_STRIDE-th step, which runs launch by launch instead of as a graph); achieved =
-its algorithmic bytes per launch (every plane it must read or write, once) / its mean
-duration.
+events during the timed region (its launches in every TIMING_STRIDE-th step, which runs
+launch by launch on the library's main stream, so each bracketed launch runs by itself);
+achieved = its algorithmic bytes per launch (every plane it must read or write, once) /
+its mean duration.
 roofline.traffic: HBM bytes per launch of that kernel from the rocprofv3 FETCH_SIZE and
 WRITE_SIZE runs recorded under profiles/ (each scaled by what the counter reads for a
 device copy of known size), reported only for the workload, precision and kernel they
@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "IMEX-RK cell-pop updates/s + %HBM roofline; FP32-split/batched vs FP64"
 UNIT = "cell-population updates/s"
 HBM_PEAK_GBS = 8000.0
-TIMING_STRIDE = 8
+TIMING_STRIDE = 16
 
 
 def recorded_traffic(kernel_class, workload_name, precision):
@@ -202,11 +202,9 @@ def main():
     cells = sum(c.nx * c.ny for c in cases)
     tiles = sim.autotune(3)
 
-    # warm-up, then find the kernel class with the largest share of a step, each class
-    # timed on one stream (on two, a launch's duration includes the work beside it)
+    # warm-up, then find the kernel class with the largest share of a step (timed steps
+    # run every launch by itself)
     sim.step(args.warmup)
-    overlap = sim.overlap()
-    sim.set_overlap(False)
     share = []
     for cls in range(len(apdvm.KERNEL_CLASSES)):
         sim.timing_enable(cls)
@@ -214,7 +212,6 @@ def main():
         n, ms = sim.timing_read()
         share.append(ms)
     sim.timing_enable(-1)
-    sim.set_overlap(overlap)
     dom = int(np.argmax(share))
 
     # timed region: the launches of the dominant class in every TIMING_STRIDE-th step are

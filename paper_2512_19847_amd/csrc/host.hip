@@ -777,14 +777,18 @@ apdvm_status enqueue_step(apdvm_ctx *c) {
   }
   const int P = c->parity;
   // a step whose launches of the timed class are bracketed by events runs launch by
-  // launch; every other step replays the graph when graphs are on
+  // launch on the main stream alone, so that the events see each launch by itself;
+  // every other step replays the graph when graphs are on
   const bool sample = c->timed_class >= 0 && c->timed_steps % c->timed_stride == 0;
   if (c->use_graph && !sample) {
     apdvm_status st = ensure_graph<T>(c, P);
     if (st != APDVM_OK) return st;
     if (hipGraphLaunch(c->graph_exec[P], c->stream) != hipSuccess) return APDVM_ERR_HIP;
   } else {
+    const bool overlap = c->overlap;
+    if (sample) c->overlap = false;
     const apdvm_status st = run_plan_direct<T>(c, c->plan[P], sample);
+    c->overlap = overlap;
     if (st != APDVM_OK) return st;
   }
   if (c->timed_class >= 0) ++c->timed_steps;
