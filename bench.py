@@ -13,11 +13,12 @@ Steps replay HIP graphs (--no-graph: launch by launch); the library's autotuner 
 the launch shapes and whether the Helmholtz solve runs on a second stream beside the
 theta-free update kernel.
 
-roofline: the kernel class with the largest share of step time is bracketed by HIP
-events during the timed region (its launches in every TIMING_STRIDE-th step, which runs
-launch by launch on the library's main stream, so each bracketed launch runs by itself);
-achieved = its algorithmic bytes per launch (every plane it must read or write, once) /
-its mean duration.
+roofline: the launches of the kernel class with the largest share of step time are timed
+during the timed region with HIP events set by the kernel launch itself
+(hipExtLaunchKernelGGL: start and end of the kernel's execution), in every
+TIMING_STRIDE-th step, which runs launch by launch on the library's main stream so that
+each timed launch runs by itself; achieved = its algorithmic bytes per launch (every
+plane it must read or write, once) / its mean duration.
 roofline.traffic: HBM bytes per launch of that kernel from the rocprofv3 FETCH_SIZE and
 WRITE_SIZE runs recorded under profiles/ (each scaled by what the counter reads for a
 device copy of known size), reported only for the workload, precision and kernel they

@@ -206,11 +206,12 @@ apdvm_status apdvm_get_overlap(apdvm_ctx *ctx, int32_t *on);
  * (WENO of q +- v, before theta is known). */
 #define APDVM_NUM_KERNEL_CLASSES 10
 
-/* From now on bracket every launch of kernel class cls with a pair of HIP events
- * (cls = -1 stops).  A step whose launches are bracketed runs launch by launch with every
- * launch on the creation stream, so that each bracketed launch runs by itself; other
- * steps replay the graph when graphs are on and use the second stream when overlap is
- * on.  Synchronises the stream and clears earlier timings. */
+/* From now on time every launch of kernel class cls with a pair of HIP events that
+ * hipExtLaunchKernelGGL sets at the start and end of the kernel's own execution (cls = -1
+ * stops).  A step with timed launches runs launch by launch with every launch on the
+ * creation stream, so that each timed launch runs by itself; other steps replay the graph
+ * when graphs are on and use the second stream when overlap is on.  Synchronises the
+ * stream and clears earlier timings. */
 apdvm_status apdvm_timing_enable(apdvm_ctx *ctx, int32_t cls);
 
 /* Bracket the timed class only in every stride-th step (stride >= 1, default 1; every

@@ -14,6 +14,7 @@
 // base + k * nx * ny.  Layout of a plane: row-major [ny][nx], x fastest.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
@@ -29,6 +30,21 @@ template <class T>
 __device__ __forceinline__ Gp<T> gp(T *p) {
   return (Gp<T>)p;
 }
+
+// Optional HIP events around one launch.  With both set the launch goes through
+// hipExtLaunchKernelGGL, whose events take the start and end of the kernel's own
+// dispatch (not the gap in the queue before it); otherwise it is a plain launch.
+struct Ev {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+#define APDVM_LAUNCH(EV, KERNEL, GRID, BLOCK, STREAM, ...)                                   \
+  do {                                                                                      \
+    if ((EV).start)                                                                         \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, (EV).start, (EV).stop, 0,       \
+                            __VA_ARGS__);                                                   \
+    else                                                                                    \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                      \
+  } while (0)
 
 constexpr int kMaxStages = 8;
 constexpr int kMaxPasses = 16;

@@ -543,38 +543,35 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
 // kernels for nx > kRowSmallCap.
 hipError_t launch_solve_part(int part, bool big, const Inst *insts, const Work *rows, int nrows,
                              const Work *cola, int ncola, const Work *colb, int ncolb,
-                             const ArgsSolve &a, hipStream_t st) {
+                             const ArgsSolve &a, hipStream_t st, const Ev &ev) {
   switch (part) {
     case 5:
-      hipLaunchKernelGGL(k_cols_full, dim3(ncola), dim3(kColThreads), 0, st, insts, cola, ncola,
-                         a);
+      APDVM_LAUNCH(ev, k_cols_full, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
       break;
     case 0:
       if (big)
-        hipLaunchKernelGGL((k_rows_forward<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
-                           0, st, insts, rows, nrows, a);
+        APDVM_LAUNCH(ev, (k_rows_forward<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
+                     st, insts, rows, nrows, a);
       else
-        hipLaunchKernelGGL((k_rows_forward<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
-                           dim3(kRowSmallThreads), 0, st, insts, rows, nrows, a);
+        APDVM_LAUNCH(ev, (k_rows_forward<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
+                     dim3(kRowSmallThreads), st, insts, rows, nrows, a);
       break;
     case 1:
-      hipLaunchKernelGGL(k_cols_a<-1>, dim3(ncola), dim3(kColThreads), 0, st, insts, cola, ncola,
-                         a);
+      APDVM_LAUNCH(ev, k_cols_a<-1>, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
       break;
     case 2:
-      hipLaunchKernelGGL(k_cols_b, dim3(ncolb), dim3(kColThreads), 0, st, insts, colb, ncolb, a);
+      APDVM_LAUNCH(ev, k_cols_b, dim3(ncolb), dim3(kColThreads), st, insts, colb, ncolb, a);
       break;
     case 3:
-      hipLaunchKernelGGL(k_cols_a<1>, dim3(ncola), dim3(kColThreads), 0, st, insts, cola, ncola,
-                         a);
+      APDVM_LAUNCH(ev, k_cols_a<1>, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
       break;
     default:
       if (big)
-        hipLaunchKernelGGL((k_rows_inverse<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
-                           0, st, insts, rows, nrows, a);
+        APDVM_LAUNCH(ev, (k_rows_inverse<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
+                     st, insts, rows, nrows, a);
       else
-        hipLaunchKernelGGL((k_rows_inverse<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
-                           dim3(kRowSmallThreads), 0, st, insts, rows, nrows, a);
+        APDVM_LAUNCH(ev, (k_rows_inverse<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
+                     dim3(kRowSmallThreads), st, insts, rows, nrows, a);
       break;
   }
   return hipGetLastError();

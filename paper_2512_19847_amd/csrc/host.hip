@@ -18,15 +18,16 @@ namespace apdvm {
 // Stencil launches: tile height, WENO order (5 or 3), central-difference order (4 or 2).
 template <typename T>
 hipError_t launch_helmholtz_rhs(int, int, int, const Inst *, const Work *, int, const ArgsR &,
-                                hipStream_t);
+                                hipStream_t, const Ev &);
 template <typename T>
 hipError_t launch_update_uq(int, int, int, const Inst *, const Work *, int, const ArgsUQ &,
-                            hipStream_t);
+                            hipStream_t, const Ev &);
 template <typename T>
 hipError_t launch_stage_terms(int, int, int, const Inst *, const Work *, int, const ArgsE &,
-                              const ArgsV &, hipStream_t);
+                              const ArgsV &, hipStream_t, const Ev &);
 template <typename T>
-hipError_t launch_grad_q(int, int, const Inst *, const Work *, int, const ArgsG &, hipStream_t);
+hipError_t launch_grad_q(int, int, const Inst *, const Work *, int, const ArgsG &, hipStream_t,
+                         const Ev &);
 
 // Tile heights the stencil kernels are built for; the autotuner picks one per class.
 constexpr int kTileRows[2] = {8, 16};
@@ -42,7 +43,7 @@ inline int shape_of(int rows, int threads) {
   return -1;
 }
 hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
-                             int, const Work *, int, const ArgsSolve &, hipStream_t);
+                             int, const Work *, int, const ArgsSolve &, hipStream_t, const Ev &);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
                               int, int, double *, int, hipStream_t);
 
@@ -679,7 +680,7 @@ hipStream_t stream_of(const apdvm_ctx *c, const Launch &l) {
 }
 
 template <typename T>
-hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
+hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
   if (l.cls == kSync) {
     if (!c->overlap) return hipSuccess;
     hipStream_t from = l.sync == kFork ? c->stream : c->side;
@@ -695,23 +696,23 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l) {
   const int nt = c->ntiles[ti];
   switch (l.cls) {
     case kHelmRhs:
-      return launch_helmholtz_rhs<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.r, st);
+      return launch_helmholtz_rhs<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.r, st, ev);
     case kColsFull:
       return launch_solve_part(5, c->big_rows, c->d_inst, c->d_rows, c->nrows, c->d_colf,
-                               c->ncolf, c->d_colb, c->ncolb, l.sv, st);
+                               c->ncolf, c->d_colb, c->ncolb, l.sv, st, ev);
     case kRowsFwd:
     case kColsA:
     case kColsB:
     case kColsAInv:
     case kRowsInv:
       return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
-                               c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st);
+                               c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st, ev);
     case kUpdateUQ:
-      return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st);
+      return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st, ev);
     case kGradQ:
-      return launch_grad_q<T>(si, c->wo, c->d_inst, tiles, nt, l.g, st);
+      return launch_grad_q<T>(si, c->wo, c->d_inst, tiles, nt, l.g, st, ev);
     default:
-      return launch_stage_terms<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st);
+      return launch_stage_terms<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.e, l.v, st, ev);
   }
 }
 
@@ -726,23 +727,19 @@ apdvm_status stage0_terms(apdvm_ctx *c) {
 template <typename T>
 apdvm_status run_plan_direct(apdvm_ctx *c, const std::vector<Launch> &plan, bool sample) {
   for (const Launch &l : plan) {
-    const bool timed = sample && c->timed_class == l.cls;
-    if (timed) {
+    Ev ev;
+    if (sample && c->timed_class == l.cls) {
       if (c->ev_used == c->events.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
           return APDVM_ERR_HIP;
         c->events.push_back({a, b});
       }
-      if (hipEventRecord(c->events[c->ev_used].first, stream_of(c, l)) != hipSuccess)
-        return APDVM_ERR_HIP;
-    }
-    if (run_launch<T>(c, l) != hipSuccess) return APDVM_ERR_HIP;
-    if (timed) {
-      if (hipEventRecord(c->events[c->ev_used].second, stream_of(c, l)) != hipSuccess)
-        return APDVM_ERR_HIP;
+      ev.start = c->events[c->ev_used].first;
+      ev.stop = c->events[c->ev_used].second;
       ++c->ev_used;
     }
+    if (run_launch<T>(c, l, ev) != hipSuccess) return APDVM_ERR_HIP;
   }
   return APDVM_OK;
 }

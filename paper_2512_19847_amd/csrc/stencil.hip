@@ -780,25 +780,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
 // central difference.
 template <typename T>
 hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const Work *work,
-                                int nwork, const ArgsR &a, hipStream_t st) {
+                                int nwork, const ArgsR &a, hipStream_t st, const Ev &ev) {
   (void)wo;
   const dim3 g(nwork);
   const int key = si * 2 + (co == 4 ? 0 : 1);
   switch (key) {
-    case 0: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 256, 4>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 1: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 256, 2>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 2: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 4>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 3: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 256, 2>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 4: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 4>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 5: hipLaunchKernelGGL((k_helmholtz_rhs<T, 16, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 6: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 512, 4>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    default: hipLaunchKernelGGL((k_helmholtz_rhs<T, 8, 512, 2>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 0: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 8, 256, 4>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 1: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 8, 256, 2>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 2: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 16, 256, 4>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 3: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 16, 256, 2>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 4: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 16, 512, 4>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 5: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 16, 512, 2>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 6: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 8, 512, 4>), g, dim3(512), st, insts, work, nwork, a); break;
+    default: APDVM_LAUNCH(ev, (k_helmholtz_rhs<T, 8, 512, 2>), g, dim3(512), st, insts, work, nwork, a); break;
   }
   return hipGetLastError();
 }
 
 #define APDVM_ONE(KERNEL, TY, NT, WO, CO, ...) \
-  hipLaunchKernelGGL((KERNEL<T, TY, NT, WO, CO>), g, dim3(NT), 0, st, __VA_ARGS__)
+  APDVM_LAUNCH(ev, (KERNEL<T, TY, NT, WO, CO>), g, dim3(NT), st, __VA_ARGS__)
 #define APDVM_DISPATCH(KERNEL, ...)                                                       \
   do {                                                                                    \
     const dim3 g(nwork);                                                                  \
@@ -825,42 +825,43 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
 
 template <typename T>
 hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Work *work,
-                            int nwork, const ArgsUQ &a, hipStream_t st) {
+                            int nwork, const ArgsUQ &a, hipStream_t st, const Ev &ev) {
   (void)co;  // no central difference in this kernel
   const dim3 g(nwork);
   const int key = si * 2 + (wo == 5 ? 0 : 1);
   switch (key) {
-    case 0: hipLaunchKernelGGL((k_update_uq<T, 8, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 1: hipLaunchKernelGGL((k_update_uq<T, 8, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 2: hipLaunchKernelGGL((k_update_uq<T, 16, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 3: hipLaunchKernelGGL((k_update_uq<T, 16, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 4: hipLaunchKernelGGL((k_update_uq<T, 16, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 5: hipLaunchKernelGGL((k_update_uq<T, 16, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 6: hipLaunchKernelGGL((k_update_uq<T, 8, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    default: hipLaunchKernelGGL((k_update_uq<T, 8, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 0: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 1: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 2: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 3: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 4: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 5: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 6: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
+    default: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
   }
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_grad_q(int si, int wo, const Inst *insts, const Work *work, int nwork,
-                         const ArgsG &a, hipStream_t st) {
+                         const ArgsG &a, hipStream_t st, const Ev &ev) {
   const dim3 g(nwork);
   const int key = si * 2 + (wo == 5 ? 0 : 1);
   switch (key) {
-    case 0: hipLaunchKernelGGL((k_grad_q<T, 8, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 1: hipLaunchKernelGGL((k_grad_q<T, 8, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 2: hipLaunchKernelGGL((k_grad_q<T, 16, 256, 5>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 3: hipLaunchKernelGGL((k_grad_q<T, 16, 256, 3>), g, dim3(256), 0, st, insts, work, nwork, a); break;
-    case 4: hipLaunchKernelGGL((k_grad_q<T, 16, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 5: hipLaunchKernelGGL((k_grad_q<T, 16, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    case 6: hipLaunchKernelGGL((k_grad_q<T, 8, 512, 5>), g, dim3(512), 0, st, insts, work, nwork, a); break;
-    default: hipLaunchKernelGGL((k_grad_q<T, 8, 512, 3>), g, dim3(512), 0, st, insts, work, nwork, a); break;
+    case 0: APDVM_LAUNCH(ev, (k_grad_q<T, 8, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 1: APDVM_LAUNCH(ev, (k_grad_q<T, 8, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 2: APDVM_LAUNCH(ev, (k_grad_q<T, 16, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 3: APDVM_LAUNCH(ev, (k_grad_q<T, 16, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
+    case 4: APDVM_LAUNCH(ev, (k_grad_q<T, 16, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 5: APDVM_LAUNCH(ev, (k_grad_q<T, 16, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 6: APDVM_LAUNCH(ev, (k_grad_q<T, 8, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
+    default: APDVM_LAUNCH(ev, (k_grad_q<T, 8, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
   }
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const Work *work,
-                              int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st) {
+                              int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st,
+                              const Ev &ev) {
   APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
   return hipGetLastError();
 }
@@ -869,13 +870,14 @@ hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const W
 
 #define APDVM_INST(T)                                                                           \
   template hipError_t launch_helmholtz_rhs<T>(int, int, int, const Inst *, const Work *, int,  \
-                                              const ArgsR &, hipStream_t);                     \
+                                              const ArgsR &, hipStream_t, const Ev &);         \
   template hipError_t launch_update_uq<T>(int, int, int, const Inst *, const Work *, int,      \
-                                          const ArgsUQ &, hipStream_t);                        \
+                                          const ArgsUQ &, hipStream_t, const Ev &);            \
   template hipError_t launch_stage_terms<T>(int, int, int, const Inst *, const Work *, int,    \
-                                            const ArgsE &, const ArgsV &, hipStream_t);        \
+                                            const ArgsE &, const ArgsV &, hipStream_t,         \
+                                            const Ev &);                                       \
   template hipError_t launch_grad_q<T>(int, int, const Inst *, const Work *, int,              \
-                                       const ArgsG &, hipStream_t);
+                                       const ArgsG &, hipStream_t, const Ev &);
 APDVM_INST(double)
 APDVM_INST(float)
 #undef APDVM_INST
