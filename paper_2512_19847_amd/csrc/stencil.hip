@@ -32,12 +32,13 @@ __device__ __forceinline__ void keep(T &x) {
   asm volatile("" : "+v"(x));
 }
 
-// Resident waves per SIMD the WENO kernels ask the register allocator for.  The 64 x 8
-// tiles on 512 threads leave LDS for three workgroups per CU (six waves per SIMD) when a
-// thread stays within 80 VGPRs; the other shapes are bounded by LDS before registers.
+// Resident waves per SIMD the WENO kernels ask the register allocator for: six (at most
+// 80 VGPRs) for the 64 x 8 tiles and for 512 threads, where the LDS of a tile leaves room
+// for that many (three workgroups of 512 threads or six of 256 per CU); the 64 x 16 tiles
+// on 256 threads are bounded by LDS before registers.
 template <int TY, int NT>
 constexpr int weno_waves_per_eu() {
-  return NT == 512 && TY == 8 ? 6 : 1;
+  return TY == 8 || NT == 512 ? 6 : 1;
 }
 
 // Work item of this workgroup.  The hardware hands consecutive workgroups to the 8
@@ -472,18 +473,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
   using Gm = Geo<TY, NT>;
-  // v1, v2 and the partner velocity, halved for the fluxes
-  __shared__ T sV1[Gm::PL], sV2[Gm::PL], sP1[Gm::PL], sP2[Gm::PL];
+  // v1, v2 and one partner component at a time, halved for the fluxes (the second
+  // component arrives in registers during the first round and replaces the first)
+  __shared__ T sV1[Gm::PL], sV2[Gm::PL], sP[Gm::PL];
   __shared__ T fx[Gm::FXN], fy[Gm::FYN];
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
+  Stage<TY, NT, 1, T> sp2;
   {
-    Stage<TY, NT, 4, T> st;
-    const Gp<const T> g[4] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0]),
-                     tplane<T>(I, a.partner[1])};
+    Stage<TY, NT, 3, T> st;
+    const Gp<const T> g[3] = {tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1]), tplane<T>(I, a.partner[0])};
     st.load(g, nx, ny, wk.a, wk.b);
-    T *l[4] = {sV1, sV2, sP1, sP2};
+    const Gp<const T> g2[1] = {tplane<T>(I, a.partner[1])};
+    sp2.load(g2, nx, ny, wk.a, wk.b);
+    T *l[3] = {sV1, sV2, sP};
     st.store(l, T(0.5));
   }
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
@@ -493,8 +497,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   T hu1[Gm::ROWS], hu2[Gm::ROWS], dv[Gm::ROWS];
   // first row of B(v) = (-v1, v2), dissipation on u1
-  faces<TY, NT, WO, T, true, true>(fx, fy, sV1, sP1, T(-1), sV2, sP1, T(1));
+  faces<TY, NT, WO, T, true, true>(fx, fy, sV1, sP, T(-1), sV2, sP, T(1));
   __syncthreads();
+  {
+    T *l[1] = {sP};
+    sp2.store(l, T(0.5));
+  }
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     hu1[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
@@ -502,7 +510,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
   __syncthreads();
   // second row of B(v) = (v2, v1), dissipation on u2
-  faces<TY, NT, WO, T, true, true>(fx, fy, sV2, sP2, T(1), sV1, sP2, T(1));
+  faces<TY, NT, WO, T, true, true>(fx, fy, sV2, sP, T(1), sV1, sP, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -607,8 +615,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
 //
 // theta(i) is staged with a halo of 3 + reach, so that D0 theta is known on the whole
 // WENO-staged region: every thread completes u on the cells it stages (the halo ones
-// redundantly, in the same arithmetic as their owner) and writes u, Hu and Ltheta on its
-// interior cells.  theta uses the face buffers, which the flux rounds only need later.
+// redundantly, in the same arithmetic as their owner), then u, Hu and Ltheta are written
+// for the interior cells.  theta uses the face buffers, which the flux rounds only need
+// later.
 template <typename T, int TY, int NT, int WO, int CO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
@@ -625,6 +634,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  const bool col = gx < nx;
   if (a.us[0] != kNoSlot) {
     SU su;
     const Gp<const double> g2[2] = {dplane(I, a.us[0]), dplane(I, a.us[1])};
@@ -633,23 +645,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const Gp<const double> gt[1] = {dplane(I, a.th)};
     sw.load(gt, nx, ny, wk.a, wk.b);
     const bool want_hu = a.hu[0] != kNoSlot, want_lt = a.out_lt != kNoSlot;
-    // pointwise inputs of the interior cells among the staged ones
-    long long go[SU::IT];
-    T hv1[SU::IT], hv2[SU::IT], dd[SU::IT];
+    // pointwise inputs of this thread's interior cells
+    T hv1[Gm::ROWS], hv2[Gm::ROWS], dd[Gm::ROWS];
 #pragma unroll
-    for (int it = 0; it < SU::IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
-      const int gx = wk.a + lx - kHalo, gy = wk.b + ly - kHalo;
-      const bool in = idx < Gm::PL && lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo &&
-                      ly < kHalo + TY && gx < nx && gy < ny;
-      go[it] = in ? (long long)gy * nx + gx : -1;
-      hv1[it] = hv2[it] = dd[it] = T(0);
-      if (in && want_hu) {
-        hv1[it] = tplane<T>(I, a.hu[0])[go[it]];
-        hv2[it] = tplane<T>(I, a.hu[1])[go[it]];
+    for (int r = 0; r < Gm::ROWS; ++r) {
+      const int gy = wk.b + ty0 + Gm::WV * r;
+      hv1[r] = hv2[r] = dd[r] = T(0);
+      if (col && gy < ny) {
+        const long long g = (long long)gy * nx + gx;
+        if (want_hu) {
+          hv1[r] = tplane<T>(I, a.hu[0])[g];
+          hv2[r] = tplane<T>(I, a.hu[1])[g];
+        }
+        if (want_lt) dd[r] = tplane<T>(I, a.ddb)[g];
       }
-      if (in && want_lt) dd[it] = tplane<T>(I, a.ddb)[go[it]];
     }
     double *sT = reinterpret_cast<double *>(sF);
     {
@@ -659,27 +668,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     __syncthreads();
     const double cth = I.dt * a.aii;
     const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
-    const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
 #pragma unroll
     for (int it = 0; it < SU::IT; ++it) {
       const int idx = threadIdx.x + it * NT;
       if (idx >= Gm::PL) break;
       const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
       const int c = (ly + C::R) * SW::W + lx + C::R;
-      const double dx = C::d1(sT, c, 1, f1x), dy = C::d1(sT, c, SW::W, f1y);
-      const double u1 = su.v[0][it] - cth * dx, u2 = su.v[1][it] - cth * dy;
+      const double u1 = su.v[0][it] - cth * C::d1(sT, c, 1, f1x);
+      const double u2 = su.v[1][it] - cth * C::d1(sT, c, SW::W, f1y);
       sU1[idx] = T(0.5) * (T)u1;
       sU2[idx] = T(0.5) * (T)u2;
-      if (go[it] >= 0) {
-        tplane<T>(I, a.out_u[0])[go[it]] = (T)u1;
-        tplane<T>(I, a.out_u[1])[go[it]] = (T)u2;
+    }
+    __syncthreads();
+    // u, Hu and Ltheta of this thread's interior cells (the staged u is halved exactly)
+    if (col) {
+      const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+#pragma unroll
+      for (int r = 0; r < Gm::ROWS; ++r) {
+        const int ly = ty0 + Gm::WV * r;
+        const int gy = wk.b + ly;
+        if (gy >= ny) break;
+        const long long g = (long long)gy * nx + gx;
+        const int c = Gm::at(tx, ly);
+        const int cw = (ly + kHalo + C::R) * SW::W + tx + kHalo + C::R;
+        tplane<T>(I, a.out_u[0])[g] = T(2) * sU1[c];
+        tplane<T>(I, a.out_u[1])[g] = T(2) * sU2[c];
         if (want_hu) {
-          tplane<T>(I, a.hu[0])[go[it]] = (T)((double)hv1[it] + dx);
-          tplane<T>(I, a.hu[1])[go[it]] = (T)((double)hv2[it] + dy);
+          tplane<T>(I, a.hu[0])[g] = (T)((double)hv1[r] + C::d1(sT, cw, 1, f1x));
+          tplane<T>(I, a.hu[1])[g] = (T)((double)hv2[r] + C::d1(sT, cw, SW::W, f1y));
         }
         if (want_lt) {
-          const double lap = C::d2(sT, c, 1, f2x) + C::d2(sT, c, SW::W, f2y);
-          tplane<T>(I, a.out_lt)[go[it]] = (T)((double)dd[it] + lap);
+          const double lap = C::d2(sT, cw, 1, f2x) + C::d2(sT, cw, SW::W, f2y);
+          tplane<T>(I, a.out_lt)[g] = (T)((double)dd[r] + lap);
         }
       }
     }
@@ -690,9 +710,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     T *l2[2] = {sU1, sU2};
     su.store(l2, T(0.5));
   }
-  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
-  const int gx = wk.a + tx;
-  const bool col = gx < nx;
   __syncthreads();
   const T ihx = T(I.ihx), ihy = T(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
