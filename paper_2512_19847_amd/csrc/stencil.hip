@@ -95,42 +95,48 @@ __device__ __forceinline__ T ind2(const Win<T> &w) {
   const T x = fma(t, t, w.e);
   return x * x;
 }
-// Candidates: the window (a, b, c) evaluated one and a half cells right of b, and the
-// window centred on c evaluated half a cell towards d.
+// Candidates at face i+1/2: q0 = (2 a - 7 b + 11 c)/6 from cells i-2, i-1, i, and the
+// other two scaled by their linear weights' ratios to the first: 6 q1 = -b + 5 c + 2 d from
+// cells i-1, i, i+1, and 3 q2 = (2 c + 5 d - e)/2 from cells i, i+1, i+2.
 template <typename T>
 __device__ __forceinline__ T cfar(T a, T b, T c) {
   return fma(T(1.0 / 3.0), a, fma(T(-7.0 / 6.0), b, T(11.0 / 6.0) * c));
 }
 template <typename T>
-__device__ __forceinline__ T cnear(T b, T c, T d) {
-  return fma(T(-1.0 / 6.0), b, fma(T(5.0 / 6.0), c, T(1.0 / 3.0) * d));
+__device__ __forceinline__ T c6(T b, T c, T d) {
+  return fma(T(5), c, fma(T(2), d, -b));
+}
+template <typename T>
+__device__ __forceinline__ T c3(T c, T d, T e) {
+  return fma(T(2.5), d, fma(T(-0.5), e, c));
 }
 
-// float64 quotient through the hardware reciprocal refined by Newton steps.
+// float64 quotient through the hardware reciprocal, one Newton step and a residual
+// correction (the reciprocal's error is squared by the Newton step, far below 2^-26,
+// so the corrected quotient is within an ulp).
 __device__ __forceinline__ double qdiv(double n, double d) {
   double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
   r = fma(r, fma(-d, r, 1.0), r);
   const double q = n * r;
   return fma(r, fma(-d, q, n), q);
 }
 
-// Numerator and denominator of one reconstruction: weights proportional to
-// d_k / s_k with s_k = (eps_w + beta_k)^2, normalised through products of the other two
-// (float64; the common factor 10 / (s0 s1 s2) cancels), or through reciprocals (float,
-// where the products could overflow).
-__device__ __forceinline__ void nd(double s0, double s1, double s2, double q0, double q1,
-                                   double q2, double &n, double &den) {
-  const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
-  n = fma(w0, q0, fma(w1, q1, w2 * q2));
-  den = w0 + w1 + w2;
+// Numerator and denominator of one reconstruction from s_k = (eps_w + beta_k)^2, q0,
+// Q1 = 6 q1 and Q2 = 3 q2: the weights d_k / s_k with d = (1, 6, 3)/10, multiplied
+// through by 10 s0 s1 s2 (float64), or by 10 (float, through reciprocals, where the
+// products could overflow).
+__device__ __forceinline__ void nd(double s0, double s1, double s2, double q0, double Q1,
+                                   double Q2, double &n, double &den) {
+  const double w0 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
+  n = fma(w0, q0, fma(p02, Q1, p01 * Q2));
+  den = fma(6.0, p02, fma(3.0, p01, w0));
 }
-__device__ __forceinline__ void nd(float s0, float s1, float s2, float q0, float q1, float q2,
+__device__ __forceinline__ void nd(float s0, float s1, float s2, float q0, float Q1, float Q2,
                                    float &n, float &den) {
-  const float w0 = 0.1f * __builtin_amdgcn_rcpf(s0), w1 = 0.6f * __builtin_amdgcn_rcpf(s1),
-              w2 = 0.3f * __builtin_amdgcn_rcpf(s2);
-  n = fma(w0, q0, fma(w1, q1, w2 * q2));
-  den = w0 + w1 + w2;
+  const float r0 = __builtin_amdgcn_rcpf(s0), r1 = __builtin_amdgcn_rcpf(s1),
+              r2 = __builtin_amdgcn_rcpf(s2);
+  n = fma(r0, q0, fma(r1, Q1, r2 * Q2));
+  den = fma(6.0f, r1, fma(3.0f, r2, r0));
 }
 // n+/d+ + n-/d- with one division
 __device__ __forceinline__ double sum2(double np, double dp, double nm, double dm) {
@@ -149,13 +155,13 @@ template <typename T>
 __device__ __forceinline__ T flux_sym(T c0, T c1, T c2, T c3, T c4, T c5) {
   const Win<T> wa = win(c0, c1, c2), wb = win(c1, c2, c3), wc = win(c2, c3, c4),
                wd = win(c3, c4, c5);
-  const T M = cnear(c1, c2, c3);  // window i at i+1/2
-  const T N = cnear(c4, c3, c2);  // window i+1 at i+1/2
+  const T M6 = c6(c1, c2, c3);  // 6 x (window i at i+1/2)
+  const T N6 = c6(c4, c3, c2);  // 6 x (window i+1 at i+1/2)
   const T P = cfar(c0, c1, c2);
   const T Pm = cfar(c5, c4, c3);
   T np, dp, nm, dm;
-  nd(ind0(wa), ind1(wb), ind2(wc), P, M, N, np, dp);
-  nd(ind2(wd), ind1(wc), ind0(wb), Pm, N, M, nm, dm);
+  nd(ind0(wa), ind1(wb), ind2(wc), P, M6, T(0.5) * N6, np, dp);
+  nd(ind2(wd), ind1(wc), ind0(wb), Pm, N6, T(0.5) * M6, nm, dm);
   return sum2(np, dp, nm, dm);
 }
 
@@ -165,12 +171,12 @@ template <typename T>
 __device__ __forceinline__ T flux_lf(const T *p, const T *m) {
   const Win<T> pa = win(p[0], p[1], p[2]), pb = win(p[1], p[2], p[3]), pc = win(p[2], p[3], p[4]);
   const T q0 = cfar(p[0], p[1], p[2]);
-  const T q1 = cnear(p[1], p[2], p[3]);
-  const T q2 = cnear(p[4], p[3], p[2]);
+  const T q1 = c6(p[1], p[2], p[3]);
+  const T q2 = c3(p[2], p[3], p[4]);
   const Win<T> mb = win(m[1], m[2], m[3]), mc = win(m[2], m[3], m[4]), md = win(m[3], m[4], m[5]);
   const T r0 = cfar(m[5], m[4], m[3]);
-  const T r1 = cnear(m[4], m[3], m[2]);
-  const T r2 = cnear(m[1], m[2], m[3]);
+  const T r1 = c6(m[4], m[3], m[2]);
+  const T r2 = c3(m[3], m[2], m[1]);
   T np, dp, nm, dm;
   nd(ind0(pa), ind1(pb), ind2(pc), q0, q1, q2, np, dp);
   nd(ind2(md), ind1(mc), ind0(mb), r0, r1, r2, nm, dm);
