@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 METRIC = "IMEX-RK cell-pop updates/s + %HBM roofline; FP32-split/batched vs FP64"
 UNIT = "cell-population updates/s"
 HBM_PEAK_GBS = 8000.0
-TIMING_STRIDE = 16
+TIMING_STRIDE = 32
 
 
 def recorded_traffic(kernel_class, workload_name, precision):
