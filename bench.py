@@ -23,6 +23,8 @@ roofline.traffic: HBM bytes per launch of that kernel from the rocprofv3 FETCH_S
 WRITE_SIZE runs recorded under profiles/ (each scaled by what the counter reads for a
 device copy of known size), reported only for the workload, precision and kernel they
 were taken on and while the kernel sources still hash to the recorded value; else null.
+roofline.traffic_frac: that measured traffic / the kernel's mean duration / 8 TB/s;
+roofline.step_frac: algorithmic bytes of the whole step / step time / 8 TB/s.
 cpu_baseline: the FP64 NumPy oracle on a bounded sample of the same workload, on the
 host (one core: NumPy's elementwise kernels and pocketfft are single-threaded).
 """
@@ -119,8 +121,19 @@ def cpu_baseline(cases, tab, budget_s=20.0):
         el = time.perf_counter() - t0
         if el >= budget_s or k >= 3 * len(cases):
             break
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0))
     return {"value": 6.0 * done_cells / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{k} instance-steps of the same workload ({el:.1f} s)"}
+            "sample": f"{k} instance-steps of the same workload ({el:.1f} s) on one core of "
+                      f"{avail} available ({model})"}
 
 
 def compare_fp64(apdvm, torch, stream, sim, cases, tab, args, sec):
@@ -230,6 +243,7 @@ def main():
     sim.timing_enable(-1)
     sec = t1 - t0
 
+    traffic = recorded_traffic(apdvm.KERNEL_CLASSES[dom], cfg["workload"], args.precision)
     bytes_step, launches = sim.traffic(dom)
     per_launch = bytes_step / launches
     mean_s = ms_dom / n_dom / 1e3
@@ -263,8 +277,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(apdvm.KERNEL_CLASSES[dom], cfg["workload"],
-                                                 args.precision),
+                     "traffic": traffic,
+                     # measured HBM bytes (rocprofv3 counters) / mean launch time / peak
+                     "traffic_frac": traffic / mean_s / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "bytes_per_launch": per_launch, "mean_launch_us": mean_s * 1e6,
                      "launches_timed": n_dom,
                      # every kernel of the step: algorithmic bytes / step time
