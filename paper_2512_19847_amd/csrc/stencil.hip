@@ -3,6 +3,11 @@
 // space discretisation of Section 3.2: WENO5 (Jiang-Shu) reconstruction of the
 // Lax-Friedrichs split fluxes and fourth-order central differences.
 //
+// Per stage: k_helmholtz_rhs (the right-hand side of step 2, before the solve);
+// k_update_uq and k_grad_q (everything of steps 3 and 4 and of the stage terms that does
+// not involve theta(i): they run while the solve produces it); k_stage_terms (u(i) with
+// its theta gradient, the rest of the stage terms, and step 1 of the next stage).
+//
 // Tiling: a workgroup of NT threads owns a 64 x TY tile of one instance (64 x 8 or
 // 64 x 16 on 256 or 512 threads, chosen per kernel class by the host autotuner).  Every
 // input plane is staged once in LDS with a 3-cell periodic halo (WENO5 reads 3 cells on
@@ -16,7 +21,7 @@
 // row-contiguous.
 //
 // Precision: T is the transport type (double or float).  theta, the Helmholtz
-// right-hand side and every history sum feeding an implicit relaxation or the
+// right-hand side, u*(i) and every history sum feeding an implicit relaxation or the
 // right-hand side are float64 whatever T is.
 #include "common.hpp"
 
