@@ -186,12 +186,20 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
 #pragma unroll
       for (int r = 0; r < R; ++r) v[p][r] = buf[lp((j + r * nbf) * es + b * bs)];
       if (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          double2 w = tw_at(tws, lb, k * r * twstep);
-          if (DIR > 0) w.y = -w.y;
-          v[p][r] = cmul(v[p][r], w);
+        // w^r for r = 1..R-1 from one table lookup: powers by products of depth <= 3
+        double2 w[R];
+        w[1] = tw_at(tws, lb, k * twstep);
+        if (DIR > 0) w[1].y = -w[1].y;
+        if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
+        if constexpr (R >= 4) w[3] = cmul(w[2], w[1]);
+        if constexpr (R == 8) {
+          w[4] = cmul(w[2], w[2]);
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
         }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], w[r]);
       }
       dft<R, DIR>(v[p]);
       dst[p] = (jq * Ns * R + k) * es + b * bs;
