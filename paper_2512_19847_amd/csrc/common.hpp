@@ -143,7 +143,7 @@ struct ArgsR {
 // Steps 3 and 4 short of theta(i), which the Helmholtz solve of the same stage is still
 // producing when this runs:
 // hu = D_W.B(v(i))[dissipation on u(i-1)]
-// u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii hu            (float64 slots)
+// u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii hu            (formed in float64)
 // Hq = (tau/2) D0_W.v(i)
 // q(i) = [te2 q^n - dt a_ii Hq - dt sum_j cG_j Gq(j)] kinv,   Gq(j) = Hq(j) + q(j)
 // The stage-terms launch of the stage completes u(i) = u*(i) - dt a_ii D0 theta(i) and
@@ -158,7 +158,7 @@ struct ArgsUQ {
   double cH[kMaxStages];
   int nG, G[kMaxStages];
   double cG[kMaxStages];
-  int out_us[2];  // u*(i), float64 slots
+  int out_us[2];  // u*(i)
   int out_q;
   int out_hu[2], out_gq;  // hu and Gq; kNoSlot when no later stage needs them
 };
@@ -179,7 +179,7 @@ struct ArgsG {
 // the next stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients
 // of this stage's E and v in that step (at_{k,j} and a_{k,j}), which stay in registers.
 struct ArgsE {
-  int us[2];          // u*(i) (float64 slots, halo 3) or kNoSlot
+  int us[2];          // u*(i) (halo 3) or kNoSlot
   int u[2];           // u of a state set (halo 3), when us[0] == kNoSlot
   int g[2];           // G of this stage (pointwise)
   int v[2];           // v of this stage (pointwise, for the fused step 1)

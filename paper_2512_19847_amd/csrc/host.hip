@@ -182,7 +182,8 @@ struct Layout {
   int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
   int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
   int ddb, G[2];
-  int Th[kMaxStages], Us[2], R, spec;  // float64
+  int Us[2];                      // u*(i) of the current stage
+  int Th[kMaxStages], R, spec;    // float64
   int ntrans, ndbl;
 };
 
@@ -215,8 +216,8 @@ Layout make_layout(int s) {
   L.ddb = t++;
   L.G[0] = t++;
   L.G[1] = t++;
-  L.Us[0] = d++;
-  L.Us[1] = d++;
+  L.Us[0] = t++;
+  L.Us[1] = t++;
   L.R = d++;
   L.spec = d++;
   L.ntrans = t;
@@ -642,7 +643,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     }
     // the partner is u^n for the first stage: read once with u^n
     const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
-    l.bytes = (reads + 1 + (keep ? 3 : 0)) * pt + 2 * pd;
+    l.bytes = (reads + 1 + 2 + (keep ? 3 : 0)) * pt;
     plan.push_back(l);
     plan.push_back(grad_q_launch(c, qi, v1, v2));
     sync(kJoin);
@@ -664,8 +665,8 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ae.out_e[1] = est ? L.E[ej][1] : kNoSlot;
     ae.out_du = L.Du[ej];
     ae.out_lt = keep ? L.Lt[i] : kNoSlot;
-    // u*, theta, G, v in; u, D0.u, E out; with keep hu and ddb in, Hu and Ltheta out
-    l.bytes = 3 * pd + (2 + 2 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
+    // theta, u*, G, v in; u, D0.u, E out; with keep hu and ddb in, Hu and Ltheta out
+    l.bytes = pd + (2 + 2 + 2 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
     if (last)
       fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
     else

@@ -21,7 +21,7 @@
 // row-contiguous.
 //
 // Precision: T is the transport type (double or float).  theta, the Helmholtz
-// right-hand side, u*(i) and every history sum feeding an implicit relaxation or the
+// right-hand side and every history sum feeding an implicit relaxation or the
 // right-hand side are float64 whatever T is.
 #include "common.hpp"
 
@@ -565,8 +565,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const long long g = (long long)gy * nx + gx;
     const double Hq = htau * (double)dv[r];
     const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
-    dplane(I, a.out_us[0])[g] = un1[r] - dt * (h1[r] + aii * (double)hu1[r]);
-    dplane(I, a.out_us[1])[g] = un2[r] - dt * (h2[r] + aii * (double)hu2[r]);
+    tplane<T>(I, a.out_us[0])[g] = (T)(un1[r] - dt * (h1[r] + aii * (double)hu1[r]));
+    tplane<T>(I, a.out_us[1])[g] = (T)(un2[r] - dt * (h2[r] + aii * (double)hu2[r]));
     tplane<T>(I, a.out_q)[g] = (T)q;
     if (a.out_hu[0] != kNoSlot) {
       tplane<T>(I, a.out_hu[0])[g] = hu1[r];
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
                                                                  int nwork, ArgsE a, ArgsV nv) {
   using Gm = Geo<TY, NT>;
   using C = Central<CO>;
-  using SU = Stage<TY, NT, 2, double>;             // u*, float64
+  using SU = Stage<TY, NT, 2, T>;                  // u*
   using SW = Stage<TY, NT, 1, double, kHalo + C::R>;  // theta(i), wide halo
   constexpr int FN = Gm::FXN + Gm::FYN;
   constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(T));
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   const bool col = gx < nx;
   if (a.us[0] != kNoSlot) {
     SU su;
-    const Gp<const double> g2[2] = {dplane(I, a.us[0]), dplane(I, a.us[1])};
+    const Gp<const T> g2[2] = {tplane<T>(I, a.us[0]), tplane<T>(I, a.us[1])};
     su.load(g2, nx, ny, wk.a, wk.b);
     SW sw;
     const Gp<const double> gt[1] = {dplane(I, a.th)};
@@ -685,8 +685,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       if (idx >= Gm::PL) break;
       const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
       const int c = (ly + C::R) * SW::W + lx + C::R;
-      const double u1 = su.v[0][it] - cth * C::d1(sT, c, 1, f1x);
-      const double u2 = su.v[1][it] - cth * C::d1(sT, c, SW::W, f1y);
+      const double u1 = (double)su.v[0][it] - cth * C::d1(sT, c, 1, f1x);
+      const double u2 = (double)su.v[1][it] - cth * C::d1(sT, c, SW::W, f1y);
       sU1[idx] = T(0.5) * (T)u1;
       sU2[idx] = T(0.5) * (T)u2;
     }
