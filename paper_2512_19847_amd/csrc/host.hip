@@ -1582,9 +1582,11 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       hipEvent_t e0 = nullptr, e1 = nullptr;
       ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
       for (int on = 0; ok && on < 2; ++on) {
-        ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 1) == APDVM_OK;
+        // two warm-up steps: in graph mode each parity's graph is captured and uploaded
+        // before the timed steps
+        ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 2) == APDVM_OK;
         ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
-        ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
+        ok = ok && apdvm_step(c, 2 * steps_per_trial) == APDVM_OK;
         ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
              hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
