@@ -196,15 +196,13 @@ apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
 apdvm_status apdvm_get_overlap(apdvm_ctx *ctx, int32_t *on);
 
 /* Kernel classes of a step, used by the profiling and tuning calls below:
- * 0 step-2 right-hand side, 1 Helmholtz rows forward FFT, 2 Helmholtz column FFT first
- * factor, 3 Helmholtz column FFT second factor with the symbol divide and its inverse,
- * 4 inverse column FFT first factor, 5 Helmholtz rows inverse FFT, 6 steps 3 and 4
- * short of theta (q, and u without its theta gradient), 7 completion of u with theta and
- * the stage terms reused by later stages, together with step 1 (the relaxation of v) of
- * the next stage, 8 single-pass Helmholtz columns (FFT, symbol divide, inverse FFT;
- * replaces 2-4 when the autotuner picks it), 9 the q part te2 D_W q of the stage terms
- * (WENO of q +- v, before theta is known). */
-#define APDVM_NUM_KERNEL_CLASSES 10
+ * 0 step-2 right-hand side, 1 Helmholtz rows forward FFT (half spectra stored
+ * column-major), 2 Helmholtz columns (FFT along y of whole contiguous columns, symbol
+ * divide, inverse FFT), 3 Helmholtz rows inverse FFT, 4 steps 3 and 4 short of theta (q,
+ * and u without its theta gradient), 5 completion of u with theta and the stage terms
+ * reused by later stages, together with step 1 (the relaxation of v) of the next stage,
+ * 6 the q part te2 D_W q of the stage terms (WENO of q +- v, before theta is known). */
+#define APDVM_NUM_KERNEL_CLASSES 7
 
 /* From now on time every launch of kernel class cls with a pair of HIP events that
  * hipExtLaunchKernelGGL sets at the start and end of the kernel's own execution (cls = -1
@@ -231,17 +229,15 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
                            int32_t *launches_per_step);
 
 /* Launch-shape choices as apdvm_autotune reports them and apdvm_set_tuning takes them
- * (APDVM_TUNING_LEN entries): entries 0..9 per kernel class, with the tile height (8 or
- * 16 rows of 64 cells) for the stencil classes 0, 6, 7 and 9 and 1 / 0 for the FFT
- * column classes in use / not in use (the other entries read 1); entries 10, 11, 12 and
- * 13 the workgroup threads (256 or 512) of classes 0, 6, 7 and 9.  Shapes: 64 x 8 or
- * 64 x 16 tiles on 256 or 512 threads. */
-#define APDVM_TUNING_LEN 14
+ * (APDVM_TUNING_LEN entries): entries 0..6 per kernel class, with the tile height (8 or
+ * 16 rows of 64 cells) for the stencil classes 0, 4, 5 and 6 (the FFT entries read 1);
+ * entries 7, 8, 9 and 10 the workgroup threads (256 or 512) of classes 0, 4, 5 and 6.
+ * Shapes: 64 x 8 or 64 x 16 tiles on 256 or 512 threads. */
+#define APDVM_TUNING_LEN 11
 
-/* Autotune the launch shapes: for the stencil kernel classes (0, 6, 7, 9) each shape,
- * and for the Helmholtz columns the four-step form (classes 2-4) against the single pass
- * (class 8, only when every ny <= 2048), are timed with HIP events over steps_per_trial
- * steps of the live simulation; the fastest is kept.  Then whole steps with and without
+/* Autotune the launch shapes: for the stencil kernel classes (0, 4, 5, 6) each shape is
+ * timed with HIP events over steps_per_trial steps of the live simulation; the fastest is
+ * kept.  Then whole steps with and without
  * the second stream (apdvm_set_overlap) are timed in the context's launch mode and the
  * faster kept.  The state, the step counter and the launch mode are restored afterwards
  * (this call allocates a temporary device copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
@@ -251,9 +247,8 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
 apdvm_status apdvm_autotune(apdvm_ctx *ctx, int32_t steps_per_trial, int32_t *choice);
 
 /* Set the launch shapes directly (APDVM_TUNING_LEN entries, the format apdvm_autotune
- * reports): a (tile height, threads) pair among the shapes above for classes 0, 6, 7 and
- * 9, and choice[8] != 0 for the single-pass Helmholtz columns (needs every ny <= 2048); the
- * other entries are ignored.  APDVM_ERR_ARG for any other pair.  Host-only. */
+ * reports): a (tile height, threads) pair among the shapes above for classes 0, 4, 5 and
+ * 6; the other entries are ignored.  APDVM_ERR_ARG for any other pair.  Host-only. */
 apdvm_status apdvm_set_tuning(apdvm_ctx *ctx, const int32_t *choice);
 
 /* Release the context (and the workspace if the library allocated it).  NULL ok. */

@@ -25,9 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libapdvm.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "apdvm.h")
 
 FP64, FP32_SPLIT = 0, 1
-KERNEL_CLASSES = ("helmholtz_rhs", "fft_rows_forward", "fft_columns_a", "fft_columns_b",
-                  "fft_columns_a_inverse", "fft_rows_inverse", "update_uq",
-                  "stage_terms_relax_v", "fft_columns_single_pass", "grad_q")
+KERNEL_CLASSES = ("helmholtz_rhs", "fft_rows_forward", "fft_columns", "fft_rows_inverse",
+                  "update_uq", "stage_terms_relax_v", "grad_q")
 # Entries of the launch-shape choice array: one per kernel class, then the workgroup
 # threads of the four stencil classes.
 TUNED_STENCIL = ("helmholtz_rhs", "update_uq", "stage_terms_relax_v", "grad_q")
@@ -329,28 +328,25 @@ class Simulation:
 
     def autotune(self, steps_per_trial=3):
         """Pick the launch shapes by timing; returns a dict over TUNING_KEYS: tile rows of
-        each stencil class, 1 / 0 for the FFT column forms in use, and the workgroup
-        threads of each stencil class."""
+        each stencil class (1 for the FFT classes) and the workgroup threads of each
+        stencil class."""
         arr = (c_int32 * len(TUNING_KEYS))()
         _check(lib().apdvm_autotune(self.ctx, int(steps_per_trial), arr), "autotune")
         return dict(zip(TUNING_KEYS, list(arr)))
 
-    def set_tuning(self, tile_rows=16, single_pass_columns=False, threads=256):
+    def set_tuning(self, tile_rows=16, threads=256):
         """Force the launch shapes: tile_rows (8 or 16) and threads (256 or 512) for every
-        stencil class, or a dict in the format autotune() returns (then
-        the other arguments are read from it); single_pass_columns selects the form of
-        the Helmholtz column FFT."""
+        stencil class, or a dict in the format autotune() returns (then threads is read
+        from it too)."""
         arr = (c_int32 * len(TUNING_KEYS))()
         if isinstance(tile_rows, dict):
             for k, name in enumerate(TUNING_KEYS):
                 arr[k] = int(tile_rows.get(name, 256 if name.startswith("threads_") else 1))
-            single_pass_columns = bool(tile_rows["fft_columns_single_pass"])
         else:
             for k in range(len(KERNEL_CLASSES)):
                 arr[k] = int(tile_rows)
             for k in range(len(KERNEL_CLASSES), len(TUNING_KEYS)):
                 arr[k] = int(threads)
-        arr[KERNEL_CLASSES.index("fft_columns_single_pass")] = 1 if single_pass_columns else 0
         _check(lib().apdvm_set_tuning(self.ctx, arr), "set_tuning")
 
     def launches_per_step(self):

@@ -54,15 +54,15 @@ constexpr int kNoSlot = -1;
 constexpr int kTileX = 64;
 constexpr int kHalo = 3;
 
-// FFT row workgroups: capacity in complex float64 values held in LDS, and threads.
-// The large form takes rows longer than kRowSmallCap.
+// FFT workgroups: capacity in complex float64 values held in LDS, and threads.  The row
+// and column kernels each take the smallest form that holds a whole row (column) of
+// every instance.
 constexpr int kFftCap = 8192;
 constexpr int kFftThreads = 1024;
 constexpr int kRowSmallCap = 1024;
 constexpr int kRowSmallThreads = 128;
-// FFT column tiles: columns per tile (16 complex float64 = 256 contiguous bytes per row).
-constexpr int kColWidth = 16;
-constexpr int kColBTarget = 1024;  // complex values per column-B tile
+constexpr int kColMidCap = 2048;
+constexpr int kColMidThreads = 256;
 
 // Two-level twiddle table of a length-n transform, staged into LDS by every FFT kernel:
 // with B = 2^lb the smallest power of two whose square is at least n, entries
@@ -74,7 +74,6 @@ struct FftPlan {
   int n;                  // transform length
   int npass;              // number of Stockham passes
   int radix[kMaxPasses];  // radices (2, 3, 4 or 8), first pass first
-  const double2 *tw;      // tw[m] = exp(-2 pi i m / n), m = 0..n-1 (device)
   const double2 *tw2;     // two-level table (device), ntw entries
   int lb, ntw;
 };
@@ -88,16 +87,13 @@ struct Inst {
   double kinv[kMaxStages];   // 1 / (tau eps^2 + dt a_ii)
   double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
   double inv_nxny;           // 1 / (nx ny)
-  FftPlan fx, fy;            // lengths nx and ny (fy supplies the ny-point twiddles)
-  FftPlan f1, f2;            // four-step factors of the column FFT: ny = n1 * n2
+  FftPlan fx, fy;            // lengths nx and ny
   const double *lam_x;       // nx/2 + 1 values of the x symbol of D_Delta
   const double *lam_y;       // ny values of the y symbol
   void *tbase;               // transport arena
   double *dbase;             // float64 arena
   int row_pairs_per_block;   // FFT row kernels: row pairs per workgroup
-  int cols_per_block;        // FFT column kernels: complex columns per tile
-  int groups_per_block;      // FFT column kernel B: k1 groups per tile
-  int cols_full_per_block;   // single-pass column kernel: columns per tile (0: unused)
+  int cols_per_block;        // FFT column kernel: whole columns per workgroup
 };
 
 // Work table entry: instance and the first cell / row pair / column of the block.
@@ -194,7 +190,8 @@ struct ArgsE {
 };
 
 // Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec
-// (ny x (nx/2 + 1) complex: the last float64 slot, with 2 ny extra doubles).
+// (column-major [nx/2][ny] complex, kx = nx/2 in the imaginary part of column 0: the
+// last float64 slot).
 struct ArgsSolve {
   int stage;
   int r, spec, out;

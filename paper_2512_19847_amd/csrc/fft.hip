@@ -7,17 +7,17 @@
 // term of R has zero mean, so this is the exact-arithmetic value; it also covers
 // sigma = 0).  All of it runs in float64.
 //
-// Five kernels, each one read and one write of a float64 plane-sized array:
+// Three kernels, each one read and one write of a float64 plane-sized array:
 //  rows forward   two real rows packed as one complex length-nx FFT, split into the two
-//                 half spectra kx = 0..nx/2.  Output: spectrum [ny][nx/2 + 1] complex.
-//  columns A      four-step FFT along y with ny = n1 n2, y = r + n2 m: a length-n1 FFT
-//                 over m for every residue r and column (strided rows, C columns of a
-//                 tile side by side so each row segment is one contiguous load).
-//  columns B      for each k1, the n2 contiguous rows n2 k1 + r: twiddle exp(-2 pi i r
-//                 k1 / ny), length-n2 FFT over r (frequency ky = k1 + n1 k2), multiply by
-//                 1 / ((lambda_x + lambda_y - sigma) nx ny) with the (0,0) rule, inverse
-//                 length-n2 FFT and the conjugate twiddle.
-//  columns A inv  inverse length-n1 FFTs, back to natural row order.
+//                 half spectra kx = 0..nx/2, stored column-major: spectrum [nx/2][ny]
+//                 complex, so every column is ny contiguous values.  kx = 0 and
+//                 kx = nx/2 are real for a real row and share column 0 as the real and
+//                 imaginary part (nx/2 columns, not nx/2 + 1).
+//  columns        whole columns, C of them per workgroup (C ny <= 8192 complex values in
+//                 LDS): FFT along y, multiply by 1 / ((lambda_x + lambda_y - sigma) nx ny)
+//                 with the (0,0) rule (column 0: separated into its two real columns'
+//                 spectra by their Hermitian symmetry, each with its own divisor), inverse
+//                 FFT, in place.
 //  rows inverse   Hermitian extension of the half spectra, inverse FFT, two real rows.
 //
 // Every FFT is a mixed-radix (8, 4, 3, 2) Stockham autosort transform in LDS: each pass
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
   constexpr int E = CAP / NT;
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
-  const int n = I.nx, h = n / 2, K = h + 1;
+  const int n = I.nx, h = n / 2;
   const int p0 = wk.a;
   const int np = min(I.row_pairs_per_block, I.ny / 2 - p0);
   const int cnt = np * n;
@@ -282,201 +282,135 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
   }
   __syncthreads();
   fft_lds<-1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
-  const Gp<dv2> S = cslot(I, a.spec) + 2LL * p0 * K;
-  const Div dk(K);
-  for (int idx = threadIdx.x; idx < np * K; idx += NT) {
-    const int p = dk.q(idx), k = idx - p * K;
-    const double2 Z = buf[lp(p * n + (k == h ? h : k))];
-    // Z[n-k]; its conjugate pairs with Z[k]
-    const double2 W = buf[lp(p * n + (k == 0 ? 0 : n - k))];
-    // A = (Z + conj W) / 2, B = (Z - conj W) / 2i: the spectra of the two real rows
-    const double2 A = make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
-    const double2 B = make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x));
-    stc(S + 2 * p * K + k, A);
-    stc(S + (2 * p + 1) * K + k, B);
+  // column-major half spectra S[k][y] for the 2 np rows y = 2 p0 .. of the block:
+  // consecutive threads write consecutive rows of one column
+  const int ny = I.ny, m = 2 * np;
+  const Gp<dv2> S = cslot(I, a.spec) + 2LL * p0;
+  const Div dm(m);
+  for (int idx = threadIdx.x; idx < m * h; idx += NT) {
+    const int k = dm.q(idx), yl = idx - k * m, p = yl >> 1;
+    const double2 Z = buf[lp(p * n + k)];
+    // Z[n-k] (Z[n/2] for k = 0); its conjugate pairs with Z[k]
+    const double2 W = buf[lp(p * n + (k == 0 ? h : n - k))];
+    double2 o;
+    if (k == 0)  // (A[0], A[n/2]) and (B[0], B[n/2]): Z[0] = A[0] + i B[0], likewise Z[n/2]
+      o = (yl & 1) ? make_double2(Z.y, W.y) : make_double2(Z.x, W.x);
+    else  // A = (Z + conj W) / 2, B = (Z - conj W) / 2i: the spectra of rows 2p, 2p + 1
+      o = (yl & 1) ? make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x))
+                   : make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
+    stc(S + (long long)k * ny + yl, o);
   }
 }
 
 // ------------------------------------------------------------------ columns
 
-// Tile of C columns of the spectrum: element j of column c at buf[j * es + c].
-constexpr int kColCap = 2048;
-constexpr int kColThreads = 256;
-constexpr int kColPer = kColCap / kColThreads;
-
-// A: length-n1 FFT over rows y = r + n2 m, m = 0..n1-1, for the C columns k0.. of the
-// tile; work item (inst, k0, r).
-template <int DIR>
-__global__ __launch_bounds__(kColThreads) void k_cols_a(const Inst *__restrict__ insts,
-                                                        const Work *__restrict__ work,
-                                                        int nwork, ArgsSolve a) {
-  __shared__ double2 buf[kColCap + kColCap / 8];
-  __shared__ double2 tws[kTwCap];
-  const Work wk = work[xcd_item_fft(nwork)];
-  const Inst &I = insts[wk.inst];
-  const int K = I.nx / 2 + 1, n1 = I.f1.n, n2 = I.f2.n;
-  const int k0 = wk.a, r = wk.b;
-  const int C = min(I.cols_per_block, K - k0);
-  const int cnt = n1 * C;
-  const Gp<dv2> S = cslot(I, a.spec) + (long long)r * K + k0;
-  const long long stride = (long long)n2 * K;
-  const Div dc(C);
-  TwStage<kColThreads> tw;
-  tw.load(I.f1);
-  double2 v[kColPer];
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    if (idx < cnt) {
-      const int m = dc.q(idx), c = idx - m * C;
-      v[e] = ldc(S + m * stride + c);
-    }
-  }
-  tw.store(tws, I.f1);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    if (idx < cnt) buf[lp(idx)] = make_double2(v[e].x, v[e].y);
-  }
-  __syncthreads();
-  fft_lds<DIR, true, kColCap, kColThreads>(buf, I.f1, C, C, 1, tws);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    if (idx < cnt) {
-      const int m = dc.q(idx), c = idx - m * C;
-      stc(S + m * stride + c, buf[lp(idx)]);
-    }
-  }
+// Divisor of a mode from its symbol values: 1 / ((lambda_x + lambda_y - sigma) nx ny)
+// (never the (0,0) mode, which takes theta_mean instead).
+__device__ __forceinline__ double mode_div(const Inst &I, double sig, double lx, double ly) {
+  return I.inv_nxny / (lx + ly - sig);
 }
 
-// Divisor of mode (kx, ky): 1 / ((lambda_x + lambda_y - sigma) nx ny); the (0,0) mode is
-// replaced by theta_mean instead (flagged by a zero divisor slot).
-__device__ __forceinline__ double mode_scale(const Inst &I, double sig, int kx, int ky) {
-  return (kx == 0 && ky == 0) ? 0.0 : I.inv_nxny / (gp(I.lam_x)[kx] + gp(I.lam_y)[ky] - sig);
-}
-
-// B: for G groups k1 = g0.. of n2 contiguous rows n2 k1 + r: twiddle, length-n2 FFT,
-// symbol divide, inverse length-n2 FFT, conjugate twiddle.  LDS layout [r][g][c].
-__global__ __launch_bounds__(kColThreads) void k_cols_b(const Inst *__restrict__ insts,
-                                                        const Work *__restrict__ work, int nwork,
-                                                        ArgsSolve a) {
-  __shared__ double2 buf[kColCap + kColCap / 8];
+// The C = cols_per_block columns kx = k0.. of the column-major spectrum, one contiguous
+// run of C ny complex values: forward FFT along y, symbol divide with the (0,0) rule,
+// inverse FFT, stored in place.  Work item (inst, k0).
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
+                                             const Work *__restrict__ work, int nwork,
+                                             ArgsSolve a) {
+  __shared__ double2 buf[CAP + CAP / 8];
   __shared__ double2 tws[kTwCap];
+  constexpr int E = CAP / NT;
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
-  const int K = I.nx / 2 + 1, n = I.ny, n1 = I.f1.n, n2 = I.f2.n;
-  const int k0 = wk.a, g0 = wk.b;
-  const int C = min(I.cols_per_block, K - k0);
-  const int G = min(I.groups_per_block, n1 - g0);
-  const int GC = G * C;
-  const int cnt = n2 * GC;
-  const Gp<dv2> S = cslot(I, a.spec) + k0;
-  const Gp<const dv2> twn = reinterpret_cast<Gp<const dv2>>(gp(I.fy.tw));  // exp(-2 pi i m / ny)
-  const double sig = I.sigma[a.stage];
-  const Div dgc(GC), dc(C), dn(n);
-  TwStage<kColThreads> tw;
-  tw.load(I.f2);
-  double2 v[kColPer], w[kColPer];
-  double d[kColPer];
-  int off[kColPer];
-  // element idx = (r, g, c): row n2 (g0 + g) + r of the spectrum before the n2-point FFT,
-  // mode ky = g0 + g + n1 r after it
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    off[e] = -1;
-    if (idx < cnt) {
-      const int r = dgc.q(idx), rem = idx - r * GC;
-      const int g = dc.q(rem), c = rem - g * C;
-      const int k1 = g0 + g;
-      off[e] = (n2 * k1 + r) * K + c;
-      v[e] = ldc(S + off[e]);
-      const int m = r * k1;
-      w[e] = ldc(twn + (m - dn.q(m) * n));
-      d[e] = mode_scale(I, sig, k0 + c, k1 + n1 * r);
-    }
-  }
-  tw.store(tws, I.f2);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) buf[lp(threadIdx.x + e * kColThreads)] = cmul(v[e], w[e]);
-  __syncthreads();
-  fft_lds<-1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1, tws);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    if (off[e] >= 0) {
-      const double2 z = buf[lp(idx)];
-      buf[lp(idx)] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
-                             : make_double2(z.x * d[e], z.y * d[e]);
-    }
-  }
-  __syncthreads();
-  fft_lds<1, true, kColCap, kColThreads>(buf, I.f2, GC, GC, 1, tws);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    if (off[e] >= 0) {
-      const double2 c = make_double2(w[e].x, -w[e].y);
-      stc(S + off[e], cmul(buf[lp(threadIdx.x + e * kColThreads)], c));
-    }
-  }
-}
-
-// Single pass over whole columns (ny <= kColCap / C): forward FFT along y, symbol divide
-// with the (0,0) rule, inverse FFT, for the C columns k0.. of the tile; work item
-// (inst, k0).  One launch instead of the three of the four-step form, for grids whose
-// columns fit a tile.
-__global__ __launch_bounds__(kColThreads) void k_cols_full(const Inst *__restrict__ insts,
-                                                           const Work *__restrict__ work,
-                                                           int nwork, ArgsSolve a) {
-  __shared__ double2 buf[kColCap + kColCap / 8];
-  __shared__ double2 tws[kTwCap];
-  const Work wk = work[xcd_item_fft(nwork)];
-  const Inst &I = insts[wk.inst];
-  const int K = I.nx / 2 + 1;
+  const int ny = I.ny, K = I.nx / 2, h = I.nx / 2;
   const int k0 = wk.a;
-  const int C = min(I.cols_full_per_block, K - k0);
-  const int cnt = I.ny * C;
-  const Gp<dv2> S = cslot(I, a.spec) + k0;
+  const int C = min(I.cols_per_block, K - k0);
+  const int cnt = C * ny;
+  const Gp<dv2> S = cslot(I, a.spec) + (long long)k0 * ny;
   const double sig = I.sigma[a.stage];
-  const Div dc(C);
-  TwStage<kColThreads> tw;
+  const Div dy(ny);
+  TwStage<NT> tw;
   tw.load(I.fy);
-  double2 v[kColPer];
-  double d[kColPer];
-  int off[kColPer];
+  // PRE: the symbol values of the thread's modes travel with the data loads.  The larger
+  // forms have no registers to spare for them (they would lower the waves per SIMD below
+  // what the LDS allows) and load them after the transform; they hit the L2, every
+  // workgroup reads the same ny values.
+  constexpr bool PRE = NT == kRowSmallThreads;
+  double2 v[E];
+  double ly[PRE ? E : 1], lx[PRE ? E : 1];
+  double lxh = 0.0;
 #pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    off[e] = -1;
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
-      const int y = dc.q(idx), c = idx - y * C;
-      off[e] = y * K + c;
-      v[e] = ldc(S + off[e]);
-      d[e] = mode_scale(I, sig, k0 + c, y);
+      v[e] = ldc(S + idx);
+      if constexpr (PRE) {
+        const int c = dy.q(idx), y = idx - c * ny;
+        ly[e] = gp(I.lam_y)[y];
+        lx[e] = gp(I.lam_x)[k0 + c];
+      }
     }
   }
+  if (PRE && k0 == 0) lxh = gp(I.lam_x)[h];
   tw.store(tws, I.fy);
 #pragma unroll
-  for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) buf[lp(threadIdx.x + e * kColThreads)] = make_double2(v[e].x, v[e].y);
-  __syncthreads();
-  fft_lds<-1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
-#pragma unroll
-  for (int e = 0; e < kColPer; ++e) {
-    const int idx = threadIdx.x + e * kColThreads;
-    if (off[e] >= 0) {
-      const double2 z = buf[lp(idx)];
-      buf[lp(idx)] = d[e] == 0.0 ? make_double2(I.theta_mean, 0.0)
-                             : make_double2(z.x * d[e], z.y * d[e]);
-    }
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) buf[lp(idx)] = v[e];
   }
   __syncthreads();
-  fft_lds<1, true, kColCap, kColThreads>(buf, I.fy, C, C, 1, tws);
+  fft_lds<-1, false, CAP, NT>(buf, I.fy, C, 1, ny, tws);
+  double2 o[E];
 #pragma unroll
-  for (int e = 0; e < kColPer; ++e)
-    if (off[e] >= 0) stc(S + off[e], buf[lp(threadIdx.x + e * kColThreads)]);
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int c = dy.q(idx), y = idx - c * ny;
+      double lyy, lxx, lxn;
+      if constexpr (PRE) {
+        lyy = ly[e];
+        lxx = lx[e];
+        lxn = lxh;
+      } else {
+        lyy = gp(I.lam_y)[y];
+        lxx = gp(I.lam_x)[k0 + c];
+        lxn = k0 + c == 0 ? gp(I.lam_x)[h] : 0.0;
+      }
+      const double2 z = buf[lp(idx)];
+      if (k0 + c == 0) {
+        // Z = F0 + i Fh with F0, Fh the (Hermitian) y spectra of the real columns kx = 0
+        // and kx = nx/2: F0 = (Z[ky] + conj Z[-ky]) / 2, Fh = (Z[ky] - conj Z[-ky]) / 2i
+        const double2 zm = buf[lp(y == 0 ? 0 : ny - y)];
+        double2 f0 = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+        double2 fh = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+        const double dh = mode_div(I, sig, lxn, lyy);
+        if (y == 0) {
+          f0 = make_double2(I.theta_mean, 0.0);  // the (0,0) rule
+        } else {
+          const double d0 = mode_div(I, sig, lxx, lyy);
+          f0 = make_double2(f0.x * d0, f0.y * d0);
+        }
+        fh = make_double2(fh.x * dh, fh.y * dh);
+        o[e] = make_double2(f0.x - fh.y, f0.y + fh.x);  // F0 + i Fh
+      } else {
+        const double d = mode_div(I, sig, lxx, lyy);
+        o[e] = make_double2(z.x * d, z.y * d);
+      }
+    }
+  }
+  __syncthreads();  // column 0 reads mirrored elements of other threads
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) buf[lp(idx)] = o[e];
+  }
+  __syncthreads();
+  fft_lds<1, false, CAP, NT>(buf, I.fy, C, 1, ny, tws);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) stc(S + idx, buf[lp(idx)]);
+  }
 }
 
 // ------------------------------------------------------------------ rows inverse
@@ -487,55 +421,51 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
                                                      ArgsSolve a) {
   __shared__ double2 buf[CAP + CAP / 8];
   __shared__ double2 tws[kTwCap];
-  constexpr int E = CAP / (2 * NT);
+  constexpr int EI = CAP / (2 * NT), EO = CAP / NT;
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
-  const int n = I.nx, h = n / 2, K = h + 1;
+  const int n = I.nx, h = n / 2, ny = I.ny;
   const int p0 = wk.a;
   const int np = min(I.row_pairs_per_block, I.ny / 2 - p0);
   const int cnt = np * h;
-  const Gp<const dv2> S = cslot(I, a.spec) + 2LL * p0 * K;
-  const Div dh(h);
+  // column-major half spectra: rows 2p and 2p + 1 of column k are adjacent
+  const Gp<const dv2> S = cslot(I, a.spec) + 2LL * p0;
+  const Div dp(np);
   TwStage<NT> tw;
   tw.load(I.fx);
-  double2 A[E], B[E], AN, BN;
+  double2 A[EI], B[EI];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
+  for (int e = 0; e < EI; ++e) {
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
-      const int p = dh.q(idx), k = idx - p * h;
-      A[e] = ldc(S + 2 * p * K + k);
-      B[e] = ldc(S + (2 * p + 1) * K + k);
+      const int k = dp.q(idx), p = idx - k * np;
+      const Gp<const dv2> s = S + (long long)k * ny + 2 * p;
+      A[e] = ldc(s);
+      B[e] = ldc(s + 1);
     }
-  }
-  // kx = nx/2 of pair p = threadIdx.x (np <= NT)
-  const int pn = threadIdx.x;
-  if (pn < np) {
-    AN = ldc(S + 2 * pn * K + h);
-    BN = ldc(S + (2 * pn + 1) * K + h);
   }
   tw.store(tws, I.fx);
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
+  for (int e = 0; e < EI; ++e) {
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
-      const int p = dh.q(idx), k = idx - p * h;
+      const int k = dp.q(idx), p = idx - k * np;
       if (k == 0) {
-        // kx = 0 and kx = nx/2 are real for a real row
+        // kx = 0 and kx = nx/2 (real for a real row) share column 0
         buf[lp(p * n)] = make_double2(A[e].x, B[e].x);
+        buf[lp(p * n + h)] = make_double2(A[e].y, B[e].y);
       } else {
         buf[lp(p * n + k)] = make_double2(A[e].x - B[e].y, A[e].y + B[e].x);      // A + i B
         buf[lp(p * n + n - k)] = make_double2(A[e].x + B[e].y, B[e].x - A[e].y);  // conj A + i conj B
       }
     }
   }
-  if (pn < np) buf[lp(pn * n + h)] = make_double2(AN.x, BN.x);
   __syncthreads();
   fft_lds<1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
   const Div dn(n);
 #pragma unroll
-  for (int e = 0; e < 2 * E; ++e) {
+  for (int e = 0; e < EO; ++e) {
     const int idx = threadIdx.x + e * NT;
     if (idx < np * n) {
       const int o = idx + dn.q(idx) * n;
@@ -546,41 +476,29 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   }
 }
 
-// part 0: rows forward, 1: columns A, 2: columns B, 3: columns A inverse, 4: rows
-// inverse, 5: single-pass columns (cola then holds its strips).  big selects the row
-// kernels for nx > kRowSmallCap.
-hipError_t launch_solve_part(int part, bool big, const Inst *insts, const Work *rows, int nrows,
-                             const Work *cola, int ncola, const Work *colb, int ncolb,
-                             const ArgsSolve &a, hipStream_t st, const Ev &ev) {
+// Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values.
+#define APDVM_FFT_FORM(V, KERNEL, WORK, NWORK)                                             \
+  do {                                                                                     \
+    if ((V) == 2)                                                                          \
+      APDVM_LAUNCH(ev, (KERNEL<kFftCap, kFftThreads>), dim3(NWORK), dim3(kFftThreads), st, \
+                   insts, WORK, NWORK, a);                                                 \
+    else if ((V) == 1)                                                                     \
+      APDVM_LAUNCH(ev, (KERNEL<kColMidCap, kColMidThreads>), dim3(NWORK),                  \
+                   dim3(kColMidThreads), st, insts, WORK, NWORK, a);                       \
+    else                                                                                   \
+      APDVM_LAUNCH(ev, (KERNEL<kRowSmallCap, kRowSmallThreads>), dim3(NWORK),              \
+                   dim3(kRowSmallThreads), st, insts, WORK, NWORK, a);                     \
+  } while (0)
+
+// part 0: rows forward, 1: columns, 2: rows inverse; rowv and colv the kernel forms
+// (the smallest that holds a whole row, a whole column).
+hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, const Work *rows,
+                             int nrows, const Work *cols, int ncols, const ArgsSolve &a,
+                             hipStream_t st, const Ev &ev) {
   switch (part) {
-    case 5:
-      APDVM_LAUNCH(ev, k_cols_full, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
-      break;
-    case 0:
-      if (big)
-        APDVM_LAUNCH(ev, (k_rows_forward<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
-                     st, insts, rows, nrows, a);
-      else
-        APDVM_LAUNCH(ev, (k_rows_forward<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
-                     dim3(kRowSmallThreads), st, insts, rows, nrows, a);
-      break;
-    case 1:
-      APDVM_LAUNCH(ev, k_cols_a<-1>, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
-      break;
-    case 2:
-      APDVM_LAUNCH(ev, k_cols_b, dim3(ncolb), dim3(kColThreads), st, insts, colb, ncolb, a);
-      break;
-    case 3:
-      APDVM_LAUNCH(ev, k_cols_a<1>, dim3(ncola), dim3(kColThreads), st, insts, cola, ncola, a);
-      break;
-    default:
-      if (big)
-        APDVM_LAUNCH(ev, (k_rows_inverse<kFftCap, kFftThreads>), dim3(nrows), dim3(kFftThreads),
-                     st, insts, rows, nrows, a);
-      else
-        APDVM_LAUNCH(ev, (k_rows_inverse<kRowSmallCap, kRowSmallThreads>), dim3(nrows),
-                     dim3(kRowSmallThreads), st, insts, rows, nrows, a);
-      break;
+    case 0: APDVM_FFT_FORM(rowv, k_rows_forward, rows, nrows); break;
+    case 1: APDVM_FFT_FORM(colv, k_cols, cols, ncols); break;
+    default: APDVM_FFT_FORM(rowv, k_rows_inverse, rows, nrows); break;
   }
   return hipGetLastError();
 }

@@ -42,8 +42,8 @@ inline int shape_of(int rows, int threads) {
     if (kShapeRows[si] == rows && kShapeThreads[si] == threads) return si;
   return -1;
 }
-hipError_t launch_solve_part(int part, bool big, const Inst *, const Work *, int, const Work *,
-                             int, const Work *, int, const ArgsSolve &, hipStream_t, const Ev &);
+hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *, const Work *, int,
+                             const Work *, int, const ArgsSolve &, hipStream_t, const Ev &);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
                               int, int, double *, int, hipStream_t);
 
@@ -237,13 +237,6 @@ int fft_radices(int n, int *rad) {
   return np;
 }
 
-void twiddles(int n, double2 *out) {
-  for (int m = 0; m < n; ++m) {
-    const long double a = -2.0L * 3.141592653589793238462643383279502884L * m / n;
-    out[m] = make_double2((double)cosl(a), (double)sinl(a));
-  }
-}
-
 // Two-level table (see FftPlan): lo[b] = w^b for b < B, hi[a] = w^(a B), w = exp(-2 pi i / n).
 // Returns the number of entries; *lb receives log2 B.
 int twiddles2(int n, double2 *out, int *lb) {
@@ -284,66 +277,42 @@ struct Sizes {
 int n_tiles(const apdvm_config &c, int ty) {
   return ((c.nx + kTileX - 1) / kTileX) * ((c.ny + ty - 1) / ty);
 }
-// Row FFT kernels: the large form holds 8192 complex values, the small one 1024.
-bool big_rows(int n, const apdvm_config *cfgs) {
-  for (int k = 0; k < n; ++k)
-    if (cfgs[k].nx > kRowSmallCap) return true;
-  return false;
+// FFT kernel forms by LDS capacity (0: kRowSmallCap, 1: kColMidCap, 2: kFftCap complex
+// values): the smallest that holds a whole row (whole column) of every instance.
+int fft_form(int longest) {
+  return longest <= kRowSmallCap ? 0 : longest <= kColMidCap ? 1 : 2;
 }
-int rpb(const apdvm_config &c, bool big) {
-  int r = (big ? kFftCap : kRowSmallCap) / c.nx;
+int form_cap(int v) { return v == 0 ? kRowSmallCap : v == 1 ? kColMidCap : kFftCap; }
+int row_form(int n, const apdvm_config *cfgs) {
+  int mx = 0;
+  for (int k = 0; k < n; ++k) mx = cfgs[k].nx > mx ? cfgs[k].nx : mx;
+  return fft_form(mx);
+}
+int col_form(int n, const apdvm_config *cfgs) {
+  int my = 0;
+  for (int k = 0; k < n; ++k) my = cfgs[k].ny > my ? cfgs[k].ny : my;
+  return fft_form(my);
+}
+// row pairs per row workgroup
+int rpb(const apdvm_config &c, int v) {
+  int r = form_cap(v) / c.nx;
   if (r > c.ny / 2) r = c.ny / 2;
   return r < 1 ? 1 : r;
 }
-// Column FFT of length ny = n1 n2 with n2 the largest divisor not above sqrt(ny).
-int col_n2(int ny) {
-  int best = 1;
-  for (int d = 2; d * d <= ny; ++d)
-    if (ny % d == 0) best = d;
-  return best;
+// columns per column workgroup (the spectrum has nx/2 columns: kx = nx/2 shares column 0)
+int cpb(const apdvm_config &c, int v) {
+  int w = form_cap(v) / c.ny;
+  if (w > c.nx / 2) w = c.nx / 2;
+  return w < 1 ? 1 : w;
 }
-int cpb(const apdvm_config &c) {
-  // tiles of column kernels A (n1 x C) and B (n2 x G x C) must fit 2048 complex values
-  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
-  int w = kColWidth;
-  if (w > c.nx / 2 + 1) w = c.nx / 2 + 1;
-  while (w > 1 && (n1 * w > 2048 || n2 * w > 2048)) --w;
-  return w;
-}
-int gpb(const apdvm_config &c) {
-  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
-  int g = kColBTarget / (n2 * cpb(c));
-  if (g > n1) g = n1;
-  return g < 1 ? 1 : g;
-}
-int n_rowblocks(const apdvm_config &c, bool big) { return (c.ny / 2 + rpb(c, big) - 1) / rpb(c, big); }
-int n_strips(const apdvm_config &c) { return (c.nx / 2 + 1 + cpb(c) - 1) / cpb(c); }
-int n_colablocks(const apdvm_config &c) { return n_strips(c) * col_n2(c.ny); }
-// single-pass column kernel: whole columns of length ny in a tile of at most 2048
-// complex values
-int cfpb(const apdvm_config &c) {
-  if (c.ny > 2048) return 0;
-  int w = kColWidth;
-  if (w > c.nx / 2 + 1) w = c.nx / 2 + 1;
-  while (w > 1 && c.ny * w > 2048) --w;
-  return w;
-}
-int n_colfblocks(const apdvm_config &c) {
-  const int w = cfpb(c);
-  return w ? (c.nx / 2 + 1 + w - 1) / w : 0;
-}
-int n_colbblocks(const apdvm_config &c) {
-  const int n1 = c.ny / col_n2(c.ny);
-  return n_strips(c) * ((n1 + gpb(c) - 1) / gpb(c));
-}
+int n_colblocks(const apdvm_config &c, int v) { return (c.nx / 2 + cpb(c, v) - 1) / cpb(c, v); }
+int n_rowblocks(const apdvm_config &c, int v) { return (c.ny / 2 + rpb(c, v) - 1) / rpb(c, v); }
 
 size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
   const size_t plane = (size_t)c.nx * c.ny;
-  const int n2 = col_n2(c.ny), n1 = c.ny / n2;
   size_t b = align_up(L.ntrans * plane * tsize);
-  b += align_up((L.ndbl * plane + 2 * (size_t)c.ny) * sizeof(double));  // spectrum tail
-  b += align_up((size_t)(c.nx + c.ny + n1 + n2) * sizeof(double2));     // twiddles
-  b += align_up((size_t)4 * kTwCap * sizeof(double2));                 // two-level twiddles
+  b += align_up(L.ndbl * plane * sizeof(double));
+  b += align_up((size_t)2 * kTwCap * sizeof(double2));                 // two-level twiddles
   b += align_up((size_t)(c.nx / 2 + 1 + c.ny) * sizeof(double));        // symbols
   return b;
 }
@@ -353,20 +322,17 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
   const bool split = cfgs[0].precision == APDVM_FP32_SPLIT;
   const size_t tsize = split ? sizeof(float) : sizeof(double);
   size_t b = align_up(n * sizeof(Inst));
-  const bool big = big_rows(n, cfgs);
-  size_t ntile8 = 0, ntile16 = 0, nrow = 0, ncola = 0, ncolb = 0, ncolf = 0;
+  const int rv = row_form(n, cfgs), cv = col_form(n, cfgs);
+  size_t ntile8 = 0, ntile16 = 0, nrow = 0, ncol = 0;
   for (int k = 0; k < n; ++k) {
     b += inst_bytes(cfgs[k], L, tsize);
     ntile8 += n_tiles(cfgs[k], kTileRows[0]);
     ntile16 += n_tiles(cfgs[k], kTileRows[1]);
-    nrow += n_rowblocks(cfgs[k], big);
-    ncola += n_colablocks(cfgs[k]);
-    ncolb += n_colbblocks(cfgs[k]);
-    ncolf += n_colfblocks(cfgs[k]);
+    nrow += n_rowblocks(cfgs[k], rv);
+    ncol += n_colblocks(cfgs[k], cv);
   }
   b += align_up(ntile8 * sizeof(Work)) + align_up(ntile16 * sizeof(Work)) + align_up(nrow * sizeof(Work)) +
-       align_up(ncola * sizeof(Work)) + align_up(ncolb * sizeof(Work)) +
-       align_up((ncolf + 1) * sizeof(Work));
+       align_up(ncol * sizeof(Work));
   b += align_up(8 * sizeof(double) * 1024);  // diagnostics partials
   return b;
 }
@@ -376,8 +342,8 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
 // One kernel launch of a step: its class, arguments and algorithmic bytes (every
 // plane it must read and write, counted once).
 enum LaunchClass {
-  kHelmRhs = 0, kRowsFwd = 1, kColsA = 2, kColsB = 3, kColsAInv = 4, kRowsInv = 5,
-  kUpdateUQ = 6, kStageTerms = 7, kColsFull = 8, kGradQ = 9, kNumClasses = 10
+  kHelmRhs = 0, kRowsFwd = 1, kCols = 2, kRowsInv = 3, kUpdateUQ = 4, kStageTerms = 5,
+  kGradQ = 6, kNumClasses = 7
 };
 // Stencil classes with a tuned launch shape, in the order of the tuning array.
 constexpr int kNumTuned = 4;
@@ -421,11 +387,9 @@ struct apdvm_ctx {
   Inst *d_inst = nullptr;
   Work *d_tiles[2] = {nullptr, nullptr};  // tile tables for kTileRows[0] and kTileRows[1]
   int ntiles[2] = {0, 0};
-  Work *d_rows = nullptr, *d_cola = nullptr, *d_colb = nullptr, *d_colf = nullptr;
-  int nrows = 0, ncola = 0, ncolb = 0, ncolf = 0;
-  int col_mode = 0;        // 0: four-step column FFT (3 launches), 1: single pass
-  bool col_full_ok = false;  // every instance has columns short enough for one pass
-  bool big_rows = false;
+  Work *d_rows = nullptr, *d_cols = nullptr;
+  int nrows = 0, ncols = 0;
+  int row_v = 0, col_v = 0;  // FFT kernel forms of the rows and columns (fft_form)
   int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
@@ -437,7 +401,7 @@ struct apdvm_ctx {
   std::vector<double> umax;
   int64_t step = 0;
   double cells = 0.0;                 // sum of nx * ny over instances
-  double spec_bytes = 0.0;            // sum of ny (nx/2 + 1) * 16 over instances
+  double spec_bytes = 0.0;            // sum of ny (nx/2) * 16 over instances
   std::vector<apdvm::Launch> plan[2]; // launch list of one step from each state set
   bool use_graph = false;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -604,15 +568,12 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ar.out_r = L.R; ar.out_ddb = L.ddb;
     l.bytes = (2 + 1 + ar.nD + ar.nL + 1) * pt + 2 * pd;
     plan.push_back(l);
-    // step 2 solve: five kernels, each one read and one write of a float64 plane
-    // (the spectrum holds nx/2 + 1 complex columns)
+    // step 2 solve: three kernels, each one read and one write of a float64 plane
+    // (the spectrum holds nx/2 complex columns of ny values)
     ArgsSolve as{};
     as.stage = i; as.r = L.R; as.spec = L.spec; as.out = th;
-    const int four[5] = {kRowsFwd, kColsA, kColsB, kColsAInv, kRowsInv};
-    const int full[3] = {kRowsFwd, kColsFull, kRowsInv};
-    const int *parts = c->col_mode ? full : four;
-    const int nparts = c->col_mode ? 3 : 5;
-    for (int m = 0; m < nparts; ++m) {
+    const int parts[3] = {kRowsFwd, kCols, kRowsInv};
+    for (int m = 0; m < 3; ++m) {
       const int k = parts[m];
       l = Launch{};
       l.cls = k;
@@ -698,16 +659,11 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
   switch (l.cls) {
     case kHelmRhs:
       return launch_helmholtz_rhs<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.r, st, ev);
-    case kColsFull:
-      return launch_solve_part(5, c->big_rows, c->d_inst, c->d_rows, c->nrows, c->d_colf,
-                               c->ncolf, c->d_colb, c->ncolb, l.sv, st, ev);
     case kRowsFwd:
-    case kColsA:
-    case kColsB:
-    case kColsAInv:
+    case kCols:
     case kRowsInv:
-      return launch_solve_part(l.cls - kRowsFwd, c->big_rows, c->d_inst, c->d_rows, c->nrows,
-                               c->d_cola, c->ncola, c->d_colb, c->ncolb, l.sv, st, ev);
+      return launch_solve_part(l.cls - kRowsFwd, c->row_v, c->col_v, c->d_inst, c->d_rows,
+                               c->nrows, c->d_cols, c->ncols, l.sv, st, ev);
     case kUpdateUQ:
       return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st, ev);
     case kGradQ:
@@ -1004,7 +960,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
 
   // carve the workspace
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
-  c->big_rows = big_rows(n, cfgs);
+  c->row_v = row_form(n, cfgs);
+  c->col_v = col_form(n, cfgs);
   for (int k = 0; k < kNumClasses; ++k) c->shape[k] = 1;
   c->wo = weno_order_of(cfgs[0]);
   c->co = central_order_of(cfgs[0]);
@@ -1013,8 +970,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->d_inst = reinterpret_cast<Inst *>(p);
   p += align_up(n * sizeof(Inst));
   c->inst.resize(n);
-  std::vector<Work> rows, cola, colb, colf;
-  c->col_full_ok = true;
+  std::vector<Work> rows, cols;
   std::vector<char> host_tables;
   struct Upload { char *dst; std::vector<char> data; };
   std::vector<Upload> uploads;
@@ -1035,37 +991,18 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.tbase = p;
     p += align_up(c->L.ntrans * plane * tsize);
     I.dbase = reinterpret_cast<double *>(p);
-    p += align_up((c->L.ndbl * plane + 2 * (size_t)cf.ny) * sizeof(double));
-    // twiddles for lengths nx, ny and the column factors n1, n2
-    const int n2 = col_n2(cf.ny), n1 = cf.ny / n2;
-    const int ntw = cf.nx + cf.ny + n1 + n2;
-    double2 *tw = reinterpret_cast<double2 *>(p);
-    p += align_up((size_t)ntw * sizeof(double2));
-    Upload u1{reinterpret_cast<char *>(tw), std::vector<char>(ntw * sizeof(double2))};
-    double2 *htw = reinterpret_cast<double2 *>(u1.data.data());
-    twiddles(cf.nx, htw);
-    twiddles(cf.ny, htw + cf.nx);
-    twiddles(n1, htw + cf.nx + cf.ny);
-    twiddles(n2, htw + cf.nx + cf.ny + n1);
-    uploads.push_back(std::move(u1));
+    p += align_up(c->L.ndbl * plane * sizeof(double));
+    // two-level twiddle tables for lengths nx and ny
     I.fx.n = cf.nx;
     I.fx.npass = fft_radices(cf.nx, I.fx.radix);
-    I.fx.tw = tw;
     I.fy.n = cf.ny;
     I.fy.npass = fft_radices(cf.ny, I.fy.radix);
-    I.fy.tw = tw + cf.nx;
-    I.f1.n = n1;
-    I.f1.npass = fft_radices(n1, I.f1.radix);
-    I.f1.tw = tw + cf.nx + cf.ny;
-    I.f2.n = n2;
-    I.f2.npass = fft_radices(n2, I.f2.radix);
-    I.f2.tw = tw + cf.nx + cf.ny + n1;
     double2 *tw2 = reinterpret_cast<double2 *>(p);
-    p += align_up((size_t)4 * kTwCap * sizeof(double2));
-    Upload u3{reinterpret_cast<char *>(tw2), std::vector<char>(4 * kTwCap * sizeof(double2))};
+    p += align_up((size_t)2 * kTwCap * sizeof(double2));
+    Upload u3{reinterpret_cast<char *>(tw2), std::vector<char>(2 * kTwCap * sizeof(double2))};
     double2 *htw2 = reinterpret_cast<double2 *>(u3.data.data());
-    FftPlan *plans[4] = {&I.fx, &I.fy, &I.f1, &I.f2};
-    for (int q = 0; q < 4; ++q) {
+    FftPlan *plans[2] = {&I.fx, &I.fy};
+    for (int q = 0; q < 2; ++q) {
       plans[q]->ntw = twiddles2(plans[q]->n, htw2 + q * kTwCap, &plans[q]->lb);
       plans[q]->tw2 = tw2 + q * kTwCap;
     }
@@ -1083,11 +1020,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     uploads.push_back(std::move(u2));
     I.lam_x = lam;
     I.lam_y = lam + cf.nx / 2 + 1;
-    I.row_pairs_per_block = rpb(cf, c->big_rows);
-    I.cols_per_block = cpb(cf);
-    I.groups_per_block = gpb(cf);
-    I.cols_full_per_block = cfpb(cf);
-    if (!I.cols_full_per_block) c->col_full_ok = false;
+    I.row_pairs_per_block = rpb(cf, c->row_v);
+    I.cols_per_block = cpb(cf, c->col_v);
     // work tables
     c->tile_first.push_back((int)c->tiles.size());
     for (int y0 = 0; y0 < cf.ny; y0 += kTileRows[1])
@@ -1096,14 +1030,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     for (int y0 = 0; y0 < cf.ny; y0 += kTileRows[0])
       for (int x0 = 0; x0 < cf.nx; x0 += kTileX) tiles8.push_back(Work{k, x0, y0, 0});
     for (int r0 = 0; r0 < cf.ny / 2; r0 += I.row_pairs_per_block) rows.push_back(Work{k, r0, 0, 0});
-    for (int k0 = 0; k0 < cf.nx / 2 + 1; k0 += I.cols_per_block) {
-      for (int r = 0; r < n2; ++r) cola.push_back(Work{k, k0, r, 0});
-      for (int g0 = 0; g0 < n1; g0 += I.groups_per_block) colb.push_back(Work{k, k0, g0, 0});
-    }
-    if (I.cols_full_per_block)
-      for (int k0 = 0; k0 < cf.nx / 2 + 1; k0 += I.cols_full_per_block)
-        colf.push_back(Work{k, k0, 0, 0});
-    c->spec_bytes += (double)cf.ny * (cf.nx / 2 + 1) * 16.0;
+    for (int k0 = 0; k0 < cf.nx / 2; k0 += I.cols_per_block) cols.push_back(Work{k, k0, 0, 0});
+    c->spec_bytes += (double)cf.ny * (cf.nx / 2) * 16.0;
     c->cfg[k] = cf;
     c->cfg[k].a_ex = c->cfg[k].a_im = c->cfg[k].b_ex = c->cfg[k].b_im = nullptr;
     c->cfg[k].cx = c->cfg[k].cy = nullptr;
@@ -1115,21 +1043,15 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->ntiles[1] = (int)c->tiles.size();
   c->ntiles[0] = (int)tiles8.size();
   c->nrows = (int)rows.size();
-  c->ncola = (int)cola.size();
-  c->ncolb = (int)colb.size();
-  c->ncolf = (int)colf.size();
+  c->ncols = (int)cols.size();
   c->d_tiles[1] = reinterpret_cast<Work *>(p);
   p += align_up(c->tiles.size() * sizeof(Work));
   c->d_tiles[0] = reinterpret_cast<Work *>(p);
   p += align_up(tiles8.size() * sizeof(Work));
   c->d_rows = reinterpret_cast<Work *>(p);
   p += align_up(rows.size() * sizeof(Work));
-  c->d_cola = reinterpret_cast<Work *>(p);
-  p += align_up(cola.size() * sizeof(Work));
-  c->d_colb = reinterpret_cast<Work *>(p);
-  p += align_up(colb.size() * sizeof(Work));
-  c->d_colf = reinterpret_cast<Work *>(p);
-  p += align_up((colf.size() + 1) * sizeof(Work));
+  c->d_cols = reinterpret_cast<Work *>(p);
+  p += align_up(cols.size() * sizeof(Work));
   c->d_partials = reinterpret_cast<double *>(p);
   p += align_up(8 * sizeof(double) * 1024);
 
@@ -1139,13 +1061,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
             hipMemcpyAsync(c->d_rows, rows.data(), rows.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->d_cola, cola.data(), cola.size() * sizeof(Work),
+            hipMemcpyAsync(c->d_cols, cols.data(), cols.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->d_colb, colb.data(), colb.size() * sizeof(Work),
-                           hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-            (colf.empty() ||
-             hipMemcpyAsync(c->d_colf, colf.data(), colf.size() * sizeof(Work),
-                            hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
             hipMemcpyAsync(c->d_inst, c->inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice,
                            c->stream) == hipSuccess;
   for (auto &u : uploads)
@@ -1445,15 +1362,7 @@ apdvm_status apdvm_traffic(apdvm_ctx *c, int32_t cls, double *bytes_per_step,
   return APDVM_OK;
 }
 
-// Autotuner: for each stencil kernel class, time every tile height on the live data
-// with HIP events and keep the fastest; the state is restored afterwards.  With the
-// environment variable APDVM_TUNE_CACHE naming a file, choices are looked up there by
-// a key of the context's shape and appended after tuning.
-static void set_col_mode(apdvm_ctx *c, int mode) {
-  if (c->col_mode == mode) return;
-  c->col_mode = mode;
-  c->plan[0] = build_plan(c, 0);
-  c->plan[1] = build_plan(c, 1);
+static void drop_graphs(apdvm_ctx *c) {
   for (int p = 0; p < 2; ++p)
     if (c->graph_exec[p]) {
       (void)hipGraphExecDestroy(c->graph_exec[p]);
@@ -1461,9 +1370,14 @@ static void set_col_mode(apdvm_ctx *c, int mode) {
     }
 }
 
+// Autotuner: for each stencil kernel class, time every launch shape on the live data
+// with HIP events and keep the fastest, then the stream structure over whole steps; the
+// state is restored afterwards.  With the environment variable APDVM_TUNE_CACHE naming a
+// file, choices are looked up there by a key of the context's shape and appended after
+// tuning.
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 shapes4 overlap gradq prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes4 overlap gradq colmajor prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
@@ -1486,12 +1400,11 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() &&
           line[key.size()] == '|') {
         std::istringstream rest(line.substr(key.size() + 1));
-        int t[kNumTuned], mode = 0, ov = 1;
+        int t[kNumTuned], ov = 1;
         bool good = true;
         for (int m = 0; m < kNumTuned; ++m) good = good && (rest >> t[m]) && t[m] >= 0 && t[m] < kNumShapes;
-        if (good && rest >> mode >> ov) {
+        if (good && rest >> ov) {
           for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = t[m];
-          set_col_mode(c, (mode && c->col_full_ok) ? 1 : 0);
           if (apdvm_set_overlap(c, ov ? 1 : 0) != APDVM_OK) return APDVM_ERR_HIP;
           cached = true;
         }
@@ -1551,32 +1464,10 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       }
       c->shape[cls] = best_si;
     }
-    if (ok && c->col_full_ok) {
-      double tmode[2] = {0.0, 0.0};
-      for (int mode = 0; ok && mode < 2; ++mode) {
-        set_col_mode(c, mode);
-        ok = apdvm_step(c, 1) == APDVM_OK;
-        const int four[3] = {kColsA, kColsB, kColsAInv};
-        const int nm = mode ? 1 : 3;
-        for (int m = 0; ok && m < nm; ++m) {
-          ok = apdvm_timing_enable(c, mode ? kColsFull : four[m]) == APDVM_OK;
-          ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
-          int64_t nl = 0;
-          double ms = 0.0;
-          ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
-          tmode[mode] += ms;
-        }
-      }
-      set_col_mode(c, tmode[1] < tmode[0] ? 1 : 0);
-    }
     // the solve beside steps 3 and 4 or after them: whole steps timed on the main stream
     ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
     c->use_graph = graph;  // the stream structures compete in the caller's launch mode
-    for (int p = 0; p < 2; ++p)  // graphs of earlier launch shapes
-      if (c->graph_exec[p]) {
-        (void)hipGraphExecDestroy(c->graph_exec[p]);
-        c->graph_exec[p] = nullptr;
-      }
+    drop_graphs(c);        // graphs of earlier launch shapes
     if (ok) {
       double tov[2] = {0.0, 0.0};
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1609,20 +1500,12 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       std::ofstream out(cache, std::ios::app);
       out << key << "|";
       for (int m = 0; m < kNumTuned; ++m) out << c->shape[classes[m]] << " ";
-      out << c->col_mode << " " << (c->overlap ? 1 : 0) << "\n";
+      out << (c->overlap ? 1 : 0) << "\n";
     }
   }
-  // the graphs captured the old launch shapes
-  for (int p = 0; p < 2; ++p)
-    if (c->graph_exec[p]) {
-      (void)hipGraphExecDestroy(c->graph_exec[p]);
-      c->graph_exec[p] = nullptr;
-    }
+  drop_graphs(c);  // the graphs captured the old launch shapes
   if (choice) {
     for (int k = 0; k < kNumClasses; ++k) choice[k] = 1;
-    // for the FFT column classes report which form runs: 1 used, 0 not used
-    choice[kColsA] = choice[kColsB] = choice[kColsAInv] = c->col_mode ? 0 : 1;
-    choice[kColsFull] = c->col_mode ? 1 : 0;
     for (int m = 0; m < kNumTuned; ++m) {
       choice[classes[m]] = kShapeRows[c->shape[classes[m]]];
       choice[kNumClasses + m] = kShapeThreads[c->shape[classes[m]]];
@@ -1639,15 +1522,8 @@ apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
     si[m] = shape_of(choice[classes[m]], choice[kNumClasses + m]);
     if (si[m] < 0) return APDVM_ERR_ARG;
   }
-  const int mode = choice[kColsFull] ? 1 : 0;
-  if (mode && !c->col_full_ok) return APDVM_ERR_ARG;
   for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = si[m];
-  set_col_mode(c, mode);
-  for (int p = 0; p < 2; ++p)
-    if (c->graph_exec[p]) {
-      (void)hipGraphExecDestroy(c->graph_exec[p]);
-      c->graph_exec[p] = nullptr;
-    }
+  drop_graphs(c);
   return APDVM_OK;
 }
 
