@@ -46,9 +46,10 @@ HBM_PEAK_GBS = 8000.0
 TIMING_STRIDE = 32
 
 
-def recorded_traffic(kernel_class, workload_name, precision):
+def recorded_traffic(kernel_class, workload_name, precision, shape):
     """HBM bytes per launch from the recorded counter runs, or None when they do not
-    apply to this kernel and workload or the kernel sources changed since."""
+    apply to this kernel, launch shape (tile rows, threads) and workload or the kernel
+    sources changed since."""
     import glob
     import hashlib
 
@@ -56,7 +57,8 @@ def recorded_traffic(kernel_class, workload_name, precision):
         with open(path) as f:
             rec = json.load(f)
         if (rec.get("kernel_class") != kernel_class or rec.get("workload") != workload_name
-                or rec.get("precision") != precision):
+                or rec.get("precision") != precision
+                or (rec.get("tile_rows"), rec.get("threads")) != shape):
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
@@ -181,6 +183,10 @@ def main():
                          "the speed ratio and the relative L2 differences of the final states")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="launch kernel by kernel instead of replaying each step as a HIP graph")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="after autotuning, run every launch on one stream (no solve beside the "
+                         "update), so that a kernel trace shows each kernel by itself, as the "
+                         "sampled timed steps do")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (torch copy kernel) so that "
                          "hardware byte counters can be scaled against a known size")
@@ -215,6 +221,8 @@ def main():
     sim.set_graph(args.graph)
     cells = sum(c.nx * c.ny for c in cases)
     tiles = sim.autotune(3)
+    if args.one_stream:
+        sim.set_overlap(False)
 
     # warm-up, then find the kernel class with the largest share of a step (timed steps
     # run every launch by itself)
@@ -243,7 +251,9 @@ def main():
     sim.timing_enable(-1)
     sec = t1 - t0
 
-    traffic = recorded_traffic(apdvm.KERNEL_CLASSES[dom], cfg["workload"], args.precision)
+    dname = apdvm.KERNEL_CLASSES[dom]
+    traffic = recorded_traffic(dname, cfg["workload"], args.precision,
+                               (tiles.get(dname), tiles.get("threads_" + dname)))
     bytes_step, launches = sim.traffic(dom)
     per_launch = bytes_step / launches
     mean_s = ms_dom / n_dom / 1e3

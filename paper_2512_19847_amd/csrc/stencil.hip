@@ -128,27 +128,21 @@ __device__ __forceinline__ double qdiv(double n, double d) {
 
 // Numerator and denominator of one reconstruction from s_k = (eps_w + beta_k)^2, q0,
 // Q1 = 6 q1 and Q2 = 3 q2: the weights d_k / s_k with d = (1, 6, 3)/10, multiplied
-// through by 10 s0 s1 s2 (float64), or by 10 (float, through reciprocals, where the
-// products could overflow).
-__device__ __forceinline__ void nd(double s0, double s1, double s2, double q0, double Q1,
-                                   double Q2, double &n, double &den) {
-  const double w0 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
+// through by 10 s0 s1 s2.  s_k >= eps_w^2 = 1e-12, so the products stay above 1e-24,
+// normal in float too.
+template <typename T>
+__device__ __forceinline__ void nd(T s0, T s1, T s2, T q0, T Q1, T Q2, T &n, T &den) {
+  const T w0 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
   n = fma(w0, q0, fma(p02, Q1, p01 * Q2));
-  den = fma(6.0, p02, fma(3.0, p01, w0));
+  den = fma(T(6), p02, fma(T(3), p01, w0));
 }
-__device__ __forceinline__ void nd(float s0, float s1, float s2, float q0, float Q1, float Q2,
-                                   float &n, float &den) {
-  const float r0 = __builtin_amdgcn_rcpf(s0), r1 = __builtin_amdgcn_rcpf(s1),
-              r2 = __builtin_amdgcn_rcpf(s2);
-  n = fma(r0, q0, fma(r1, Q1, r2 * Q2));
-  den = fma(6.0f, r1, fma(3.0f, r2, r0));
-}
-// n+/d+ + n-/d- with one division
+// n+/d+ + n-/d-: float64 with one division; float with two hardware reciprocals (the
+// product d+ d- can fall below the float range where every beta vanishes)
 __device__ __forceinline__ double sum2(double np, double dp, double nm, double dm) {
   return qdiv(fma(np, dm, nm * dp), dp * dm);
 }
 __device__ __forceinline__ float sum2(float np, float dp, float nm, float dm) {
-  return fma(np, dm, nm * dp) * __builtin_amdgcn_rcpf(dp * dm);
+  return fma(np, __builtin_amdgcn_rcpf(dp), nm * __builtin_amdgcn_rcpf(dm));
 }
 
 // Face between cells c2 and c3 of six consecutive values c0..c5 of one function g:
@@ -192,24 +186,17 @@ __device__ __forceinline__ T flux_lf(const T *p, const T *m) {
 // i+1/2 the left-biased value combines (3 g_i - g_{i-1})/2 and (g_i + g_{i+1})/2 with
 // linear weights 1/3 and 2/3 and indicators (g_i - g_{i-1})^2 and (g_{i+1} - g_i)^2;
 // multiplied through by 3 (eps_w + beta_0)^2 (eps_w + beta_1)^2 the weights become
-// s1 and 2 s0 with s_k = (eps_w + beta_k)^2 (float: reciprocals, as for WENO5).
+// s1 and 2 s0 with s_k = (eps_w + beta_k)^2.
 template <typename T>
 __device__ __forceinline__ T sq3(T d) {
   const T x = fma(d, d, T(1e-6));
   return x * x;
 }
-__device__ __forceinline__ void nd3(double s0, double s1, double q0, double q1, double &n,
-                                    double &den) {
-  const double w1 = 2.0 * s0;
+template <typename T>
+__device__ __forceinline__ void nd3(T s0, T s1, T q0, T q1, T &n, T &den) {
+  const T w1 = T(2) * s0;
   n = fma(s1, q0, w1 * q1);
   den = s1 + w1;
-}
-__device__ __forceinline__ void nd3(float s0, float s1, float q0, float q1, float &n,
-                                    float &den) {
-  const float w0 = (1.0f / 3.0f) * __builtin_amdgcn_rcpf(s0),
-              w1 = (2.0f / 3.0f) * __builtin_amdgcn_rcpf(s1);
-  n = fma(w0, q0, w1 * q1);
-  den = w0 + w1;
 }
 // Face between cells c2 and c3 of g (c1..c4 used): left- plus right-biased WENO3; the
 // two share the candidate (c2 + c3)/2 and the indicator (c3 - c2)^2.
