@@ -62,41 +62,42 @@ __device__ __forceinline__ int wrap(int g, int n) {
 }
 
 // WENO5 of Jiang and Shu, written through 3-cell windows.  For cells g_{k-1}, g_k,
-// g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and h = (g_{k+1} - g_{k-1}) / 2.  The
-// Jiang-Shu smoothness indicators of the three sub-stencils of a reconstruction are
-//   beta0 = 13/12 S^2 + (S + h)^2 on window i-1, beta1 = 13/12 S^2 + h^2 on window i,
-//   beta2 = 13/12 S^2 + (S - h)^2 on window i+1
-// (for window i-1, a - 4b + 3c = 2(S + h); for window i+1, 3c - 4d + e = 2(S - h)).
-// A window carries e = eps_w + 13/12 S^2 (eps_w = 1e-6), S and h, so each indicator
-// term (eps_w + beta)^2 is one fused multiply-add and a square.  Candidates at face
+// g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and D = g_{k+1} - g_{k-1}.  The Jiang-Shu
+// smoothness indicators of the three sub-stencils of a reconstruction are, times four,
+//   4 beta0 = 13/3 S^2 + (2S + D)^2 on window i-1, 4 beta1 = 13/3 S^2 + D^2 on window i,
+//   4 beta2 = 13/3 S^2 + (2S - D)^2 on window i+1
+// (for window i-1, a - 4b + 3c = 2S + D; for window i+1, 3c - 4d + e = 2S - D).
+// A window carries e = 4 eps_w + 13/3 S^2 (eps_w = 1e-6), S and D, so each indicator term
+// (4 eps_w + 4 beta)^2 = 16 (eps_w + beta)^2 is one fused multiply-add and a square; the
+// common factor 16 cancels in the normalised weights.  Candidates at face
 // i+1/2: q0 = (2 g_{i-2} - 7 g_{i-1} + 11 g_i)/6, q1 = (-g_{i-1} + 5 g_i + 2 g_{i+1})/6,
 // q2 = (2 g_i + 5 g_{i+1} - g_{i+2})/6, weights alpha_k = d_k / (eps_w + beta_k)^2 with
 // d = (1, 6, 3)/10; the right-biased reconstruction is the mirror image.
 
 template <typename T>
 struct Win {
-  T e, s, h;
+  T e, s, d;
 };
 template <typename T>
 __device__ __forceinline__ Win<T> win(T l, T c, T r) {
   const T S = fma(T(-2), c, l + r);
-  return Win<T>{fma(T(13.0 / 12.0) * S, S, T(1e-6)), S, T(0.5) * (r - l)};
+  return Win<T>{fma(T(13.0 / 3.0) * S, S, T(4e-6)), S, r - l};
 }
-// (eps_w + beta_k)^2 of the three indicator forms of a window
+// 16 (eps_w + beta_k)^2 of the three indicator forms of a window
 template <typename T>
 __device__ __forceinline__ T ind0(const Win<T> &w) {
-  const T t = w.s + w.h;
+  const T t = fma(T(2), w.s, w.d);
   const T x = fma(t, t, w.e);
   return x * x;
 }
 template <typename T>
 __device__ __forceinline__ T ind1(const Win<T> &w) {
-  const T x = fma(w.h, w.h, w.e);
+  const T x = fma(w.d, w.d, w.e);
   return x * x;
 }
 template <typename T>
 __device__ __forceinline__ T ind2(const Win<T> &w) {
-  const T t = w.s - w.h;
+  const T t = fma(T(2), w.s, -w.d);
   const T x = fma(t, t, w.e);
   return x * x;
 }
@@ -116,20 +117,19 @@ __device__ __forceinline__ T c3(T c, T d, T e) {
   return fma(T(2.5), d, fma(T(-0.5), e, c));
 }
 
-// float64 quotient through the hardware reciprocal, one Newton step and a residual
-// correction (the reciprocal's error is squared by the Newton step, far below 2^-26,
-// so the corrected quotient is within an ulp).
+// float64 quotient through the hardware reciprocal and one Newton step (the
+// reciprocal's error, about 2^-26, is squared by the step: the quotient is within a few
+// ulps, far inside what the weights need).
 __device__ __forceinline__ double qdiv(double n, double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
-  const double q = n * r;
-  return fma(r, fma(-d, q, n), q);
+  return n * r;
 }
 
-// Numerator and denominator of one reconstruction from s_k = (eps_w + beta_k)^2, q0,
+// Numerator and denominator of one reconstruction from s_k = 16 (eps_w + beta_k)^2, q0,
 // Q1 = 6 q1 and Q2 = 3 q2: the weights d_k / s_k with d = (1, 6, 3)/10, multiplied
-// through by 10 s0 s1 s2.  s_k >= eps_w^2 = 1e-12, so the products stay above 1e-24,
-// normal in float too.
+// through by 10 s0 s1 s2.  s_k >= 16 eps_w^2 = 1.6e-11, so the products stay above
+// 2.5e-22, normal in float too.
 template <typename T>
 __device__ __forceinline__ void nd(T s0, T s1, T s2, T q0, T Q1, T Q2, T &n, T &den) {
   const T w0 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
