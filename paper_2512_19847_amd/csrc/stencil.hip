@@ -245,6 +245,69 @@ __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf)
   return sf * flux3_sym(f[stride], f[2 * stride], f[3 * stride], f[4 * stride]);
 }
 
+// WENO5 fluxes at the three consecutive faces k = 0, 1, 2 between cells 2 + k and 3 + k of
+// eight consecutive cells (stride apart): face k takes the same operations as face_flux
+// on cells k .. k + 5, but each window and split value is formed once for the up to three
+// faces that use it (windows centred on cells 1..5 for f+ and 2..6 for f-, or 1..6
+// without dissipation, instead of six per face).
+template <typename T, bool DISS>
+__device__ __forceinline__ void face_flux3(const T *f, const T *w, int stride, T sf, T *out) {
+  if (DISS) {
+    T p[7], m[8];  // f+ on cells 0..6, f- on cells 1..7
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const T fk = f[k * stride], wk = w[k * stride];
+      if (k < 7) p[k] = fma(sf, fk, wk);
+      if (k > 0) m[k] = fma(sf, fk, -wk);
+    }
+    Win<T> wp[6], wm[7];
+#pragma unroll
+    for (int c = 1; c <= 5; ++c) wp[c] = win(p[c - 1], p[c], p[c + 1]);
+#pragma unroll
+    for (int c = 2; c <= 6; ++c) wm[c] = win(m[c - 1], m[c], m[c + 1]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T q0 = cfar(p[j], p[j + 1], p[j + 2]);
+      const T q1 = c6(p[j + 1], p[j + 2], p[j + 3]);
+      const T q2 = c3(p[j + 2], p[j + 3], p[j + 4]);
+      const T r0 = cfar(m[j + 5], m[j + 4], m[j + 3]);
+      const T r1 = c6(m[j + 4], m[j + 3], m[j + 2]);
+      const T r2 = c3(m[j + 3], m[j + 2], m[j + 1]);
+      T np, dp, nm, dm;
+      nd(ind0(wp[j + 1]), ind1(wp[j + 2]), ind2(wp[j + 3]), q0, q1, q2, np, dp);
+      nd(ind2(wm[j + 4]), ind1(wm[j + 3]), ind0(wm[j + 2]), r0, r1, r2, nm, dm);
+      out[j] = sum2(np, dp, nm, dm);
+    }
+  } else {
+    T c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = f[k * stride];
+    Win<T> wc[7];
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) wc[k] = win(c[k - 1], c[k], c[k + 1]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T M6 = c6(c[j + 1], c[j + 2], c[j + 3]);
+      const T N6 = c6(c[j + 4], c[j + 3], c[j + 2]);
+      const T P = cfar(c[j], c[j + 1], c[j + 2]);
+      const T Pm = cfar(c[j + 5], c[j + 4], c[j + 3]);
+      T np, dp, nm, dm;
+      nd(ind0(wc[j + 1]), ind1(wc[j + 2]), ind2(wc[j + 3]), P, M6, T(0.5) * N6, np, dp);
+      nd(ind2(wc[j + 4]), ind1(wc[j + 3]), ind0(wc[j + 2]), Pm, N6, T(0.5) * M6, nm, dm);
+      out[j] = sf * sum2(np, dp, nm, dm);
+    }
+  }
+}
+
+// Faces per thread in the flux rounds: three (face_flux3) for WENO5 where the registers
+// allow it without fewer waves per SIMD: float, and the float64 stage-terms kernel on
+// 64 x 16 tiles, whose LDS already limits it to six waves per SIMD (ST: the stage-terms
+// kernel); one otherwise.
+template <typename T, int WO, int TY = 8, int NT = 256, bool ST = false>
+constexpr int faces_per_thread() {
+  return WO == 5 && (sizeof(T) == 4 || (ST && TY == 16 && NT == 512)) ? 3 : 1;
+}
+
 // LDS tile geometry for a 64 x TY tile with a 3-cell halo, worked on by NT threads
 // (NT / 64 wavefronts; thread t owns column t % 64 and rows t / 64 + (NT / 64) k).
 template <int TY, int NT>
@@ -302,11 +365,45 @@ struct Stage {
 };
 
 // x faces (TY rows x 65) and y faces (TY + 1 rows x 64) of two fluxes in one index
-// space; the x part is padded to whole wavefronts so no wavefront mixes the two.
-template <int TY, int NT, int WO, typename T, bool DX, bool DY>
+// space; the x part is padded to whole wavefronts so no wavefront mixes the two.  With
+// three faces per thread an item is a run of three faces along the flux direction; the
+// last run of a row (column) starts three faces before its end and stores only the faces
+// no earlier run covers, so every read stays inside the staged tile.
+template <int TY, int NT, int WO, typename T, bool DX, bool DY,
+          int FPT = faces_per_thread<T, WO>()>
 __device__ __forceinline__ void faces(T *fx, T *fy, const T *fxf, const T *fxw, T sx,
                                       const T *fyf, const T *fyw, T sy) {
   using Gm = Geo<TY, NT>;
+  if constexpr (FPT == 3) {
+    constexpr int NFX = kTileX + 1, NIX = (NFX + 2) / 3;  // x faces, runs per row
+    constexpr int XI = TY * NIX, XIP = (XI + 63) / 64 * 64;
+    constexpr int NFY = TY + 1, NIY = (NFY + 2) / 3;      // y faces, runs per column
+    constexpr int YI = NIY * kTileX;
+    for (int idx = threadIdx.x; idx < XIP + YI; idx += NT) {
+      T o[3];
+      if (idx < XIP) {
+        if (idx < XI) {
+          const int ly = idx / NIX, i = idx - ly * NIX;
+          const int f0 = min(3 * i, NFX - 3);
+          const int base = (ly + kHalo) * Gm::W + f0;  // cell f0 - 3 of row ly
+          face_flux3<T, DX>(fxf + base, fxw + base, 1, sx, o);
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if (f0 + k >= 3 * i) fx[ly * NFX + f0 + k] = o[k];
+        }
+      } else {
+        const int j = idx - XIP;
+        const int i = j / kTileX, lx = j - i * kTileX;
+        const int f0 = min(3 * i, NFY - 3);
+        const int base = f0 * Gm::W + lx + kHalo;  // cell f0 - 3 of column lx
+        face_flux3<T, DY>(fyf + base, fyw + base, Gm::W, sy, o);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (f0 + k >= 3 * i) fy[(f0 + k) * kTileX + lx] = o[k];
+      }
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < Gm::FXP + Gm::FYN; idx += NT) {
     if (idx < Gm::FXP) {
       if (idx < Gm::FXN) {
@@ -716,7 +813,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   // first component of (tau/4) D0_W.B(u); E is assembled at the end
   T e1[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
-  faces<TY, NT, WO, T, false, false>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
+  constexpr int FPT = faces_per_thread<T, WO, TY, NT, true>();
+  faces<TY, NT, WO, T, false, false, FPT>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -725,7 +823,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
   __syncthreads();
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
-  faces<TY, NT, WO, T, false, false>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
+  faces<TY, NT, WO, T, false, false, FPT>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
   __syncthreads();
   if (!col) return;
   // pointwise inputs of E and of the fused step 1: G, v, and
