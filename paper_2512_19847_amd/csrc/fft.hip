@@ -476,7 +476,8 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   }
 }
 
-// Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values.
+// Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values
+// (the launch takes ev, st, insts and a of the calling function).
 #define APDVM_FFT_FORM(V, KERNEL, WORK, NWORK)                                             \
   do {                                                                                     \
     if ((V) == 2)                                                                          \

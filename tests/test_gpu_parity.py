@@ -177,6 +177,27 @@ def test_batched_heterogeneous_instances():
         assert max(err.values()) <= TOL, (k, err)
 
 
+@pytest.mark.parametrize("sides", [((2048, 16), (16, 2048)), ((8192, 8), (8, 8192))])
+def test_extreme_aspect_ratios_every_fft_form(sides):
+    """Long thin instances in one context: rows and columns of up to 2048 (8192) values
+    take the 2048-value (8192-value) FFT forms, while the short sides put many rows
+    (columns) into one workgroup; two steps against the oracle.  q is ~1e-4 here, a
+    cancellation of O(|u|^2) terms whose rounding the 1/h = 1300 of the long side
+    amplifies, so v and q are held against max |u|^2 (kinetic floor)."""
+    cases = []
+    for k, (nx, ny) in enumerate(sides):
+        c = wl.make_case(f"thin{k}", wl.random_divfree(nx, ny, kmax=3, rms=0.1, seed=50 + k),
+                         0.05, 0.05, "ars443", cfl=wl.CFL_ARS)
+        cases.append(dict(state=c.state, eps=c.eps, tau=c.tau, dt=c.dt))
+    _say(f"case aspect ratios {sides}")
+    got = _run_gpu(cases, "ars443", 2)
+    for k, c in enumerate(cases):
+        ref = _oracle(c["state"], c["eps"], c["tau"], c["dt"], "ars443", 2)
+        err = _relerr(got[k], ref, kinetic_floor=True)
+        _say(f"  instance {k} {sides[k]} relerr {err}")
+        assert max(err.values()) <= TOL, (k, err)
+
+
 @pytest.mark.parametrize("eps", [1.0, 1e-2, 1e-6])
 def test_shear_layer_512_one_step(eps):
     """Full 512^2 size of the third-order shear-layer runs, one step, every cell."""
