@@ -155,18 +155,17 @@ struct TwStage {
   }
 };
 
-// One Stockham pass over nb transforms of length n held in LDS, element j of
-// transform b at buf[j * es + b * bs].  BMAJOR: consecutive threads take consecutive
-// transforms (column tiles) instead of consecutive butterflies (rows).  The first pass
-// (Ns = 1) has unit twiddles and skips them.
-template <int R, int DIR, bool BMAJOR, int CAP, int NT>
-__device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs, int Ns,
-                                     const double2 *tws, int lb) {
+// One Stockham pass over nb transforms of length n held in LDS, element j of transform b
+// at buf[lp(b n + j)]; consecutive threads take consecutive butterflies of a transform.
+// The first pass (Ns = 1) has unit twiddles and skips them.
+template <int R, int DIR, int CAP, int NT>
+__device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const double2 *tws,
+                                     int lb) {
   constexpr int NPER = (CAP + R * NT - 1) / (R * NT);
   const int nbf = n / R;
   const int total = nbf * nb;
   const int twstep = n / (Ns * R);
-  const Div dmaj(BMAJOR ? nb : nbf), dns(Ns);
+  const Div dnbf(nbf), dns(Ns);
   double2 v[NPER][R];
   int dst[NPER];
 #pragma unroll
@@ -174,17 +173,11 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
     const int t = threadIdx.x + p * NT;
     dst[p] = -1;
     if (t < total) {
-      int j, b;
-      if (BMAJOR) {
-        j = dmaj.q(t);
-        b = t - j * nb;
-      } else {
-        b = dmaj.q(t);
-        j = t - b * nbf;
-      }
+      const int b = dnbf.q(t), j = t - b * nbf;
       const int jq = dns.q(j), k = j - jq * Ns;
+      const int src = b * n + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[lp((j + r * nbf) * es + b * bs)];
+      for (int r = 0; r < R; ++r) v[p][r] = buf[lp(src + r * nbf)];
       if (Ns > 1) {
         // w^r for r = 1..R-1 from one table lookup: powers by products of depth <= 3
         double2 w[R];
@@ -202,7 +195,7 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
         for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], w[r]);
       }
       dft<R, DIR>(v[p]);
-      dst[p] = (jq * Ns * R + k) * es + b * bs;
+      dst[p] = b * n + jq * Ns * R + k;
     }
   }
   __syncthreads();
@@ -210,23 +203,24 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int es, int bs
   for (int p = 0; p < NPER; ++p) {
     if (dst[p] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lp(dst[p] + r * Ns * es)] = v[p][r];
+      for (int r = 0; r < R; ++r) buf[lp(dst[p] + r * Ns)] = v[p][r];
     }
   }
   __syncthreads();
 }
 
-template <int DIR, bool BMAJOR, int CAP, int NT>
-__device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb, int es, int bs,
+// Length-n transforms (plan P) of nb contiguous runs of n values in LDS.
+template <int DIR, int CAP, int NT>
+__device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb,
                                         const double2 *tws) {
   int Ns = 1;
   for (int ps = 0; ps < P.npass; ++ps) {
     const int R = P.radix[ps];
     switch (R) {
-      case 8: pass<8, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
-      case 4: pass<4, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
-      case 3: pass<3, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
-      default: pass<2, DIR, BMAJOR, CAP, NT>(buf, P.n, nb, es, bs, Ns, tws, P.lb); break;
+      case 8: pass<8, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
+      case 4: pass<4, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
+      case 3: pass<3, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
+      default: pass<2, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
     }
     Ns *= R;
   }
@@ -281,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
     if (idx < cnt) buf[lp(idx)] = make_double2(ra[e], rb[e]);
   }
   __syncthreads();
-  fft_lds<-1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
+  fft_lds<-1, CAP, NT>(buf, I.fx, np, tws);
   // column-major half spectra S[k][y] for the 2 np rows y = 2 p0 .. of the block:
   // consecutive threads write consecutive rows of one column
   const int ny = I.ny, m = 2 * np;
@@ -359,7 +353,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
     if (idx < cnt) buf[lp(idx)] = v[e];
   }
   __syncthreads();
-  fft_lds<-1, false, CAP, NT>(buf, I.fy, C, 1, ny, tws);
+  fft_lds<-1, CAP, NT>(buf, I.fy, C, tws);
   double2 o[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -405,7 +399,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
     if (idx < cnt) buf[lp(idx)] = o[e];
   }
   __syncthreads();
-  fft_lds<1, false, CAP, NT>(buf, I.fy, C, 1, ny, tws);
+  fft_lds<1, CAP, NT>(buf, I.fy, C, tws);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int idx = threadIdx.x + e * NT;
@@ -461,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
     }
   }
   __syncthreads();
-  fft_lds<1, false, CAP, NT>(buf, I.fx, np, 1, n, tws);
+  fft_lds<1, CAP, NT>(buf, I.fx, np, tws);
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
   const Div dn(n);
 #pragma unroll

@@ -497,6 +497,35 @@ __device__ __forceinline__ Gp<double> dplane(const Inst &I, int slot) {
   return gp(I.dbase + (long long)slot * I.plane);
 }
 
+// History terms of a stage update at one cell: s_k += sum_{j < n} c_j plane(slot[j][k]),
+// k < NC components, accumulated in float64 in the order j = 0, 1, ...  load() issues the
+// loads of the first kHistBatch terms together, ahead of any use (a plain loop waits for
+// each load before issuing the next, one memory round trip per term); add() sums them
+// and takes any further terms one by one.
+constexpr int kHistBatch = 3;
+template <typename T, int NC>
+struct Hist {
+  T v[kHistBatch][NC];
+  __device__ __forceinline__ void load(const Inst &I, const int *slot, int n, long long g) {
+#pragma unroll
+    for (int j = 0; j < kHistBatch; ++j)
+      if (j < n)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[j][k] = tplane<T>(I, slot[j * NC + k])[g];
+  }
+  __device__ __forceinline__ void add(const Inst &I, double *s, const int *slot, const double *c,
+                                      int n, long long g) const {
+#pragma unroll
+    for (int j = 0; j < kHistBatch; ++j)
+      if (j < n)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) s[k] += c[j] * (double)v[j][k];
+    for (int j = kHistBatch; j < n; ++j)
+#pragma unroll
+      for (int k = 0; k < NC; ++k) s[k] += c[j] * (double)tplane<T>(I, slot[j * NC + k])[g];
+  }
+};
+
 // ------------------------------------------------------------------ step 2 RHS
 
 template <typename T, int TY, int NT, int CO>
@@ -525,11 +554,15 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
     base[r] = 0.0;
     if (col && gy < I.ny) {
       const long long g = (long long)gy * I.nx + gx;
+      Hist<T, 1> HD, HL;
+      HD.load(I, a.D, a.nD, g);
+      HL.load(I, a.L, a.nL, g);
+      const double thn = dplane(I, a.thn)[g];
+      const double du0 = (double)tplane<T>(I, a.du0)[g];
       double hd = 0.0, hl = 0.0;
-      for (int j = 0; j < a.nD; ++j) hd += a.cD[j] * (double)tplane<T>(I, a.D[j])[g];
-      for (int j = 0; j < a.nL; ++j) hl += a.cL[j] * (double)tplane<T>(I, a.L[j])[g];
-      base[r] = -sig * dplane(I, a.thn)[g] + c_d * hd + c_0 * (double)tplane<T>(I, a.du0)[g] -
-                c_l * hl;
+      HD.add(I, &hd, a.D, a.cD, a.nD, g);
+      HL.add(I, &hl, a.L, a.cL, a.nL, g);
+      base[r] = -sig * thn + c_d * hd + c_0 * du0 - c_l * hl;
     }
   }
   {
@@ -630,14 +663,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
     if (gy < ny) {
       const long long g = (long long)gy * nx + gx;
+      Hist<T, 2> HH;
+      Hist<T, 1> HG;
+      HH.load(I, &a.H[0][0], a.nH, g);
+      HG.load(I, a.G, a.nG, g);
       un1[r] = (double)tplane<T>(I, a.un[0])[g];
       un2[r] = (double)tplane<T>(I, a.un[1])[g];
       qn[r] = (double)tplane<T>(I, a.qn)[g];
-      for (int j = 0; j < a.nH; ++j) {
-        h1[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][0])[g];
-        h2[r] += a.cH[j] * (double)tplane<T>(I, a.H[j][1])[g];
-      }
-      for (int j = 0; j < a.nG; ++j) hg[r] += a.cG[j] * (double)tplane<T>(I, a.G[j])[g];
+      double h[2] = {0.0, 0.0};
+      HH.add(I, h, &a.H[0][0], a.cH, a.nH, g);
+      HG.add(I, &hg[r], a.G, a.cG, a.nG, g);
+      h1[r] = h[0];
+      h2[r] = h[1];
     }
   }
   const double dt = I.dt, te2 = I.te2, kinv = I.kinv[a.stage], aii = a.aii;
@@ -841,19 +878,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       g1[r] = tplane<T>(I, a.g[0])[g];
       g2[r] = tplane<T>(I, a.g[1])[g];
       if (nv.stage > 0) {
+        Hist<T, 2> HE, HV;
+        HE.load(I, &nv.E[0][0], nv.nE, g);
+        HV.load(I, &nv.V[0][0], nv.nV, g);
         w1[r] = tplane<T>(I, a.v[0])[g];
         w2[r] = tplane<T>(I, a.v[1])[g];
-        double h1 = 0.0, h2 = 0.0;
-        for (int j = 0; j < nv.nE; ++j) {
-          h1 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][0])[g];
-          h2 += nv.cE[j] * (double)tplane<T>(I, nv.E[j][1])[g];
-        }
-        for (int j = 0; j < nv.nV; ++j) {
-          h1 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][0])[g];
-          h2 += nv.cV[j] * (double)tplane<T>(I, nv.V[j][1])[g];
-        }
-        rv1[r] = te2d * (double)tplane<T>(I, nv.vn[0])[g] - dt * h1;
-        rv2[r] = te2d * (double)tplane<T>(I, nv.vn[1])[g] - dt * h2;
+        const double vn1 = (double)tplane<T>(I, nv.vn[0])[g];
+        const double vn2 = (double)tplane<T>(I, nv.vn[1])[g];
+        double h[2] = {0.0, 0.0};
+        HE.add(I, h, &nv.E[0][0], nv.cE, nv.nE, g);
+        HV.add(I, h, &nv.V[0][0], nv.cV, nv.nV, g);
+        rv1[r] = te2d * vn1 - dt * h[0];
+        rv2[r] = te2d * vn2 - dt * h[1];
       }
     }
   }
