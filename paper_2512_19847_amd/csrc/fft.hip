@@ -236,8 +236,9 @@ __device__ __forceinline__ Gp<dv2> cslot(const Inst &I, int slot) {
 
 
 // Each kernel below stages its tile in two phases: every thread first issues all of its
-// global loads (data, twiddle table, and the Helmholtz divisors of the elements it will
-// scale), then writes them to LDS, so one memory round trip covers the whole tile.
+// global loads (data, twiddle table and, in the small column form, the symbol values of
+// the modes it will scale), then writes them to LDS, so one memory round trip covers the
+// whole tile.
 
 // ------------------------------------------------------------------ rows forward
 
