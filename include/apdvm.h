@@ -237,9 +237,9 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
 
 /* Autotune the launch shapes: for the stencil kernel classes (0, 4, 5, 6) each shape is
  * timed with HIP events over steps_per_trial steps of the live simulation; the fastest is
- * kept.  Then whole steps with and without
- * the second stream (apdvm_set_overlap) are timed in the context's launch mode and the
- * faster kept.  The state, the step counter and the launch mode are restored afterwards
+ * kept.  Then whole steps with and without the second stream (apdvm_set_overlap) are
+ * timed in the context's launch mode, twice each and interleaved, each run at least
+ * 2 steps_per_trial steps and about 10 ms, and the faster kept.  The state, the step counter and the launch mode are restored afterwards
  * (this call allocates a temporary device copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
  * choice for the same context shape is read from it and no trial runs; new choices are
  * appended to it.  choice (NULL, or APDVM_TUNING_LEN entries) receives the choice.

@@ -1469,20 +1469,30 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     c->use_graph = graph;  // the stream structures compete in the caller's launch mode
     drop_graphs(c);        // graphs of earlier launch shapes
     if (ok) {
+      // two passes over the two structures, interleaved (off, on, off, on) so that a drift
+      // of the clock or of other work on the device hits both alike; each timed run has at
+      // least 2 steps_per_trial steps and, once the step time is known, enough steps for
+      // about 10 ms
       double tov[2] = {0.0, 0.0};
+      int nsteps = 2 * steps_per_trial;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-      for (int on = 0; ok && on < 2; ++on) {
+      for (int t = 0; ok && t < 4; ++t) {
+        const int on = t & 1;
         // two warm-up steps: in graph mode each parity's graph is captured and uploaded
         // before the timed steps
         ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 2) == APDVM_OK;
         ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
-        ok = ok && apdvm_step(c, 2 * steps_per_trial) == APDVM_OK;
+        ok = ok && apdvm_step(c, nsteps) == APDVM_OK;
         ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
              hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.0f;
         ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        tov[on] = ms;
+        tov[on] += ms / nsteps;
+        if (t == 0 && ms > 0.0f && ms < 10.0f) {
+          const int want = (int)(10.0f / (ms / nsteps)) + 1;
+          nsteps = want > 64 ? 64 : (want > nsteps ? want : nsteps);
+        }
       }
       if (e0) (void)hipEventDestroy(e0);
       if (e1) (void)hipEventDestroy(e1);
