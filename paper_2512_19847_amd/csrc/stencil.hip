@@ -56,7 +56,11 @@ __device__ __forceinline__ int xcd_item(int nwork) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Periodic index.  A staged tile reaches at most its width plus the halo past either end
+// of the grid, so one add or subtract of n wraps every index of a grid of 72 cells or
+// more; the division remains for smaller grids, whose halos can wrap several times.
 __device__ __forceinline__ int wrap(int g, int n) {
+  g += g < 0 ? n : (g >= n ? -n : 0);
   if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
   return g;
 }
