@@ -328,6 +328,12 @@ struct Geo {
   __device__ static int at(int lx, int ly) { return (ly + kHalo) * W + lx + kHalo; }
 };
 
+// Value at a 32-bit byte offset from a plane base.
+template <typename G>
+__device__ __forceinline__ G ld_byte(Gp<const G> base, unsigned boff) {
+  return *reinterpret_cast<Gp<const G>>(reinterpret_cast<Gp<const char>>(base) + boff);
+}
+
 // Staging of NP planes (with periodic halo H) into LDS in two phases: load() issues
 // every global load of the thread into registers, store() converts, scales and writes
 // them to LDS.  Loads of several planes (and of later phases) are thus in flight
@@ -351,9 +357,12 @@ struct Stage {
         gx = wrap(gx, nx);
         gy = wrap(gy, ny);
       }
-      const long long off = idx < PL ? (long long)gy * nx + gx : 0;
+      // byte offset in 32 bits (a plane holds at most 8192^2 float64 values, 512 MiB),
+      // so each load takes the plane base as a scalar and this offset as its only
+      // per-lane address
+      const unsigned boff = idx < PL ? (unsigned)(gy * nx + gx) * (unsigned)sizeof(G) : 0u;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) v[p][it] = plane[p][off];
+      for (int p = 0; p < NP; ++p) v[p][it] = ld_byte(plane[p], boff);
     }
   }
   template <typename S>
@@ -501,6 +510,24 @@ __device__ __forceinline__ Gp<double> dplane(const Inst &I, int slot) {
   return gp(I.dbase + (long long)slot * I.plane);
 }
 
+// One cell of every plane: its byte offsets in transport and float64 planes, in 32 bits
+// (a plane holds at most 8192^2 float64 values, 512 MiB), so a load or store takes the
+// plane base as a scalar and one shared offset as its per-lane address.
+struct Cell {
+  unsigned t, d;
+};
+template <typename T>
+__device__ __forceinline__ Cell cell_at(int idx) {
+  return Cell{(unsigned)idx * (unsigned)sizeof(T), (unsigned)idx * 8u};
+}
+template <typename T>
+__device__ __forceinline__ Gp<T> tcell(const Inst &I, int slot, const Cell &c) {
+  return reinterpret_cast<Gp<T>>(reinterpret_cast<Gp<char>>(tplane<T>(I, slot)) + c.t);
+}
+__device__ __forceinline__ Gp<double> dcell(const Inst &I, int slot, const Cell &c) {
+  return reinterpret_cast<Gp<double>>(reinterpret_cast<Gp<char>>(dplane(I, slot)) + c.d);
+}
+
 // History terms of a stage update at one cell: s_k += sum_{j < n} c_j plane(slot[j][k]),
 // k < NC components, accumulated in float64 in the order j = 0, 1, ...  load() issues the
 // loads of the first kHistBatch terms together, ahead of any use (a plain loop waits for
@@ -510,15 +537,15 @@ constexpr int kHistBatch = 3;
 template <typename T, int NC>
 struct Hist {
   T v[kHistBatch][NC];
-  __device__ __forceinline__ void load(const Inst &I, const int *slot, int n, long long g) {
+  __device__ __forceinline__ void load(const Inst &I, const int *slot, int n, const Cell &g) {
 #pragma unroll
     for (int j = 0; j < kHistBatch; ++j)
       if (j < n)
 #pragma unroll
-        for (int k = 0; k < NC; ++k) v[j][k] = tplane<T>(I, slot[j * NC + k])[g];
+        for (int k = 0; k < NC; ++k) v[j][k] = *tcell<T>(I, slot[j * NC + k], g);
   }
   __device__ __forceinline__ void add(const Inst &I, double *s, const int *slot, const double *c,
-                                      int n, long long g) const {
+                                      int n, const Cell &g) const {
 #pragma unroll
     for (int j = 0; j < kHistBatch; ++j)
       if (j < n)
@@ -526,7 +553,7 @@ struct Hist {
         for (int k = 0; k < NC; ++k) s[k] += c[j] * (double)v[j][k];
     for (int j = kHistBatch; j < n; ++j)
 #pragma unroll
-      for (int k = 0; k < NC; ++k) s[k] += c[j] * (double)tplane<T>(I, slot[j * NC + k])[g];
+      for (int k = 0; k < NC; ++k) s[k] += c[j] * (double)*tcell<T>(I, slot[j * NC + k], g);
   }
 };
 
@@ -557,12 +584,12 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
     const int gy = wk.b + ty0 + Gm::WV * r;
     base[r] = 0.0;
     if (col && gy < I.ny) {
-      const long long g = (long long)gy * I.nx + gx;
+      const Cell g = cell_at<T>(gy * I.nx + gx);
       Hist<T, 1> HD, HL;
       HD.load(I, a.D, a.nD, g);
       HL.load(I, a.L, a.nL, g);
-      const double thn = dplane(I, a.thn)[g];
-      const double du0 = (double)tplane<T>(I, a.du0)[g];
+      const double thn = *dcell(I, a.thn, g);
+      const double du0 = (double)*tcell<T>(I, a.du0, g);
       double hd = 0.0, hl = 0.0;
       HD.add(I, &hd, a.D, a.cD, a.nD, g);
       HL.add(I, &hl, a.L, a.cL, a.nL, g);
@@ -587,9 +614,9 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
     // D0^2 : B(v) = -D_xx v1 + 2 D_x D_y v2 + D_yy v1
     const T ddb = -C::d2(sV1, c, 1, ihx2) + T(2) * C::dxy(sV2, c, Gm::W, ihx12, ihy12) +
                   C::d2(sV1, c, Gm::W, ihy2);
-    const long long g = (long long)gy * I.nx + gx;
-    dplane(I, a.out_r)[g] = base[r] - (double)ddb;
-    tplane<T>(I, a.out_ddb)[g] = ddb;
+    const Cell g = cell_at<T>(gy * I.nx + gx);
+    *dcell(I, a.out_r, g) = base[r] - (double)ddb;
+    *tcell<T>(I, a.out_ddb, g) = ddb;
   }
 }
 
@@ -666,14 +693,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const int gy = wk.b + ty0 + Gm::WV * r;
     un1[r] = un2[r] = qn[r] = h1[r] = h2[r] = hg[r] = 0.0;
     if (gy < ny) {
-      const long long g = (long long)gy * nx + gx;
+      const Cell g = cell_at<T>(gy * nx + gx);
       Hist<T, 2> HH;
       Hist<T, 1> HG;
       HH.load(I, &a.H[0][0], a.nH, g);
       HG.load(I, a.G, a.nG, g);
-      un1[r] = (double)tplane<T>(I, a.un[0])[g];
-      un2[r] = (double)tplane<T>(I, a.un[1])[g];
-      qn[r] = (double)tplane<T>(I, a.qn)[g];
+      un1[r] = (double)*tcell<T>(I, a.un[0], g);
+      un2[r] = (double)*tcell<T>(I, a.un[1], g);
+      qn[r] = (double)*tcell<T>(I, a.qn, g);
       double h[2] = {0.0, 0.0};
       HH.add(I, h, &a.H[0][0], a.cH, a.nH, g);
       HG.add(I, &hg[r], a.G, a.cG, a.nG, g);
@@ -687,16 +714,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int gy = wk.b + ty0 + Gm::WV * r;
     if (gy >= ny) break;
-    const long long g = (long long)gy * nx + gx;
+    const Cell g = cell_at<T>(gy * nx + gx);
     const double Hq = htau * (double)dv[r];
     const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
-    tplane<T>(I, a.out_us[0])[g] = (T)(un1[r] - dt * (h1[r] + aii * (double)hu1[r]));
-    tplane<T>(I, a.out_us[1])[g] = (T)(un2[r] - dt * (h2[r] + aii * (double)hu2[r]));
-    tplane<T>(I, a.out_q)[g] = (T)q;
+    *tcell<T>(I, a.out_us[0], g) = (T)(un1[r] - dt * (h1[r] + aii * (double)hu1[r]));
+    *tcell<T>(I, a.out_us[1], g) = (T)(un2[r] - dt * (h2[r] + aii * (double)hu2[r]));
+    *tcell<T>(I, a.out_q, g) = (T)q;
     if (a.out_hu[0] != kNoSlot) {
-      tplane<T>(I, a.out_hu[0])[g] = hu1[r];
-      tplane<T>(I, a.out_hu[1])[g] = hu2[r];
-      tplane<T>(I, a.out_gq)[g] = (T)(Hq + q);
+      *tcell<T>(I, a.out_hu[0], g) = hu1[r];
+      *tcell<T>(I, a.out_hu[1], g) = hu2[r];
+      *tcell<T>(I, a.out_gq, g) = (T)(Hq + q);
     }
   }
 }
@@ -734,9 +761,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= ny) break;
-    const long long g = (long long)gy * nx + gx;
-    tplane<T>(I, a.out_g[0])[g] = te2 * face_dx<TY>(fx, tx, ly, ihx);
-    tplane<T>(I, a.out_g[1])[g] = te2 * face_dy<TY>(fy, tx, ly, ihy);
+    const Cell g = cell_at<T>(gy * nx + gx);
+    *tcell<T>(I, a.out_g[0], g) = te2 * face_dx<TY>(fx, tx, ly, ihx);
+    *tcell<T>(I, a.out_g[1], g) = te2 * face_dy<TY>(fy, tx, ly, ihy);
   }
 }
 
@@ -788,12 +815,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       const int gy = wk.b + ty0 + Gm::WV * r;
       hv1[r] = hv2[r] = dd[r] = T(0);
       if (col && gy < ny) {
-        const long long g = (long long)gy * nx + gx;
+        const Cell g = cell_at<T>(gy * nx + gx);
         if (want_hu) {
-          hv1[r] = tplane<T>(I, a.hu[0])[g];
-          hv2[r] = tplane<T>(I, a.hu[1])[g];
+          hv1[r] = *tcell<T>(I, a.hu[0], g);
+          hv2[r] = *tcell<T>(I, a.hu[1], g);
         }
-        if (want_lt) dd[r] = tplane<T>(I, a.ddb)[g];
+        if (want_lt) dd[r] = *tcell<T>(I, a.ddb, g);
       }
     }
     double *sT = reinterpret_cast<double *>(sF);
@@ -824,18 +851,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
         const int ly = ty0 + Gm::WV * r;
         const int gy = wk.b + ly;
         if (gy >= ny) break;
-        const long long g = (long long)gy * nx + gx;
+        const Cell g = cell_at<T>(gy * nx + gx);
         const int c = Gm::at(tx, ly);
         const int cw = (ly + kHalo + C::R) * SW::W + tx + kHalo + C::R;
-        tplane<T>(I, a.out_u[0])[g] = T(2) * sU1[c];
-        tplane<T>(I, a.out_u[1])[g] = T(2) * sU2[c];
+        *tcell<T>(I, a.out_u[0], g) = T(2) * sU1[c];
+        *tcell<T>(I, a.out_u[1], g) = T(2) * sU2[c];
         if (want_hu) {
-          tplane<T>(I, a.hu[0])[g] = (T)((double)hv1[r] + C::d1(sT, cw, 1, f1x));
-          tplane<T>(I, a.hu[1])[g] = (T)((double)hv2[r] + C::d1(sT, cw, SW::W, f1y));
+          *tcell<T>(I, a.hu[0], g) = (T)((double)hv1[r] + C::d1(sT, cw, 1, f1x));
+          *tcell<T>(I, a.hu[1], g) = (T)((double)hv2[r] + C::d1(sT, cw, SW::W, f1y));
         }
         if (want_lt) {
           const double lap = C::d2(sT, cw, 1, f2x) + C::d2(sT, cw, SW::W, f2y);
-          tplane<T>(I, a.out_lt)[g] = (T)((double)dd[r] + lap);
+          *tcell<T>(I, a.out_lt, g) = (T)((double)dd[r] + lap);
         }
       }
     }
@@ -878,17 +905,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     g1[r] = g2[r] = w1[r] = w2[r] = T(0);
     rv1[r] = rv2[r] = 0.0;
     if (gy < ny) {
-      const long long g = (long long)gy * nx + gx;
-      g1[r] = tplane<T>(I, a.g[0])[g];
-      g2[r] = tplane<T>(I, a.g[1])[g];
+      const Cell g = cell_at<T>(gy * nx + gx);
+      g1[r] = *tcell<T>(I, a.g[0], g);
+      g2[r] = *tcell<T>(I, a.g[1], g);
       if (nv.stage > 0) {
         Hist<T, 2> HE, HV;
         HE.load(I, &nv.E[0][0], nv.nE, g);
         HV.load(I, &nv.V[0][0], nv.nV, g);
-        w1[r] = tplane<T>(I, a.v[0])[g];
-        w2[r] = tplane<T>(I, a.v[1])[g];
-        const double vn1 = (double)tplane<T>(I, nv.vn[0])[g];
-        const double vn2 = (double)tplane<T>(I, nv.vn[1])[g];
+        w1[r] = *tcell<T>(I, a.v[0], g);
+        w2[r] = *tcell<T>(I, a.v[1], g);
+        const double vn1 = (double)*tcell<T>(I, nv.vn[0], g);
+        const double vn2 = (double)*tcell<T>(I, nv.vn[1], g);
         double h[2] = {0.0, 0.0};
         HE.add(I, h, &nv.E[0][0], nv.cE, nv.nE, g);
         HV.add(I, h, &nv.V[0][0], nv.cV, nv.nV, g);
@@ -903,24 +930,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= ny) break;
-    const long long g = (long long)gy * nx + gx;
+    const Cell g = cell_at<T>(gy * nx + gx);
     const int c = Gm::at(tx, ly);
     const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
     const T E1 = (e1[r] - T(0.5) * (u2 * u2 - u1 * u1)) + g1[r];
     const T E2 = (qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2) +
                  g2[r];
-    tplane<T>(I, a.out_du)[g] = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
+    *tcell<T>(I, a.out_du, g) = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
     if (a.out_e[0] != kNoSlot) {
-      tplane<T>(I, a.out_e[0])[g] = E1;
-      tplane<T>(I, a.out_e[1])[g] = E2;
+      *tcell<T>(I, a.out_e[0], g) = E1;
+      *tcell<T>(I, a.out_e[1], g) = E2;
     }
     if (nv.stage > 0) {
       // step 1 of the next stage; its newest history terms are this E and this v
       const double v1 = (double)w1[r], v2 = (double)w2[r];
       const double s1 = a.c_e_next * (double)E1 + a.c_v_next * v1;
       const double s2 = a.c_e_next * (double)E2 + a.c_v_next * v2;
-      tplane<T>(I, nv.out[0])[g] = (T)((rv1[r] - dt * s1) * kinv);
-      tplane<T>(I, nv.out[1])[g] = (T)((rv2[r] - dt * s2) * kinv);
+      *tcell<T>(I, nv.out[0], g) = (T)((rv1[r] - dt * s1) * kinv);
+      *tcell<T>(I, nv.out[1], g) = (T)((rv2[r] - dt * s2) * kinv);
     }
   }
 }
