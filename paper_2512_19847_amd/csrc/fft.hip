@@ -123,6 +123,15 @@ __device__ __forceinline__ void stc(Gp<dv2> p, double2 v) {
   *p = t;
 }
 
+// Global address at a 32-bit byte offset from a wave-uniform base (a plane or the spectrum
+// is at most 512 MiB): the base stays in scalar registers and the offset is the only
+// per-lane address.
+template <typename P>
+__device__ __forceinline__ P at_byte(P base, unsigned b) {
+  using C = __attribute__((address_space(1))) const char *;
+  return (P)((C)base + b);
+}
+
 // LDS layout of the FFT buffers: one padding element after every 8, so the strided
 // writes of the early Stockham passes (stride R Ns elements of 16 bytes) spread over the
 // banks instead of hitting the same few.
@@ -265,8 +274,8 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
       const int o = idx + dn.q(idx) * n;  // row 2p, column x
-      ra[e] = R[o];
-      rb[e] = R[o + n];
+      ra[e] = *at_byte(R, (unsigned)o * 8u);
+      rb[e] = *at_byte(R, (unsigned)(o + n) * 8u);
     }
   }
   tw.store(tws, I.fx);
@@ -293,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
     else  // A = (Z + conj W) / 2, B = (Z - conj W) / 2i: the spectra of rows 2p, 2p + 1
       o = (yl & 1) ? make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x))
                    : make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
-    stc(S + (long long)k * ny + yl, o);
+    stc(at_byte(S, (unsigned)(k * ny + yl) * 16u), o);
   }
 }
 
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   for (int e = 0; e < E; ++e) {
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
-      v[e] = ldc(S + idx);
+      v[e] = ldc(at_byte(S, (unsigned)idx * 16u));
       if constexpr (PRE) {
         const int c = dy.q(idx), y = idx - c * ny;
         ly[e] = gp(I.lam_y)[y];
@@ -404,7 +413,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) stc(S + idx, buf[lp(idx)]);
+    if (idx < cnt) stc(at_byte(S, (unsigned)idx * 16u), buf[lp(idx)]);
   }
 }
 
@@ -434,9 +443,9 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
       const int k = dp.q(idx), p = idx - k * np;
-      const Gp<const dv2> s = S + (long long)k * ny + 2 * p;
-      A[e] = ldc(s);
-      B[e] = ldc(s + 1);
+      const unsigned b = (unsigned)(k * ny + 2 * p) * 16u;
+      A[e] = ldc(at_byte(S, b));
+      B[e] = ldc(at_byte(S, b + 16u));
     }
   }
   tw.store(tws, I.fx);
@@ -465,8 +474,8 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
     if (idx < np * n) {
       const int o = idx + dn.q(idx) * n;
       const double2 z = buf[lp(idx)];
-      T[o] = z.x;
-      T[o + n] = z.y;
+      *at_byte(T, (unsigned)o * 8u) = z.x;
+      *at_byte(T, (unsigned)(o + n) * 8u) = z.y;
     }
   }
 }
