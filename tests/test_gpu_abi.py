@@ -258,3 +258,29 @@ def test_autotune_restores_state():
     sim.close()
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    """APDVM_TUNE_CACHE: the first autotune appends one line keyed by the context's shape;
+    a second context of the same shape reads its choice back (no trials, the file keeps
+    one line) and steps bitwise like the first."""
+    import torch
+
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("APDVM_TUNE_CACHE", str(cache))
+    st = _state()
+    runs = []
+    for _ in range(2):
+        sim = _sim(stream=torch.cuda.Stream())
+        sim.set_graph(True)
+        sim.set_fields(0, *st)
+        choice = sim.autotune(1)
+        overlap = sim.overlap()
+        sim.step(3)
+        runs.append((choice, overlap, sim.get_fields(0)))
+        sim.close()
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and "|" in lines[0], lines
+    assert runs[0][0] == runs[1][0] and runs[0][1] == runs[1][1]
+    for x, y in zip(runs[0][2], runs[1][2]):
+        assert np.array_equal(x, y)
