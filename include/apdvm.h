@@ -185,9 +185,9 @@ apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
 apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
 
 /* Stream structure of a step.  on = 1 (default): per stage, the Helmholtz right-hand
- * side and solve run on the context's second stream while the theta-free part of steps 3
- * and 4 (class 6) runs on the creation stream; the stage-terms launch (class 7) waits for
- * both.  on = 0: every launch on the creation stream, in the same order.  Results are
+ * side and solve (classes 0-3) run on the context's second stream while the theta-free
+ * part of steps 3 and 4 (class 4) and the q part of the stage terms (class 6) run on the
+ * creation stream; the stage-terms launch (class 5) waits for both.  on = 0: every launch on the creation stream, in the same order.  Results are
  * identical either way.  apdvm_autotune picks the faster.  Synchronises both streams
  * when the setting changes. */
 apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
