@@ -187,9 +187,9 @@ apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
 /* Stream structure of a step.  on = 1 (default): per stage, the Helmholtz right-hand
  * side and solve (classes 0-3) run on the context's second stream while the theta-free
  * part of steps 3 and 4 (class 4) and the q part of the stage terms (class 6) run on the
- * creation stream; the stage-terms launch (class 5) waits for both.  on = 0: every launch on the creation stream, in the same order.  Results are
- * identical either way.  apdvm_autotune picks the faster.  Synchronises both streams
- * when the setting changes. */
+ * creation stream; the stage-terms launch (class 5) waits for both.  on = 0: every launch
+ * on the creation stream, in the same order.  Results are identical either way.
+ * apdvm_autotune picks the faster.  Synchronises both streams when the setting changes. */
 apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
 
 /* Current stream structure (1: solve beside steps 3 and 4, 0: one stream).  Host-only. */
