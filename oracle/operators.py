@@ -18,7 +18,10 @@ reading used here:
     reconstruction this is exactly the printed Lax-Friedrichs flux.
   * The dissipation variable w of a flux is the unknown of the equation the flux
     appears in: v1 (x) and v2 (y) for grad q in the v equations; u1 (first
-    component) and u2 (second component) for div B(v) in the u equations.
+    component) and u2 (second component) for div B(v) in the u equations.  Each slot
+    is pinned against its Fourier symbol at tiny amplitude, and the whole step against
+    the amplification matrix G(k) (tests/test_linear_mode.py); the swapped readings
+    make G(k) unstable.
   * Fourth-order central first derivative D, second derivative L, mixed derivative
     D_x D_y.
 Third-order variant (Section 4.1 convergence tables, "third order WENO"): WENO3 of

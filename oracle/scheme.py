@@ -28,7 +28,11 @@ Readings (each listed with its pin in the design notes):
   * Dissipation partner of D_LF.B(v(j)) in step 3: u(j-1) (u(0) := u^n for the first
     solved stage).  The printed flux needs jumps of the unknown u, but u(j) is not
     known when its own flux is formed; using the previous stage keeps step 3
-    explicit.  Parity unpinned beyond self-consistency (convergence tests).
+    explicit.  Pinned by the linear single-mode closed form (tests/test_linear_mode.py):
+    the oracle reproduces the amplification matrix built from the operator symbols
+    and the stage equations to 1e-12, that matrix converges to the paper's continuous
+    moment system, and this reading is stable on every mode where swapping the
+    partners is not.
   * Helmholtz (0,0) mode set to mean(theta^n) (see helmholtz.py).
 """
 

@@ -234,3 +234,14 @@ def test_eps_zero_tau_zero_runs_finite():
     h = 2 * np.pi / n
     out = scheme.run(st, scheme.Params(0.0, 0.0, 0.02), tb.preset("paper2"), Production(h, h), 5)
     assert all(np.all(np.isfinite(f)) for f in out)
+
+
+@pytest.mark.parametrize("nx,ny,kmax", [(64, 64, 8), (96, 72, 4)])
+def test_random_fields_are_discretely_divergence_free(nx, ny, kmax):
+    """The random initial velocities are the discrete curl of the stream function with
+    the scheme's fourth-order central difference, so the scheme's D0.u vanishes to
+    rounding (well-prepared data, Theorem 3.5), at the requested rms speed."""
+    st = wl.random_divfree(nx, ny, kmax=kmax, rms=0.1, seed=3)
+    ops = Production(2 * np.pi / nx, 2 * np.pi / ny)
+    assert np.max(np.abs(ops.div_c(st[0], st[1]))) < 1e-13
+    assert abs(math.sqrt(np.mean(st[0] ** 2 + st[1] ** 2)) - 0.1) < 1e-14
