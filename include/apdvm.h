@@ -19,11 +19,13 @@
  *    copied in or out; device arrays follow the same layout and are caller-owned.
  *  - Every call returns an apdvm_status.  A call that fails validation changes
  *    nothing.  No entry point throws or aborts.
- *  - Work is enqueued on the stream given at creation.  apdvm_step only enqueues;
- *    the get_* calls synchronise that stream before returning.  Within a step the
- *    library may run part of each stage on a second stream of its own, forked from and
- *    joined back to the creation stream inside the step (see apdvm_set_overlap), so
- *    ordering against the creation stream is as if every launch were on it.
+ *  - Work is enqueued on the stream given at creation.  apdvm_step enqueues (and
+ *    synchronises only when a finite check falls inside the call, see
+ *    apdvm_set_finite_check); the host get_* calls synchronise that stream before
+ *    returning.  Within a step the library may run part of each stage on a second
+ *    stream of its own, forked from and joined back to the creation stream inside the
+ *    step (see apdvm_set_overlap), so ordering against the creation stream is as if
+ *    every launch were on it.
  *  - A context is not thread-safe: calls on one context must not overlap.
  */
 #ifndef APDVM_H
@@ -120,14 +122,21 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws,
 
 /* Initial fields of instance k from host arrays.  v1 and v2 may both be NULL (then
  * v = F(u) = (1/2 (u2^2 - u1^2), u1 u2), local equilibrium); q may be NULL (then 0).
- * Rejects NaN/Inf (APDVM_ERR_NONFINITE).  Resets the step counter of the context
- * only when called for every instance before the next step. */
+ * Rejects NaN/Inf (APDVM_ERR_NONFINITE, nothing changed).  The fields also become the
+ * snapshot of the finite check (apdvm_set_finite_check).  The step counter is not
+ * changed (a checkpoint restore is set_fields for every instance, then apdvm_set_step).
+ * Synchronises the stream. */
 apdvm_status apdvm_set_fields(apdvm_ctx *ctx, int32_t k, const double *u1,
                               const double *u2, const double *theta, const double *v1,
                               const double *v2, const double *q);
 
-/* Same from six device arrays of nx*ny float64 each (no NULLs).  The caller
- * guarantees the values are finite. */
+/* Same from six device arrays of nx*ny float64 each (u1, u2, theta, v1, v2, q; no
+ * NULLs), read on the context's stream: the caller makes their contents complete in
+ * that stream's order (produced on it, or an event it waits on).  The values are checked
+ * on the device first (APDVM_ERR_NONFINITE if any is NaN or Inf, nothing changed), in
+ * the same pass that gives the mean of theta and max |u| for the dt rule; in the
+ * FP32-split form the rounding to float runs on the device.  Synchronises the stream
+ * before returning, so the arrays may be reused afterwards. */
 apdvm_status apdvm_set_fields_device(apdvm_ctx *ctx, int32_t k, const double *const dev[6]);
 
 /* Initial fields of instance k from populations F[6][ny][nx] (host, float64), mapped
@@ -140,15 +149,29 @@ apdvm_status apdvm_set_populations(apdvm_ctx *ctx, int32_t k, const double *F);
  * implicit stage: step 1 (fused into the previous stage's terms), then the right-hand
  * side and the Helmholtz solve of step 2 beside the parts of steps 3 and 4 that do not
  * involve theta(i) (q(i), and u(i) short of its dt a_ii D0 theta(i) term), then the
- * completion of u(i) with the stage's reusable terms. */
+ * completion of u(i) with the stage's reusable terms.
+ * After every K-th step (K from apdvm_set_finite_check) the state of every instance is
+ * checked on the device; a state that passes becomes the snapshot.  If any check of the
+ * call fails, the call synchronises, makes the snapshot (the last state that passed, of
+ * every instance) the current state again, sets the step counter back to its step and
+ * returns APDVM_ERR_NONFINITE.  A call containing a check synchronises the stream at its
+ * end, so such calls cannot be captured into a caller's graph (set K = 0 for that). */
 apdvm_status apdvm_step(apdvm_ctx *ctx, int64_t nsteps);
+
+/* Finite check of apdvm_step every `every` steps (counted by the step counter; 0 turns it
+ * off).  Default 64, or the value of the environment variable APDVM_FINITE_EVERY at
+ * apdvm_create.  Cost per check: one read of the six state planes and, when it passes,
+ * one copy of them into the snapshot.  Host-only. */
+apdvm_status apdvm_set_finite_check(apdvm_ctx *ctx, int32_t every);
 
 /* Copy the six fields of instance k to host arrays (any pointer may be NULL to skip
  * that field).  Synchronises the stream. */
 apdvm_status apdvm_get_fields(apdvm_ctx *ctx, int32_t k, double *u1, double *u2,
                               double *theta, double *v1, double *v2, double *q);
 
-/* Same into six device arrays of nx*ny float64 each (enqueued, not synchronised). */
+/* Same into six device arrays of nx*ny float64 each (NULL entries skipped), enqueued on
+ * the context's stream and not synchronised: a consumer on another stream waits for it
+ * (an event recorded on the context's stream after this call). */
 apdvm_status apdvm_get_fields_device(apdvm_ctx *ctx, int32_t k, double *const dev[6]);
 
 /* Physical moments of instance k (host): rho = 1 + 2 eps^2 theta, u, and the pressure
@@ -253,6 +276,22 @@ apdvm_status apdvm_set_tuning(apdvm_ctx *ctx, const int32_t *choice);
 
 /* Release the context (and the workspace if the library allocated it).  NULL ok. */
 void apdvm_destroy(apdvm_ctx *ctx);
+
+/* Batched form (hundreds of independent simulations of uneven sizes and eps / Ma
+ * advanced together).  A context already holds any number of instances, each
+ * with its own grid, eps, tau, dt and FFT plan, and every launch of a step covers all of
+ * them through its work tables; these names are the same calls under the batch
+ * vocabulary (apdvm_batch is the context type). */
+typedef struct apdvm_ctx apdvm_batch;
+apdvm_status apdvm_batch_create(int32_t n, const apdvm_config *cfgs, void *dev_ws,
+                                size_t ws_bytes, void *hip_stream, apdvm_batch **out);
+apdvm_status apdvm_batch_set_fields(apdvm_batch *b, int32_t k, const double *u1,
+                                    const double *u2, const double *theta, const double *v1,
+                                    const double *v2, const double *q);
+apdvm_status apdvm_batch_step(apdvm_batch *b, int64_t nsteps);
+apdvm_status apdvm_batch_get_fields(apdvm_batch *b, int32_t k, double *u1, double *u2,
+                                    double *theta, double *v1, double *v2, double *q);
+void apdvm_batch_destroy(apdvm_batch *b);
 
 /* Static text for a status code. */
 const char *apdvm_status_string(apdvm_status s);

@@ -108,6 +108,13 @@ def _declare(L):
     L.apdvm_traffic.argtypes = [P, c_int32, POINTER(c_double), POINTER(c_int32)]
     L.apdvm_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
     L.apdvm_set_tuning.argtypes = [P, POINTER(c_int32)]
+    L.apdvm_set_finite_check.argtypes = [P, c_int32]
+    L.apdvm_batch_create.argtypes = [c_int32, POINTER(Config), P, c_size_t, P, POINTER(P)]
+    L.apdvm_batch_set_fields.argtypes = [P, c_int32] + [P] * 6
+    L.apdvm_batch_step.argtypes = [P, c_int64]
+    L.apdvm_batch_get_fields.argtypes = [P, c_int32] + [P] * 6
+    L.apdvm_batch_destroy.argtypes = [P]
+    L.apdvm_batch_destroy.restype = None
     L.apdvm_destroy.argtypes = [P]
     L.apdvm_destroy.restype = None
     for name in ("apdvm_workspace_bytes", "apdvm_create", "apdvm_set_fields",
@@ -117,7 +124,9 @@ def _declare(L):
                  "apdvm_diagnostics", "apdvm_launches_per_step", "apdvm_set_graph",
                  "apdvm_set_overlap", "apdvm_get_overlap",
                  "apdvm_timing_enable", "apdvm_timing_read", "apdvm_timing_stride", "apdvm_traffic",
-                 "apdvm_autotune", "apdvm_set_tuning"):
+                 "apdvm_autotune", "apdvm_set_tuning", "apdvm_set_finite_check",
+                 "apdvm_batch_create", "apdvm_batch_set_fields", "apdvm_batch_step",
+                 "apdvm_batch_get_fields"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -213,8 +222,11 @@ class Simulation:
         self.n = len(cfgs)
         self.shapes = [(c.ny, c.nx) for c in cfgs]
         nbytes = workspace_bytes(cfgs)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # allocated on the stream the library uses it on, so the caching allocator
+        # orders its reuse after that stream's work
+        with torch.cuda.stream(self.stream):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         arr = (Config * self.n)(*cfgs)
         ctx = c_void_p()
         _check(lib().apdvm_create(self.n, arr, c_void_p(self.workspace.data_ptr()), nbytes,
@@ -243,10 +255,14 @@ class Simulation:
         _check(lib().apdvm_set_fields(self.ctx, k, *ptrs), "set_fields")
 
     def set_fields_device(self, k, tensors):
+        """Six float64 device tensors (u1, u2, theta, v1, v2, q).  The library reads them
+        on its stream, after the work already queued on the caller's current stream
+        (which produced them); the call returns once they have been read."""
         t = [x.contiguous() for x in tensors]
         for x in t:
             if x.dtype != self.torch.float64 or tuple(x.shape) != self.shapes[k]:
                 raise ValueError("device fields must be float64 with the instance shape")
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
         arr = (c_void_p * 6)(*[x.data_ptr() for x in t])
         _check(lib().apdvm_set_fields_device(self.ctx, k, arr), "set_fields_device")
 
@@ -267,8 +283,18 @@ class Simulation:
         return tuple(out)
 
     def get_fields_device(self, k, tensors):
-        arr = (c_void_p * 6)(*[x.data_ptr() for x in tensors])
+        """Write the fields into six float64 device tensors (None skips one).  The copies
+        run on the library's stream after earlier work of the caller's current stream, and
+        the caller's current stream waits for them before its next work."""
+        for x in tensors:
+            if x is not None and (x.dtype != self.torch.float64 or tuple(x.shape) != self.shapes[k]
+                                  or not x.is_contiguous()):
+                raise ValueError("device fields must be contiguous float64 with the instance shape")
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        arr = (c_void_p * 6)(*[x.data_ptr() if x is not None else None for x in tensors])
         _check(lib().apdvm_get_fields_device(self.ctx, k, arr), "get_fields_device")
+        cur.wait_stream(self.stream)
 
     def get_moments(self, k=0):
         out = [np.empty(self.shapes[k]) for _ in range(4)]
@@ -290,6 +316,10 @@ class Simulation:
 
     def set_step(self, step):
         _check(lib().apdvm_set_step(self.ctx, int(step)), "set_step")
+
+    def set_finite_check(self, every):
+        """Check the state for NaN / Inf every `every` steps inside step() (0: off)."""
+        _check(lib().apdvm_set_finite_check(self.ctx, int(every)), "set_finite_check")
 
     def diagnostics(self, k=0):
         out = np.empty(8)

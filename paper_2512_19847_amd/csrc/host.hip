@@ -46,10 +46,21 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *, const W
                              const Work *, int, const ArgsSolve &, hipStream_t, const Ev &);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
                               int, int, double *, int, hipStream_t);
+hipError_t launch_field_stats(int split, const void *const f[6], long long n, double *partials,
+                              int nblocks, hipStream_t st);
+hipError_t launch_convert(void *dst, const void *src, long long n, int to_float, hipStream_t st);
+hipError_t launch_state_finite(int split, const Inst *, const Work *, int, int, const int *slots6,
+                               unsigned *flag, hipStream_t);
+hipError_t launch_snapshot(int split, const Inst *, const Work *, int, int, const int *src6,
+                           const int *dst6, const unsigned *flag, long long *ck_step,
+                           long long step, hipStream_t);
 
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kStatBlocks = 512;    // workgroups of the input-field statistics kernel
+constexpr size_t kFlagBytes = 256;  // finite flag (unsigned) at 0, snapshot step (int64) at 8
+constexpr int kDefaultFiniteEvery = 64;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // ----------------------------------------------------------- validation helpers
@@ -179,6 +190,7 @@ struct Layout {
   int s;
   int st[2][5];  // state sets: u1, u2, v1, v2, q
   int th[2];     // float64: theta of each state set
+  int ck[5], thck;  // snapshot of the last state that passed the finite check
   int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
   int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
   int ddb, G[2];
@@ -196,6 +208,8 @@ Layout make_layout(int s) {
     for (int f = 0; f < 5; ++f) L.st[p][f] = t++;
   L.th[0] = d++;
   L.th[1] = d++;
+  for (int f = 0; f < 5; ++f) L.ck[f] = t++;
+  L.thck = d++;
   for (int j = 0; j <= s - 2; ++j) {
     L.E[j][0] = t++;
     L.E[j][1] = t++;
@@ -334,6 +348,8 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
   b += align_up(ntile8 * sizeof(Work)) + align_up(ntile16 * sizeof(Work)) + align_up(nrow * sizeof(Work)) +
        align_up(ncol * sizeof(Work));
   b += align_up(8 * sizeof(double) * 1024);  // diagnostics partials
+  b += align_up(3 * sizeof(double) * kStatBlocks);  // input-field statistics partials
+  b += align_up(kFlagBytes);                          // finite flag and snapshot step
   return b;
 }
 
@@ -415,6 +431,11 @@ struct apdvm_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
+  // Finite check every finite_every steps (0: off): device flag, step of the snapshot.
+  double *d_stats = nullptr;
+  unsigned *d_flag = nullptr;
+  long long *d_ck_step = nullptr;
+  int finite_every = 0;
 };
 
 namespace {
@@ -756,12 +777,6 @@ bool all_finite(const double *p, size_t n) {
   return true;
 }
 
-long double kahan_mean(const double *p, size_t n) {
-  long double s = 0.0L;
-  for (size_t i = 0; i < n; ++i) s += p[i];
-  return s / (long double)n;
-}
-
 template <typename T>
 apdvm_status put_plane(apdvm_ctx *c, int k, int slot, const double *src, bool dev_src) {
   const Inst &I = c->inst[k];
@@ -772,18 +787,8 @@ apdvm_status put_plane(apdvm_ctx *c, int k, int slot, const double *src, bool de
                                      dev_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                      c->stream));
   }
-  if (dev_src) {
-    std::vector<double> tmp(n);
-    if (hipMemcpyAsync(tmp.data(), src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-      return APDVM_ERR_HIP;
-    std::vector<T> t(n);
-    for (size_t i = 0; i < n; ++i) t[i] = (T)tmp[i];
-    if (hipMemcpyAsync(dst, t.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream) != hipSuccess)
-      return APDVM_ERR_HIP;
-    return hip_status(hipStreamSynchronize(c->stream));
-  }
+  if (dev_src)  // rounded to float on the device, in stream order
+    return hip_status(launch_convert(dst, src, (long long)n, 1, c->stream));
   std::vector<T> t(n);
   for (size_t i = 0; i < n; ++i) t[i] = (T)src[i];
   if (hipMemcpyAsync(dst, t.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream) != hipSuccess)
@@ -801,18 +806,12 @@ apdvm_status get_plane(apdvm_ctx *c, int k, int slot, double *dst, bool dev_dst)
                                      dev_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                      c->stream));
   }
+  if (dev_dst)  // widened to float64 on the device, in stream order
+    return hip_status(launch_convert(dst, src, (long long)n, 0, c->stream));
   std::vector<T> t(n);
   if (hipMemcpyAsync(t.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return APDVM_ERR_HIP;
-  if (dev_dst) {
-    std::vector<double> d(n);
-    for (size_t i = 0; i < n; ++i) d[i] = (double)t[i];
-    if (hipMemcpyAsync(dst, d.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
-        hipSuccess)
-      return APDVM_ERR_HIP;
-    return hip_status(hipStreamSynchronize(c->stream));
-  }
   for (size_t i = 0; i < n; ++i) dst[i] = (double)t[i];
   return APDVM_OK;
 }
@@ -855,14 +854,84 @@ apdvm_status get_state(apdvm_ctx *c, int k, double *const f[6], bool dev) {
   return APDVM_OK;
 }
 
-// After new fields for instance k: theta mean, dt derivation, parameter upload.
-apdvm_status after_fields(apdvm_ctx *c, int k, const double *theta_host, const double *u1,
-                          const double *u2) {
+// The six state slots of state set P (u1, u2, v1, v2, q, then theta), or of the snapshot
+// (P = -1).
+void state_slots(const apdvm_ctx *c, int P, int *out6) {
+  const Layout &L = c->L;
+  for (int f = 0; f < 5; ++f) out6[f] = P < 0 ? L.ck[f] : L.st[P][f];
+  out6[5] = P < 0 ? L.thck : L.th[P];
+}
+
+// Copy the state of instance k between state set P and the snapshot (to_snapshot: P ->
+// snapshot, else snapshot -> P), enqueued on the stream.
+apdvm_status copy_snapshot(apdvm_ctx *c, int k, int P, bool to_snapshot) {
+  const Inst &I = c->inst[k];
+  const size_t tb = (size_t)I.plane * (c->split ? sizeof(float) : sizeof(double));
+  const size_t db = (size_t)I.plane * sizeof(double);
+  int a[6], b[6];
+  state_slots(c, P, a);
+  state_slots(c, -1, b);
+  char *tbase = static_cast<char *>(I.tbase);
+  char *dbase = reinterpret_cast<char *>(I.dbase);
+  for (int f = 0; f < 6; ++f) {
+    char *base = f < 5 ? tbase : dbase;
+    const size_t pb = f < 5 ? tb : db;
+    char *x = base + (size_t)a[f] * pb, *y = base + (size_t)b[f] * pb;
+    if (hipMemcpyAsync(to_snapshot ? y : x, to_snapshot ? x : y, pb, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess)
+      return APDVM_ERR_HIP;
+  }
+  return APDVM_OK;
+}
+
+// Statistics of six device fields of n values (u, v, q float when split, theta float64):
+// mean of theta, max |u|, all finite.
+apdvm_status device_field_stats(apdvm_ctx *c, bool split, const void *const f[6], size_t n,
+                                double *mean, double *umax, bool *finite) {
+  std::vector<double> part(3 * (size_t)kStatBlocks);
+  if (launch_field_stats(split ? 1 : 0, f, (long long)n, c->d_stats, kStatBlocks, c->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(part.data(), c->d_stats, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  long double s = 0.0L;
+  double um = 0.0, fin = 1.0;
+  for (int b = 0; b < kStatBlocks; ++b) {
+    s += part[3 * b];
+    um = std::fmax(um, part[3 * b + 1]);
+    fin = std::fmin(fin, part[3 * b + 2]);
+  }
+  *mean = (double)(s / (long double)n);
+  *umax = um;
+  *finite = fin == 1.0 && std::isfinite((double)s);
+  return APDVM_OK;
+}
+
+// After new fields for instance k (um: max |u| of the given float64 fields): the mean of
+// theta from the stored state (one device reduction, whichever entry point brought the
+// fields), dt derivation, parameter upload, and the snapshot of the finite check (the new
+// fields are known to be finite).
+apdvm_status after_fields(apdvm_ctx *c, int k, double um) {
   Inst &I = c->inst[k];
-  const size_t n = (size_t)I.plane;
-  I.theta_mean = (double)kahan_mean(theta_host, n);
-  double um = 0.0;
-  for (size_t i = 0; i < n; ++i) um = std::fmax(um, std::sqrt(u1[i] * u1[i] + u2[i] * u2[i]));
+  {
+    int sl[6];
+    state_slots(c, c->parity, sl);
+    const size_t n = (size_t)I.plane, tb = c->split ? sizeof(float) : sizeof(double);
+    const void *f[6];
+    for (int m = 0; m < 6; ++m)
+      f[m] = m == 5 ? static_cast<const void *>(I.dbase + (size_t)sl[5] * n)
+                    : static_cast<const void *>(static_cast<const char *>(I.tbase) +
+                                                (size_t)sl[m] * n * tb);
+    // state_slots order is u1, u2, v1, v2, q, theta; the statistics take u1, u2, theta,
+    // v1, v2, q
+    const void *g[6] = {f[0], f[1], f[5], f[2], f[3], f[4]};
+    double mean = 0.0, ignored = 0.0;
+    bool finite = false;
+    const apdvm_status st = device_field_stats(c, c->split, g, n, &mean, &ignored, &finite);
+    if (st != APDVM_OK) return st;
+    I.theta_mean = mean;
+  }
   c->umax[k] = um;
   const apdvm_config &cf = c->cfg[k];
   if (!(cf.dt > 0.0)) {
@@ -877,7 +946,15 @@ apdvm_status after_fields(apdvm_ctx *c, int k, const double *theta_host, const d
   }
   c->has_fields[k] = 1;
   c->terms_ready = false;
-  return upload_inst(c, k);
+  apdvm_status st = upload_inst(c, k);
+  if (st != APDVM_OK) return st;
+  st = copy_snapshot(c, k, c->parity, true);
+  if (st != APDVM_OK) return st;
+  const long long step = c->step;
+  return hip_status(hipMemcpyAsync(c->d_ck_step, &step, sizeof(step), hipMemcpyHostToDevice,
+                                   c->stream)) == APDVM_OK
+             ? hip_status(hipStreamSynchronize(c->stream))
+             : APDVM_ERR_HIP;
 }
 
 }  // namespace
@@ -1054,6 +1131,17 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   p += align_up(cols.size() * sizeof(Work));
   c->d_partials = reinterpret_cast<double *>(p);
   p += align_up(8 * sizeof(double) * 1024);
+  c->d_stats = reinterpret_cast<double *>(p);
+  p += align_up(3 * sizeof(double) * kStatBlocks);
+  c->d_flag = reinterpret_cast<unsigned *>(p);
+  c->d_ck_step = reinterpret_cast<long long *>(p + 8);
+  p += align_up(kFlagBytes);
+  c->finite_every = kDefaultFiniteEvery;
+  if (const char *e = std::getenv("APDVM_FINITE_EVERY")) {
+    char *end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (end != e && v >= 0 && v <= (1L << 30)) c->finite_every = (int)v;
+  }
 
   bool ok = hipMemcpyAsync(c->d_tiles[1], c->tiles.data(), c->tiles.size() * sizeof(Work),
                            hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -1068,6 +1156,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   for (auto &u : uploads)
     ok = ok && hipMemcpyAsync(u.dst, u.data.data(), u.data.size(), hipMemcpyHostToDevice,
                               c->stream) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->d_flag, 0, kFlagBytes, c->stream) == hipSuccess;
   ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
   if (!ok) {
     apdvm_destroy(c);
@@ -1104,32 +1193,29 @@ apdvm_status apdvm_set_fields(apdvm_ctx *c, int32_t k, const double *u1, const d
   const double *f[6] = {u1, u2, theta, v1, v2, q};
   apdvm_status st = put_state(c, k, f, false);
   if (st != APDVM_OK) return st;
-  st = after_fields(c, k, theta, u1, u2);
-  if (st != APDVM_OK) return st;
-  // the copies read caller-owned and temporary host arrays: finish them here
-  return hip_status(hipStreamSynchronize(c->stream));
+  double um = 0.0;
+  for (size_t i = 0; i < n; ++i) um = std::fmax(um, std::sqrt(u1[i] * u1[i] + u2[i] * u2[i]));
+  // after_fields synchronises: the copies read caller-owned and temporary host arrays
+  return after_fields(c, k, um);
 }
 
 apdvm_status apdvm_set_fields_device(apdvm_ctx *c, int32_t k, const double *const dev[6]) {
   if (!c || k < 0 || k >= c->n || !dev) return APDVM_ERR_ARG;
   for (int m = 0; m < 6; ++m)
     if (!dev[m]) return APDVM_ERR_ARG;
-  apdvm_status st = put_state(c, k, dev, true);
-  if (st != APDVM_OK) return st;
-  // the mean of theta and the dt rule need host copies of theta and u
+  if (hipSetDevice(c->device) != hipSuccess) return APDVM_ERR_HIP;
+  // validate on the device before anything of the context changes: every value finite;
+  // the same pass gives the mean of theta and max |u| for the dt rule
   const size_t n = (size_t)c->inst[k].plane;
-  std::vector<double> th(n), u1(n), u2(n);
-  if (hipMemcpyAsync(th.data(), dev[2], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipMemcpyAsync(u1.data(), dev[0], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipMemcpyAsync(u2.data(), dev[1], n * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
-    return APDVM_ERR_HIP;
-  st = after_fields(c, k, th.data(), u1.data(), u2.data());
+  double mean = 0.0, um = 0.0;
+  bool finite = false;
+  const void *f[6] = {dev[0], dev[1], dev[2], dev[3], dev[4], dev[5]};
+  apdvm_status st = device_field_stats(c, false, f, n, &mean, &um, &finite);
   if (st != APDVM_OK) return st;
-  return hip_status(hipStreamSynchronize(c->stream));
+  if (!finite) return APDVM_ERR_NONFINITE;
+  st = put_state(c, k, dev, true);
+  if (st != APDVM_OK) return st;
+  return after_fields(c, k, um);  // synchronises
 }
 
 apdvm_status apdvm_set_populations(apdvm_ctx *c, int32_t k, const double *F) {
@@ -1160,16 +1246,67 @@ apdvm_status apdvm_set_populations(apdvm_ctx *c, int32_t k, const double *F) {
   return apdvm_set_fields(c, k, &f[0], &f[n], &f[2 * n], &f[3 * n], &f[4 * n], &f[5 * n]);
 }
 
+// Finite check of the current state of every instance, then the snapshot of it if the
+// check (and every earlier one) passed.
+static apdvm_status enqueue_check(apdvm_ctx *c) {
+  int cur[6], ck[6];
+  state_slots(c, c->parity, cur);
+  state_slots(c, -1, ck);
+  if (launch_state_finite(c->split ? 1 : 0, c->d_inst, c->d_tiles[1], c->ntiles[1], kTileRows[1],
+                          cur, c->d_flag, c->stream) != hipSuccess ||
+      launch_snapshot(c->split ? 1 : 0, c->d_inst, c->d_tiles[1], c->ntiles[1], kTileRows[1], cur,
+                      ck, c->d_flag, c->d_ck_step, c->step, c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  return APDVM_OK;
+}
+
+// Read the flag of the checks enqueued so far (synchronises).  On a failed check: the
+// snapshot (the last state that passed) becomes the current state, the step counter
+// returns to its step, the flag is cleared, and APDVM_ERR_NONFINITE is returned.
+static apdvm_status collect_checks(apdvm_ctx *c) {
+  unsigned flag = 0;
+  if (hipMemcpyAsync(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  if (!flag) return APDVM_OK;
+  long long step = 0;
+  if (hipMemcpyAsync(&step, c->d_ck_step, sizeof(step), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return APDVM_ERR_HIP;
+  for (int k = 0; k < c->n; ++k)
+    if (copy_snapshot(c, k, c->parity, false) != APDVM_OK) return APDVM_ERR_HIP;
+  const unsigned zero = 0;
+  if (hipMemcpyAsync(c->d_flag, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
+  c->step = step;
+  c->terms_ready = false;
+  return APDVM_ERR_NONFINITE;
+}
+
 apdvm_status apdvm_step(apdvm_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return APDVM_ERR_ARG;
   for (int k = 0; k < c->n; ++k)
     if (!c->has_fields[k]) return APDVM_ERR_STATE;
   if (hipSetDevice(c->device) != hipSuccess) return APDVM_ERR_HIP;
+  bool checked = false;
   for (int64_t t = 0; t < nsteps; ++t) {
     const apdvm_status st = c->split ? enqueue_step<float>(c) : enqueue_step<double>(c);
     if (st != APDVM_OK) return st;
     ++c->step;
+    if (c->finite_every > 0 && c->step % c->finite_every == 0) {
+      if (enqueue_check(c) != APDVM_OK) return APDVM_ERR_HIP;
+      checked = true;
+    }
   }
+  return checked ? collect_checks(c) : APDVM_OK;
+}
+
+apdvm_status apdvm_set_finite_check(apdvm_ctx *c, int32_t every) {
+  if (!c || every < 0) return APDVM_ERR_ARG;
+  c->finite_every = every;
   return APDVM_OK;
 }
 
@@ -1442,6 +1579,8 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     const int64_t step0 = c->step;
     const bool graph = c->use_graph;
     const int stride = c->timed_stride;
+    const int every = c->finite_every;
+    c->finite_every = 0;  // the trial steps are not part of the run
     c->use_graph = false;
     c->timed_stride = 1;
     bool ok = copy_state(true);
@@ -1505,6 +1644,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     c->step = step0;
     c->use_graph = graph;
     c->timed_stride = stride;
+    c->finite_every = every;
     if (!ok) return APDVM_ERR_HIP;
     if (cache) {
       std::ofstream out(cache, std::ios::app);
@@ -1536,6 +1676,26 @@ apdvm_status apdvm_set_tuning(apdvm_ctx *c, const int32_t *choice) {
   drop_graphs(c);
   return APDVM_OK;
 }
+
+apdvm_status apdvm_batch_create(int32_t n, const apdvm_config *cfgs, void *dev_ws,
+                                size_t ws_bytes, void *hip_stream, apdvm_batch **out) {
+  return apdvm_create(n, cfgs, dev_ws, ws_bytes, hip_stream, out);
+}
+
+apdvm_status apdvm_batch_set_fields(apdvm_batch *b, int32_t k, const double *u1,
+                                    const double *u2, const double *theta, const double *v1,
+                                    const double *v2, const double *q) {
+  return apdvm_set_fields(b, k, u1, u2, theta, v1, v2, q);
+}
+
+apdvm_status apdvm_batch_step(apdvm_batch *b, int64_t nsteps) { return apdvm_step(b, nsteps); }
+
+apdvm_status apdvm_batch_get_fields(apdvm_batch *b, int32_t k, double *u1, double *u2,
+                                    double *theta, double *v1, double *v2, double *q) {
+  return apdvm_get_fields(b, k, u1, u2, theta, v1, v2, q);
+}
+
+void apdvm_batch_destroy(apdvm_batch *b) { apdvm_destroy(b); }
 
 void apdvm_destroy(apdvm_ctx *c) {
   if (!c) return;
