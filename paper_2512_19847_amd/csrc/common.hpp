@@ -122,12 +122,18 @@ struct ArgsV {
 // R = -sigma theta^n + 1/(dt a_ii^2) sum_j cD_j D0.u(j) + 1/(dt a_ii) D0.u^n
 //     - D0^2:B(v(i)) - 1/a_ii sum_j cL_j Ltheta(j),
 // with Ltheta(j) = D0^2:B(v(j)) + D_Delta theta(j).  Also stores D0^2:B(v(i)).
+// In the FP32-split form the velocity of stage j is u^n + du(j) (u^n float64, the stage
+// increment du(j) float), the D slots hold D0.du(j) and du0 is the float64 D0.u^n, so
+// the u^n part enters once with the coefficient 1/(dt a_ii) + sum_a/(dt a_ii^2),
+// sum_a = sum_j cD_j.
 struct ArgsR {
   int stage;
   double aii;
   int v[2];       // v(i), read with a halo of 2 (corners included)
   int thn;        // theta^n (float64 slot)
-  int du0;        // D0.u^n
+  int du0;        // D0.u^n (transport slot; float64 slot when du0_dbl)
+  int du0_dbl;
+  double sum_a;
   int nD, D[kMaxStages];
   double cD[kMaxStages];
   int nL, L[kMaxStages];
@@ -140,6 +146,7 @@ struct ArgsR {
 // producing when this runs:
 // hu = D_W.B(v(i))[dissipation on u(i-1)]
 // u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii hu            (formed in float64)
+// (with un[0] == kNoSlot, the FP32-split form, the increment du*(i) = u*(i) - u^n)
 // Hq = (tau/2) D0_W.v(i)
 // q(i) = [te2 q^n - dt a_ii Hq - dt sum_j cG_j Gq(j)] kinv,   Gq(j) = Hq(j) + q(j)
 // The stage-terms launch of the stage completes u(i) = u*(i) - dt a_ii D0 theta(i) and
@@ -169,6 +176,11 @@ struct ArgsG {
 
 // Completion of a stage and its terms that later stages reuse:
 // u(i) = u*(i) - dt a_ii D0 theta(i), Hu(i) = hu + D0 theta(i) (in place),
+// (FP32-split form: us holds the increment du*(i); du(i) = du*(i) - dt a_ii D0 theta(i)
+// rounded to float, u(i) = u^n + du(i) from the base u[] (float copy of u^n) or, in the
+// last stage, ub (float64 u^n) with the new float64 state written to out_ud and its
+// float copy to out_u; out_du receives D0.du(i), or in the last stage du0_out receives
+// the float64 D0.u^{n+1} = du0_in + D0.du(s)),
 // E = (tau/4) D0_W.B(u) + G - F(u) with G from ArgsG, D0.u,
 // Ltheta = D0^2:B(v) + D_Delta theta.  With us[0] == kNoSlot (the terms of a state set)
 // u is read from u[] and nothing of theta is used.  The same launch performs step 1 of
@@ -185,8 +197,21 @@ struct ArgsE {
   int hu[2];          // hu in, Hu out, or kNoSlot (with us)
   int ddb;            // D0^2:B(v) of this stage (only when out_lt != kNoSlot)
   int out_e[2];       // kNoSlot when only the fused next step reads E
-  int out_du, out_lt; // out_lt only with us
+  int out_du, out_lt; // out_lt only with us; out_du may be kNoSlot
   double c_e_next, c_v_next;
+  int ub[2];          // split form, last stage: float64 u^n (halo 3), else kNoSlot
+  int out_ud[2];      // split form, last stage: float64 u^{n+1}
+  int du0_in, du0_out;  // split form, last stage: float64 D0.u^n and D0.u^{n+1}
+};
+
+// The planes that hold one state set (or the snapshot of the finite check): five
+// transport slots u1, u2, v1, v2, q (in the FP32-split form u1, u2 are the float copies
+// of the velocity) and nd float64 slots: theta, then in the split form the float64
+// velocity u1, u2.
+struct StateSet {
+  int t[5];
+  int nd;
+  int d[3];
 };
 
 // Helmholtz solve: R (float64 slot) -> theta (float64 slot), spectrum in slot spec

@@ -49,11 +49,12 @@ hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, in
 hipError_t launch_field_stats(int split, const void *const f[6], long long n, double *partials,
                               int nblocks, hipStream_t st);
 hipError_t launch_convert(void *dst, const void *src, long long n, int to_float, hipStream_t st);
-hipError_t launch_state_finite(int split, const Inst *, const Work *, int, int, const int *slots6,
+hipError_t launch_state_finite(int split, const Inst *, const Work *, int, int, const StateSet &,
                                unsigned *flag, hipStream_t);
-hipError_t launch_snapshot(int split, const Inst *, const Work *, int, int, const int *src6,
-                           const int *dst6, const unsigned *flag, long long *ck_step,
+hipError_t launch_snapshot(int split, const Inst *, const Work *, int, int, const StateSet &,
+                           const StateSet &, const unsigned *flag, long long *ck_step,
                            long long step, hipStream_t);
+hipError_t launch_div_u(int co, const Inst *, const Work *, int, int, int, int, hipStream_t);
 
 namespace {
 
@@ -191,6 +192,9 @@ struct Layout {
   int st[2][5];  // state sets: u1, u2, v1, v2, q
   int th[2];     // float64: theta of each state set
   int ck[5], thck;  // snapshot of the last state that passed the finite check
+  // FP32-split form only (float64 arena): the velocity of each state set, D0.u of each
+  // state set, and the velocity of the snapshot
+  int ud[2][2], du0[2], ckud[2];
   int E[kMaxStages][2], V[kMaxStages][2], Du[kMaxStages], Lt[kMaxStages];
   int Hu[kMaxStages][2], Gq[kMaxStages], U[kMaxStages][2], Q[kMaxStages];
   int ddb, G[2];
@@ -199,7 +203,7 @@ struct Layout {
   int ntrans, ndbl;
 };
 
-Layout make_layout(int s) {
+Layout make_layout(int s, bool split) {
   Layout L;
   std::memset(&L, 0xff, sizeof(L));  // every slot starts as kNoSlot (-1)
   L.s = s;
@@ -210,6 +214,15 @@ Layout make_layout(int s) {
   L.th[1] = d++;
   for (int f = 0; f < 5; ++f) L.ck[f] = t++;
   L.thck = d++;
+  if (split) {
+    for (int p = 0; p < 2; ++p) {
+      L.ud[p][0] = d++;
+      L.ud[p][1] = d++;
+      L.du0[p] = d++;
+    }
+    L.ckud[0] = d++;
+    L.ckud[1] = d++;
+  }
   for (int j = 0; j <= s - 2; ++j) {
     L.E[j][0] = t++;
     L.E[j][1] = t++;
@@ -332,8 +345,8 @@ size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
 }
 
 size_t workspace_bytes(int n, const apdvm_config *cfgs) {
-  const Layout L = make_layout(internal_stages(cfgs[0]));
   const bool split = cfgs[0].precision == APDVM_FP32_SPLIT;
+  const Layout L = make_layout(internal_stages(cfgs[0]), split);
   const size_t tsize = split ? sizeof(float) : sizeof(double);
   size_t b = align_up(n * sizeof(Inst));
   const int rv = row_form(n, cfgs), cv = col_form(n, cfgs);
@@ -359,7 +372,8 @@ size_t workspace_bytes(int n, const apdvm_config *cfgs) {
 // plane it must read and write, counted once).
 enum LaunchClass {
   kHelmRhs = 0, kRowsFwd = 1, kCols = 2, kRowsInv = 3, kUpdateUQ = 4, kStageTerms = 5,
-  kGradQ = 6, kNumClasses = 7
+  kGradQ = 6, kNumClasses = 7,
+  kDivU = 8  // float64 D0.u of a state set (FP32-split form, after new fields only)
 };
 // Stencil classes with a tuned launch shape, in the order of the tuning array.
 constexpr int kNumTuned = 4;
@@ -373,6 +387,7 @@ enum SyncKind { kNoSync = 0, kFork = 1, kJoin = 2 };
 struct Launch {
   int cls;
   int sync;   // SyncKind of a kSync entry
+  int du[3];  // kDivU: float64 slots u1, u2 in, D0.u out
   bool side;  // runs on the solve stream (when the two streams overlap)
   ArgsV v;  // step 1 of the next stage, fused into a stage-terms launch
   ArgsR r;
@@ -529,10 +544,19 @@ Launch grad_q_launch(const apdvm_ctx *c, int q, int v1, int v2) {
   return l;
 }
 
-// Stage-terms launches for the state set P itself (stage 0), used after new fields.
+// Stage-terms launches for the state set P itself (stage 0), used after new fields.  In
+// the FP32-split form the float64 D0.u^n comes first (k_div_u); the stage-terms launch
+// then forms E from the float copy of u^n.
 std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const double pt = c->cells * (c->split ? 4.0 : 8.0);
+  std::vector<Launch> out;
+  if (c->split) {
+    Launch d{};
+    d.cls = kDivU;
+    d.du[0] = L.ud[P][0]; d.du[1] = L.ud[P][1]; d.du[2] = L.du0[P];
+    out.push_back(d);
+  }
   Launch l{};
   l.cls = kStageTerms;
   ArgsE &a = l.e;
@@ -543,11 +567,19 @@ std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
   a.out_u[0] = a.out_u[1] = a.hu[0] = a.hu[1] = kNoSlot;
   a.out_e[0] = e_stored(c, 0) ? L.E[0][0] : kNoSlot;
   a.out_e[1] = e_stored(c, 0) ? L.E[0][1] : kNoSlot;
-  a.out_du = L.Du[0];
+  a.out_du = c->split ? kNoSlot : L.Du[0];
   a.out_lt = kNoSlot;
+  a.ub[0] = a.ub[1] = a.out_ud[0] = a.out_ud[1] = a.du0_in = a.du0_out = kNoSlot;
+  if (c->split) {  // E of the state from its float64 velocity
+    a.ub[0] = L.ud[P][0];
+    a.ub[1] = L.ud[P][1];
+  }
   l.bytes = (2 + 2 + 2 + 1 + (e_stored(c, 0) ? 2 : 0)) * pt;  // u, G, v in; D0.u, E out
+  if (c->split) l.bytes += 2 * (c->cells * 8.0) - 3 * pt;     // float64 u in, no D0.u out
   fill_relax(c, 1, P, l.v, a, pt, l.bytes);
-  return {grad_q_launch(c, L.st[P][4], L.st[P][2], L.st[P][3]), l};
+  out.push_back(grad_q_launch(c, L.st[P][4], L.st[P][2], L.st[P][3]));
+  out.push_back(l);
+  return out;
 }
 
 // Launch list of one step starting from state set P.  Per stage: the right-hand side and
@@ -579,15 +611,21 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     l.cls = kHelmRhs;
     l.side = true;
     ArgsR &ar = l.r;
-    ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P]; ar.du0 = L.Du[0];
+    ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P];
+    // FP32-split: float64 D0.u^n of this state set; the D slots hold D0 of the increments
+    ar.du0 = c->split ? L.du0[P] : L.Du[0];
+    ar.du0_dbl = c->split ? 1 : 0;
+    ar.sum_a = 0.0;
     for (int j = 1; j < i; ++j) {
       if (c->A[i][j] != 0.0) {
         ar.D[ar.nD] = L.Du[j]; ar.cD[ar.nD++] = c->A[i][j];
         ar.L[ar.nL] = L.Lt[j]; ar.cL[ar.nL++] = c->A[i][j];
+        ar.sum_a += c->A[i][j];
       }
     }
     ar.out_r = L.R; ar.out_ddb = L.ddb;
-    l.bytes = (2 + 1 + ar.nD + ar.nL + 1) * pt + 2 * pd;
+    // v in (2), D0^2:B out (1), histories, D0.u^n (transport or float64); theta^n in, R out
+    l.bytes = (2 + ar.nD + ar.nL + 1) * pt + (c->split ? pd : pt) + 2 * pd;
     plan.push_back(l);
     // step 2 solve: three kernels, each one read and one write of a float64 plane
     // (the spectrum holds nx/2 complex columns of ny values)
@@ -610,7 +648,10 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     au.stage = i; au.aii = aii; au.v[0] = v1; au.v[1] = v2;
     au.partner[0] = i == 1 ? L.st[P][0] : L.U[i - 1][0];
     au.partner[1] = i == 1 ? L.st[P][1] : L.U[i - 1][1];
-    au.un[0] = L.st[P][0]; au.un[1] = L.st[P][1]; au.qn = L.st[P][4];
+    // FP32-split: the increment u*(i) - u^n, without u^n
+    au.un[0] = c->split ? kNoSlot : L.st[P][0];
+    au.un[1] = c->split ? kNoSlot : L.st[P][1];
+    au.qn = L.st[P][4];
     for (int j = 1; j < i; ++j) {
       if (c->A[i][j] != 0.0) {
         au.H[au.nH][0] = L.Hu[j][0]; au.H[au.nH][1] = L.Hu[j][1]; au.cH[au.nH++] = c->A[i][j];
@@ -623,8 +664,9 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     } else {
       au.out_hu[0] = au.out_hu[1] = au.out_gq = kNoSlot;
     }
-    // the partner is u^n for the first stage: read once with u^n
-    const int reads = 2 + (i == 1 ? 0 : 2) + 3 + 2 * au.nH + au.nG;
+    // the partner is u^n for the first stage: read once with u^n (the split form reads
+    // only the partner)
+    const int reads = 2 + (i == 1 || c->split ? 0 : 2) + 3 + 2 * au.nH + au.nG;
     l.bytes = (reads + 1 + 2 + (keep ? 3 : 0)) * pt;
     plan.push_back(l);
     plan.push_back(grad_q_launch(c, qi, v1, v2));
@@ -635,6 +677,16 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     l.cls = kStageTerms;
     ArgsE &ae = l.e;
     ae.us[0] = L.Us[0]; ae.us[1] = L.Us[1]; ae.u[0] = ae.u[1] = kNoSlot;
+    ae.ub[0] = ae.ub[1] = ae.out_ud[0] = ae.out_ud[1] = ae.du0_in = ae.du0_out = kNoSlot;
+    if (c->split) {
+      // increment form on the float64 base u^n; the last stage writes the float64 state
+      // u^{n+1} and its D0.u, the next step's D0.u^n
+      ae.ub[0] = L.ud[P][0]; ae.ub[1] = L.ud[P][1];
+      if (last) {
+        ae.out_ud[0] = L.ud[Q][0]; ae.out_ud[1] = L.ud[Q][1];
+        ae.du0_in = L.du0[P]; ae.du0_out = L.du0[Q];
+      }
+    }
     ae.g[0] = L.G[0]; ae.g[1] = L.G[1];
     ae.v[0] = v1; ae.v[1] = v2; ae.th = th; ae.aii = aii;
     ae.out_u[0] = u1; ae.out_u[1] = u2;
@@ -645,10 +697,16 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const bool est = e_stored(c, ej);
     ae.out_e[0] = est ? L.E[ej][0] : kNoSlot;
     ae.out_e[1] = est ? L.E[ej][1] : kNoSlot;
-    ae.out_du = L.Du[ej];
+    ae.out_du = c->split && last ? kNoSlot : L.Du[ej];
     ae.out_lt = keep ? L.Lt[i] : kNoSlot;
     // theta, u*, G, v in; u, D0.u, E out; with keep hu and ddb in, Hu and Ltheta out
     l.bytes = pd + (2 + 2 + 2 + 2 + 1 + (est ? 2 : 0) + (keep ? 6 : 0)) * pt;
+    if (c->split) {
+      if (last)  // base u^n and D0.u^n in, u^{n+1} and D0.u^{n+1} out, in float64
+        l.bytes += 6 * pd - pt;
+      else  // float64 base u^n
+        l.bytes += 2 * pd;
+    }
     if (last)
       fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
     else
@@ -673,6 +731,9 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
     return e != hipSuccess ? e : hipStreamWaitEvent(to, ev, 0);
   }
   hipStream_t st = stream_of(c, l);
+  if (l.cls == kDivU)
+    return launch_div_u(c->co, c->d_inst, c->d_tiles[1], c->ntiles[1], l.du[0], l.du[1], l.du[2],
+                        st);
   const int si = c->shape[l.cls];
   const int ti = shape_table(si);
   Work *tiles = c->d_tiles[ti];
@@ -827,9 +888,15 @@ apdvm_status put_state(apdvm_ctx *c, int k, const double *const f[6], bool dev) 
     if (st != APDVM_OK) return st;
   }
   const Inst &I = c->inst[k];
+  const size_t nb = (size_t)I.plane * sizeof(double);
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (c->split)  // the float64 velocity beside its float copy
+    for (int m = 0; m < 2; ++m)
+      if (hipMemcpyAsync(I.dbase + (size_t)L.ud[P][m] * I.plane, f[m], nb, kind, c->stream) !=
+          hipSuccess)
+        return APDVM_ERR_HIP;
   double *th = I.dbase + (size_t)L.th[P] * I.plane;
-  return hip_status(hipMemcpyAsync(th, f[2], (size_t)I.plane * sizeof(double),
-                                   dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  return hip_status(hipMemcpyAsync(th, f[2], nb, kind, c->stream));
 }
 
 apdvm_status get_state(apdvm_ctx *c, int k, double *const f[6], bool dev) {
@@ -839,6 +906,15 @@ apdvm_status get_state(apdvm_ctx *c, int k, double *const f[6], bool dev) {
   const int fidx[5] = {0, 1, 3, 4, 5};
   for (int m = 0; m < 5; ++m) {
     if (!f[fidx[m]]) continue;
+    if (c->split && m < 2) {  // the velocity from its float64 planes
+      const Inst &I = c->inst[k];
+      if (hipMemcpyAsync(f[m], I.dbase + (size_t)L.ud[P][m] * I.plane,
+                         (size_t)I.plane * sizeof(double),
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         c->stream) != hipSuccess)
+        return APDVM_ERR_HIP;
+      continue;
+    }
     const apdvm_status st = c->split ? get_plane<float>(c, k, tslots[m], f[fidx[m]], dev)
                                      : get_plane<double>(c, k, tslots[m], f[fidx[m]], dev);
     if (st != APDVM_OK) return st;
@@ -854,12 +930,18 @@ apdvm_status get_state(apdvm_ctx *c, int k, double *const f[6], bool dev) {
   return APDVM_OK;
 }
 
-// The six state slots of state set P (u1, u2, v1, v2, q, then theta), or of the snapshot
-// (P = -1).
-void state_slots(const apdvm_ctx *c, int P, int *out6) {
+// The planes of state set P, or of the snapshot (P = -1).
+StateSet state_set(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
-  for (int f = 0; f < 5; ++f) out6[f] = P < 0 ? L.ck[f] : L.st[P][f];
-  out6[5] = P < 0 ? L.thck : L.th[P];
+  StateSet s;
+  for (int f = 0; f < 5; ++f) s.t[f] = P < 0 ? L.ck[f] : L.st[P][f];
+  s.d[0] = P < 0 ? L.thck : L.th[P];
+  s.nd = 1;
+  if (c->split) {
+    for (int m = 0; m < 2; ++m) s.d[1 + m] = P < 0 ? L.ckud[m] : L.ud[P][m];
+    s.nd = 3;
+  }
+  return s;
 }
 
 // Copy the state of instance k between state set P and the snapshot (to_snapshot: P ->
@@ -868,15 +950,14 @@ apdvm_status copy_snapshot(apdvm_ctx *c, int k, int P, bool to_snapshot) {
   const Inst &I = c->inst[k];
   const size_t tb = (size_t)I.plane * (c->split ? sizeof(float) : sizeof(double));
   const size_t db = (size_t)I.plane * sizeof(double);
-  int a[6], b[6];
-  state_slots(c, P, a);
-  state_slots(c, -1, b);
+  const StateSet a = state_set(c, P), b = state_set(c, -1);
   char *tbase = static_cast<char *>(I.tbase);
   char *dbase = reinterpret_cast<char *>(I.dbase);
-  for (int f = 0; f < 6; ++f) {
+  for (int f = 0; f < 5 + a.nd; ++f) {
     char *base = f < 5 ? tbase : dbase;
     const size_t pb = f < 5 ? tb : db;
-    char *x = base + (size_t)a[f] * pb, *y = base + (size_t)b[f] * pb;
+    const int sa = f < 5 ? a.t[f] : a.d[f - 5], sb = f < 5 ? b.t[f] : b.d[f - 5];
+    char *x = base + (size_t)sa * pb, *y = base + (size_t)sb * pb;
     if (hipMemcpyAsync(to_snapshot ? y : x, to_snapshot ? x : y, pb, hipMemcpyDeviceToDevice,
                        c->stream) != hipSuccess)
       return APDVM_ERR_HIP;
@@ -915,17 +996,14 @@ apdvm_status device_field_stats(apdvm_ctx *c, bool split, const void *const f[6]
 apdvm_status after_fields(apdvm_ctx *c, int k, double um) {
   Inst &I = c->inst[k];
   {
-    int sl[6];
-    state_slots(c, c->parity, sl);
+    const StateSet ss = state_set(c, c->parity);
     const size_t n = (size_t)I.plane, tb = c->split ? sizeof(float) : sizeof(double);
-    const void *f[6];
-    for (int m = 0; m < 6; ++m)
-      f[m] = m == 5 ? static_cast<const void *>(I.dbase + (size_t)sl[5] * n)
-                    : static_cast<const void *>(static_cast<const char *>(I.tbase) +
-                                                (size_t)sl[m] * n * tb);
-    // state_slots order is u1, u2, v1, v2, q, theta; the statistics take u1, u2, theta,
-    // v1, v2, q
-    const void *g[6] = {f[0], f[1], f[5], f[2], f[3], f[4]};
+    const void *f[5];
+    for (int m = 0; m < 5; ++m)
+      f[m] = static_cast<const char *>(I.tbase) + (size_t)ss.t[m] * n * tb;
+    // the statistics take u1, u2, theta, v1, v2, q (u of the transport planes: only the
+    // theta sum is used here)
+    const void *g[6] = {f[0], f[1], I.dbase + (size_t)ss.d[0] * n, f[2], f[3], f[4]};
     double mean = 0.0, ignored = 0.0;
     bool finite = false;
     const apdvm_status st = device_field_stats(c, c->split, g, n, &mean, &ignored, &finite);
@@ -1013,7 +1091,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
         c->A[i + off][j + off] = cfgs[0].a_im[i * s0 + j];
       }
   }
-  c->L = make_layout(c->s);
+  c->L = make_layout(c->s, c->split);
   c->has_fields.assign(n, 0);
   c->umax.assign(n, 0.0);
   if (hipGetDevice(&c->device) != hipSuccess ||
@@ -1249,9 +1327,7 @@ apdvm_status apdvm_set_populations(apdvm_ctx *c, int32_t k, const double *F) {
 // Finite check of the current state of every instance, then the snapshot of it if the
 // check (and every earlier one) passed.
 static apdvm_status enqueue_check(apdvm_ctx *c) {
-  int cur[6], ck[6];
-  state_slots(c, c->parity, cur);
-  state_slots(c, -1, ck);
+  const StateSet cur = state_set(c, c->parity), ck = state_set(c, -1);
   if (launch_state_finite(c->split ? 1 : 0, c->d_inst, c->d_tiles[1], c->ntiles[1], kTileRows[1],
                           cur, c->d_flag, c->stream) != hipSuccess ||
       launch_snapshot(c->split ? 1 : 0, c->d_inst, c->d_tiles[1], c->ntiles[1], kTileRows[1], cur,
@@ -1389,9 +1465,11 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
   const int nblk = c->tile_count[k];
   const int cap = 1024;
   const int used = nblk < cap ? nblk : cap;
+  // the velocity from its float64 planes (the transport planes in FP64, the float64
+  // velocity of the FP32-split form)
+  const int su1 = c->split ? L.ud[P][0] : L.st[P][0], su2 = c->split ? L.ud[P][1] : L.st[P][1];
   if (launch_diagnostics(c->d_inst, c->d_tiles[1] + c->tile_first[k], nblk, kTileRows[1],
-                         c->split ? 1 : 0,
-                         L.st[P][0], L.st[P][1], L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
+                         c->split ? 1 : 0, su1, su2, L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
                          c->co, c->d_partials, used, c->stream) != hipSuccess)
     return APDVM_ERR_HIP;
   std::vector<double> part(8 * (size_t)used);
@@ -1554,7 +1632,8 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     const int P = c->parity;
     const size_t tsz = c->split ? sizeof(float) : sizeof(double);
     size_t total = 0;
-    for (const Inst &I : c->inst) total += (size_t)I.plane * (5 * tsz + sizeof(double));
+    const StateSet cur = state_set(c, P);
+    for (const Inst &I : c->inst) total += (size_t)I.plane * (5 * tsz + cur.nd * sizeof(double));
     char *snap = nullptr;
     if (hipMalloc(&snap, total) != hipSuccess) return APDVM_ERR_NOMEM;
     auto copy_state = [&](bool save) {
@@ -1563,16 +1642,18 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       for (const Inst &I : c->inst) {
         const size_t pb = (size_t)I.plane * tsz;
         for (int f = 0; f < 5; ++f) {
-          char *dev = static_cast<char *>(I.tbase) + (size_t)L.st[P][f] * pb;
+          char *dev = static_cast<char *>(I.tbase) + (size_t)cur.t[f] * pb;
           ok = ok && hipMemcpyAsync(save ? q : dev, save ? dev : q, pb, hipMemcpyDeviceToDevice,
                                     c->stream) == hipSuccess;
           q += pb;
         }
-        char *th = reinterpret_cast<char *>(I.dbase + (size_t)L.th[P] * I.plane);
         const size_t db = (size_t)I.plane * sizeof(double);
-        ok = ok && hipMemcpyAsync(save ? q : th, save ? th : q, db, hipMemcpyDeviceToDevice,
-                                  c->stream) == hipSuccess;
-        q += db;
+        for (int m = 0; m < cur.nd; ++m) {
+          char *dp = reinterpret_cast<char *>(I.dbase + (size_t)cur.d[m] * I.plane);
+          ok = ok && hipMemcpyAsync(save ? q : dp, save ? dp : q, db, hipMemcpyDeviceToDevice,
+                                    c->stream) == hipSuccess;
+          q += db;
+        }
       }
       return ok;
     };

@@ -52,7 +52,11 @@ __global__ __launch_bounds__(256) void k_diag(const Inst *__restrict__ insts,
     const Inst &I = insts[wk.inst];
     const int nx = I.nx, ny = I.ny;
     const T *tb = reinterpret_cast<const T *>(I.tbase);
-    const T *u1 = tb + (long long)su1 * I.plane, *u2 = tb + (long long)su2 * I.plane;
+    // the velocity is float64 in both forms: transport planes of the FP64 form, the
+    // float64 velocity planes of the FP32-split form
+    const double *ub = sizeof(T) == sizeof(double) ? reinterpret_cast<const double *>(I.tbase)
+                                                   : I.dbase;
+    const double *u1 = ub + (long long)su1 * I.plane, *u2 = ub + (long long)su2 * I.plane;
     const T *v1 = tb + (long long)sv1 * I.plane, *v2 = tb + (long long)sv2 * I.plane;
     const T *q = tb + (long long)sq * I.plane;
     const double *th = I.dbase + (long long)dth * I.plane;

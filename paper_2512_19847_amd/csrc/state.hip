@@ -110,18 +110,12 @@ hipError_t launch_convert(void *dst, const void *src, long long n, int to_float,
 
 // ------------------------------------------------------------ finite check and snapshot
 
-// State planes of one check: five transport slots (u1, u2, v1, v2, q) and theta.
-struct StateSlots {
-  int t[5];
-  int th;
-};
-
 // Marks *flag when any value of the state is not finite.  One 64 x ty tile per workgroup
 // of 256 threads (the 16-row tile table), every instance of the context.
 template <typename T>
 __global__ __launch_bounds__(256) void k_state_finite(const Inst *__restrict__ insts,
                                                       const Work *__restrict__ tiles, int ntiles,
-                                                      int ty, StateSlots s,
+                                                      int ty, StateSet s,
                                                       unsigned *__restrict__ flag) {
   const Work wk = tiles[blockIdx.x];
   const Inst &I = insts[wk.inst];
@@ -135,7 +129,7 @@ __global__ __launch_bounds__(256) void k_state_finite(const Inst *__restrict__ i
     const long long g = (long long)y * I.nx + x;
 #pragma unroll
     for (int p = 0; p < 5; ++p) fin = fin && isfinite((double)tb[(long long)s.t[p] * I.plane + g]);
-    fin = fin && isfinite(I.dbase[(long long)s.th * I.plane + g]);
+    for (int p = 0; p < s.nd; ++p) fin = fin && isfinite(I.dbase[(long long)s.d[p] * I.plane + g]);
   }
   if (!fin) *flag = 1u;  // every writer stores the same value
 }
@@ -145,7 +139,7 @@ __global__ __launch_bounds__(256) void k_state_finite(const Inst *__restrict__ i
 template <typename T>
 __global__ __launch_bounds__(256) void k_snapshot(const Inst *__restrict__ insts,
                                                   const Work *__restrict__ tiles, int ntiles,
-                                                  int ty, StateSlots src, StateSlots dst,
+                                                  int ty, StateSet src, StateSet dst,
                                                   const unsigned *__restrict__ flag,
                                                   long long *__restrict__ ck_step,
                                                   long long step) {
@@ -163,15 +157,13 @@ __global__ __launch_bounds__(256) void k_snapshot(const Inst *__restrict__ insts
 #pragma unroll
     for (int p = 0; p < 5; ++p)
       tb[(long long)dst.t[p] * I.plane + g] = tb[(long long)src.t[p] * I.plane + g];
-    I.dbase[(long long)dst.th * I.plane + g] = I.dbase[(long long)src.th * I.plane + g];
+    for (int p = 0; p < src.nd; ++p)
+      I.dbase[(long long)dst.d[p] * I.plane + g] = I.dbase[(long long)src.d[p] * I.plane + g];
   }
 }
 
 hipError_t launch_state_finite(int split, const Inst *insts, const Work *tiles, int ntiles,
-                               int ty, const int *slots6, unsigned *flag, hipStream_t st) {
-  StateSlots s;
-  for (int p = 0; p < 5; ++p) s.t[p] = slots6[p];
-  s.th = slots6[5];
+                               int ty, const StateSet &s, unsigned *flag, hipStream_t st) {
   if (split)
     hipLaunchKernelGGL(k_state_finite<float>, dim3(ntiles), dim3(256), 0, st, insts, tiles,
                        ntiles, ty, s, flag);
@@ -182,15 +174,8 @@ hipError_t launch_state_finite(int split, const Inst *insts, const Work *tiles, 
 }
 
 hipError_t launch_snapshot(int split, const Inst *insts, const Work *tiles, int ntiles, int ty,
-                           const int *src6, const int *dst6, const unsigned *flag,
+                           const StateSet &a, const StateSet &b, const unsigned *flag,
                            long long *ck_step, long long step, hipStream_t st) {
-  StateSlots a, b;
-  for (int p = 0; p < 5; ++p) {
-    a.t[p] = src6[p];
-    b.t[p] = dst6[p];
-  }
-  a.th = src6[5];
-  b.th = dst6[5];
   if (split)
     hipLaunchKernelGGL(k_snapshot<float>, dim3(ntiles), dim3(256), 0, st, insts, tiles, ntiles,
                        ty, a, b, flag, ck_step, step);

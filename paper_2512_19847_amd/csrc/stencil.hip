@@ -25,6 +25,8 @@
 // right-hand side are float64 whatever T is.
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace apdvm {
 
 // ------------------------------------------------------------------ helpers
@@ -224,6 +226,21 @@ __device__ __forceinline__ T flux3_lf(const T *p, const T *m) {
   return sum2(np, dp, nm, dm);
 }
 
+// Shift of the dissipation variable inside one flux window.  A WENO reconstruction is
+// exactly translation invariant (the smoothness indicators see differences only; every
+// candidate is an affine combination), so adding a constant c to every value of f+ and
+// -c to every value of f- changes the left-biased part by +c and the right-biased one by
+// -c, and the flux not at all.  In float the split values (sf f +- w) / 2 are dominated
+// by the larger dissipation variable (a velocity of order one against v of order |u|^2),
+// and each reconstructed face would carry its rounding, which the flux difference
+// divides by h; with w - c, c a value of w in the window, the subtraction is exact for a
+// smooth w and the rounding falls to that of f and of the variation of w.  float64 keeps
+// the plain form.
+template <typename T>
+__device__ __forceinline__ T diss_shift(T c) {
+  return sizeof(T) == sizeof(float) ? c : T(0);
+}
+
 // Numerical flux at the face between cells k = 2 and k = 3 of six consecutive cells
 // (stride apart in LDS).  f and w are staged halved, so f+ = sf f + w and
 // f- = sf f - w are the Lax-Friedrichs split fluxes (sf f +- alpha w)/2 with alpha = 1
@@ -234,9 +251,10 @@ __device__ __forceinline__ T face_flux(const T *f, const T *w, int stride, T sf)
   constexpr int K0 = WO == 5 ? 0 : 1, K1 = WO == 5 ? 6 : 5;
   if (DISS) {
     T p[6], m[6];
+    const T c = diss_shift(w[2 * stride]);
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
-      const T fk = f[k * stride], wk = w[k * stride];
+      const T fk = f[k * stride], wk = w[k * stride] - c;
       p[k] = fma(sf, fk, wk);
       m[k] = fma(sf, fk, -wk);
     }
@@ -258,9 +276,10 @@ template <typename T, bool DISS>
 __device__ __forceinline__ void face_flux3(const T *f, const T *w, int stride, T sf, T *out) {
   if (DISS) {
     T p[7], m[8];  // f+ on cells 0..6, f- on cells 1..7
+    const T c = diss_shift(w[3 * stride]);  // one shift for the three faces (see diss_shift)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const T fk = f[k * stride], wk = w[k * stride];
+      const T fk = f[k * stride], wk = w[k * stride] - c;
       if (k < 7) p[k] = fma(sf, fk, wk);
       if (k > 0) m[k] = fma(sf, fk, -wk);
     }
@@ -467,6 +486,27 @@ struct Central<4> {
             p[c + 2 * st]) *
            f;
   }
+  // float64 arithmetic on values of type S
+  template <typename S>
+  __device__ static double d2w(const S *p, int c, int st, double f) {
+    return (-(double)p[c - 2 * st] + 16.0 * (double)p[c - st] - 30.0 * (double)p[c] +
+            16.0 * (double)p[c + st] - (double)p[c + 2 * st]) *
+           f;
+  }
+  template <typename S>
+  __device__ static double dxyw(const S *p, int c, int W, double fx, double fy) {
+    const int o[4] = {-2, -1, 1, 2};
+    const double w[4] = {1.0, -8.0, 8.0, -1.0};
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double dy = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) dy += w[b] * (double)p[c + o[a] + o[b] * W];
+      acc += w[a] * (dy * fy);
+    }
+    return acc * fx;
+  }
   template <typename S>
   __device__ static S dxy(const S *p, int c, int W, S fx, S fy) {
     const int o[4] = {-2, -1, 1, 2};
@@ -500,7 +540,27 @@ struct Central<2> {
     const S dyp = (p[c + 1 + W] - p[c + 1 - W]) * fy, dym = (p[c - 1 + W] - p[c - 1 - W]) * fy;
     return (dyp - dym) * fx;
   }
+  template <typename S>
+  __device__ static double d2w(const S *p, int c, int st, double f) {
+    return ((double)p[c - st] - 2.0 * (double)p[c] + (double)p[c + st]) * f;
+  }
+  template <typename S>
+  __device__ static double dxyw(const S *p, int c, int W, double fx, double fy) {
+    const double dyp = ((double)p[c + 1 + W] - (double)p[c + 1 - W]) * fy,
+                 dym = ((double)p[c - 1 + W] - (double)p[c - 1 - W]) * fy;
+    return (dyp - dym) * fx;
+  }
 };
+
+// float64 central first difference of the 2R + 1 values w[0..2R] centred on w[R], with
+// its evaluation order fixed by explicit fused operations, so that every kernel forming
+// D0.u of the float64 velocity (the last stage of the FP32-split form and the set-up
+// kernel k_div_u) gets the same bits from the same values.
+template <int CO>
+__device__ __forceinline__ double d0_fixed(const double *w, double f) {
+  if constexpr (CO == 2) return (w[2] - w[0]) * f;
+  return fma(8.0, w[3] - w[1], w[0] - w[4]) * f;
+}
 
 template <typename T>
 __device__ __forceinline__ Gp<T> tplane(const Inst &I, int slot) {
@@ -589,11 +649,12 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
       HD.load(I, a.D, a.nD, g);
       HL.load(I, a.L, a.nL, g);
       const double thn = *dcell(I, a.thn, g);
-      const double du0 = (double)*tcell<T>(I, a.du0, g);
+      const double du0 = a.du0_dbl ? *dcell(I, a.du0, g) : (double)*tcell<T>(I, a.du0, g);
       double hd = 0.0, hl = 0.0;
       HD.add(I, &hd, a.D, a.cD, a.nD, g);
       HL.add(I, &hl, a.L, a.cL, a.nL, g);
-      base[r] = -sig * thn + c_d * hd + c_0 * du0 - c_l * hl;
+      const double c_u0 = a.du0_dbl ? fma(c_d, a.sum_a, c_0) : c_0;
+      base[r] = -sig * thn + c_d * hd + c_u0 * du0 - c_l * hl;
     }
   }
   {
@@ -603,20 +664,23 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
   __syncthreads();
   if (!col) return;
   using C = Central<CO>;
-  const T ihx12 = T(C::f1(I.ihx)), ihy12 = T(C::f1(I.ihy));
-  const T ihx2 = T(C::f2(I.ihx)), ihy2 = T(C::f2(I.ihy));
+  const double ihx12 = C::f1(I.ihx), ihy12 = C::f1(I.ihy);
+  const double ihx2 = C::f2(I.ihx), ihy2 = C::f2(I.ihy);
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + Gm::WV * r;
     const int gy = wk.b + ly;
     if (gy >= I.ny) break;
     const int c = Gm::at(tx, ly);
-    // D0^2 : B(v) = -D_xx v1 + 2 D_x D_y v2 + D_yy v1
-    const T ddb = -C::d2(sV1, c, 1, ihx2) + T(2) * C::dxy(sV2, c, Gm::W, ihx12, ihy12) +
-                  C::d2(sV1, c, Gm::W, ihy2);
+    // D0^2 : B(v) = -D_xx v1 + 2 D_x D_y v2 + D_yy v1, in float64 arithmetic whatever T
+    // is: its rounding would enter R as white noise, which the inverse of D_Delta carries
+    // into the smooth modes of theta (the rounding of v itself enters as the second
+    // difference of a noise, which that inverse undoes)
+    const double ddb = -C::d2w(sV1, c, 1, ihx2) + 2.0 * C::dxyw(sV2, c, Gm::W, ihx12, ihy12) +
+                       C::d2w(sV1, c, Gm::W, ihy2);
     const Cell g = cell_at<T>(gy * I.nx + gx);
-    *dcell(I, a.out_r, g) = base[r] - (double)ddb;
-    *tcell<T>(I, a.out_ddb, g) = ddb;
+    *dcell(I, a.out_r, g) = base[r] - ddb;
+    *tcell<T>(I, a.out_ddb, g) = (T)ddb;
   }
 }
 
@@ -626,7 +690,9 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
 // short of its theta gradient,
 //   u*(i) = u^n - dt sum_j cH_j Hu(j) - dt a_ii D_W.B(v(i)),
 // so this kernel can run while the Helmholtz solve of the same stage produces theta(i).
-// The stage-terms kernel of the stage subtracts dt a_ii D0 theta(i) from u*(i).
+// The stage-terms kernel of the stage subtracts dt a_ii D0 theta(i) from u*(i).  In the
+// FP32-split form (a.un[0] == kNoSlot) the kernel stores the increment u*(i) - u^n: it is
+// of size dt |Hu|, so its float rounding is that much smaller than the rounding of u.
 template <typename T, int TY, int NT, int WO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
@@ -698,8 +764,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       Hist<T, 1> HG;
       HH.load(I, &a.H[0][0], a.nH, g);
       HG.load(I, a.G, a.nG, g);
-      un1[r] = (double)*tcell<T>(I, a.un[0], g);
-      un2[r] = (double)*tcell<T>(I, a.un[1], g);
+      if (a.un[0] != kNoSlot) {  // else the increment du*(i) of the split form
+        un1[r] = (double)*tcell<T>(I, a.un[0], g);
+        un2[r] = (double)*tcell<T>(I, a.un[1], g);
+      }
       qn[r] = (double)*tcell<T>(I, a.qn, g);
       double h[2] = {0.0, 0.0};
       HH.add(I, h, &a.H[0][0], a.cH, a.nH, g);
@@ -767,6 +835,165 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
 }
 
+// FP32-split completion of a stage (the increment form of k_stage_terms, below), with
+// the staged velocity in float64.  Phase 1 writes the theta terms of the interior cells
+// (Hu, Ltheta) and stages the increment du(i) = du*(i) - dt a_ii D0 theta(i).  Phase 2
+// forms D0.du(i) at the interior cells, or in the last stage the float64 D0.u^{n+1} of
+// the new state from the values phase 3 stores (so it equals D0 of the stored state bit
+// for bit, as k_div_u forms it after a restart).  Phase 3 stages u(i) = u^n + du(i),
+// halved, for the flux rounds (in float64: the viscous term (tau/4) D0_W.B(u) of E would
+// otherwise carry the float rounding of u divided by h), and writes the interior
+// velocities: float u(i) and, in the last stage, the float64 state u^{n+1} = u^n + du(s)
+// with its float copy.  Only the float rounding of du*(i), of size dt |Hu|, reaches D0.u.
+template <typename T, int TY, int NT, int CO, typename SU>
+__device__ __forceinline__ void stage_increment(const Inst &I, const Work &wk, const ArgsE &a,
+                                                const SU &su, const double *sT, double *sU1,
+                                                double *sU2, const T *hv1, const T *hv2,
+                                                const T *dd, bool want_hu, bool want_lt,
+                                                double cth, double f1x, double f1y) {
+  using Gm = Geo<TY, NT>;
+  using C = Central<CO>;
+  constexpr int SWW = kTileX + 2 * (kHalo + C::R);  // row length of the staged theta
+  constexpr int R = C::R;
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  const bool col = gx < nx;
+  const bool last = a.out_ud[0] != kNoSlot;
+  // phase 1
+  if (col) {
+    const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+#pragma unroll
+    for (int r = 0; r < Gm::ROWS; ++r) {
+      const int ly = ty0 + Gm::WV * r;
+      const int gy = wk.b + ly;
+      if (gy >= ny) break;
+      const Cell g = cell_at<T>(gy * nx + gx);
+      const int cw = (ly + kHalo + R) * SWW + tx + kHalo + R;
+      if (want_hu) {
+        *tcell<T>(I, a.hu[0], g) = (T)((double)hv1[r] + C::d1(sT, cw, 1, f1x));
+        *tcell<T>(I, a.hu[1], g) = (T)((double)hv2[r] + C::d1(sT, cw, SWW, f1y));
+      }
+      if (want_lt) {
+        const double lap = C::d2(sT, cw, 1, f2x) + C::d2(sT, cw, SWW, f2y);
+        *tcell<T>(I, a.out_lt, g) = (T)((double)dd[r] + lap);
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < SU::IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= Gm::PL) break;
+    const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+    const int c = (ly + R) * SWW + lx + R;
+    sU1[idx] = (double)su.v[0][it] - cth * C::d1(sT, c, 1, f1x);
+    sU2[idx] = (double)su.v[1][it] - cth * C::d1(sT, c, SWW, f1y);
+  }
+  __syncthreads();
+  // phase 2: u^n on the staged region (float64, or its float copy when no float64 base
+  // is given)
+  double b1[SU::IT], b2[SU::IT];
+  if (a.ub[0] != kNoSlot) {
+    Stage<TY, NT, 2, double> sb;
+    const Gp<const double> g2[2] = {dplane(I, a.ub[0]), dplane(I, a.ub[1])};
+    sb.load(g2, nx, ny, wk.a, wk.b);
+#pragma unroll
+    for (int it = 0; it < SU::IT; ++it) {
+      b1[it] = sb.v[0][it];
+      b2[it] = sb.v[1][it];
+    }
+  } else {
+    Stage<TY, NT, 2, T> sb;
+    const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};
+    sb.load(g2, nx, ny, wk.a, wk.b);
+#pragma unroll
+    for (int it = 0; it < SU::IT; ++it) {
+      b1[it] = (double)sb.v[0][it];
+      b2[it] = (double)sb.v[1][it];
+    }
+  }
+  if (col) {
+#pragma unroll
+    for (int r = 0; r < Gm::ROWS; ++r) {
+      const int ly = ty0 + Gm::WV * r;
+      const int gy = wk.b + ly;
+      if (gy >= ny) break;
+      const int c = Gm::at(tx, ly);
+      double wx[2 * R + 1], wy[2 * R + 1];
+      if (last) {
+        const Gp<const double> p1 = dplane(I, a.ub[0]), p2 = dplane(I, a.ub[1]);
+#pragma unroll
+        for (int k = -R; k <= R; ++k) {
+          wx[k + R] = p1[(long long)gy * nx + wrap(gx + k, nx)] + sU1[c + k];
+          wy[k + R] = p2[(long long)wrap(gy + k, ny) * nx + gx] + sU2[c + k * Gm::W];
+        }
+        const Cell g = cell_at<T>(gy * nx + gx);
+        *dcell(I, a.du0_out, g) = d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y);
+      } else if (a.out_du != kNoSlot) {
+#pragma unroll
+        for (int k = -R; k <= R; ++k) {
+          wx[k + R] = sU1[c + k];
+          wy[k + R] = sU2[c + k * Gm::W];
+        }
+        const Cell g = cell_at<T>(gy * nx + gx);
+        *tcell<T>(I, a.out_du, g) = (T)(d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y));
+      }
+    }
+  }
+  __syncthreads();
+  // phase 3: each thread replaces the increments of its own staged elements
+#pragma unroll
+  for (int it = 0; it < SU::IT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (idx >= Gm::PL) break;
+    const double u1 = b1[it] + sU1[idx], u2 = b2[it] + sU2[idx];
+    sU1[idx] = 0.5 * u1;
+    sU2[idx] = 0.5 * u2;
+    const int ly = idx / Gm::W, lx = idx - ly * Gm::W;
+    const int gxs = wk.a + lx - kHalo, gys = wk.b + ly - kHalo;
+    if (lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo && ly < kHalo + TY && gxs < nx &&
+        gys < ny) {
+      const Cell g = cell_at<T>(gys * nx + gxs);
+      *tcell<T>(I, a.out_u[0], g) = (T)u1;
+      *tcell<T>(I, a.out_u[1], g) = (T)u2;
+      if (last) {
+        *dcell(I, a.out_ud[0], g) = u1;
+        *dcell(I, a.out_ud[1], g) = u2;
+      }
+    }
+  }
+}
+
+// D0.u of the float64 velocity of a state (FP32-split form): once after new fields or a
+// restore; the steps then carry the float64 D0.u^n themselves.  64 x 16 tiles on 256
+// threads; neighbours read straight from the planes (this runs outside the steps).
+template <int CO>
+__global__ __launch_bounds__(256) void k_div_u(const Inst *__restrict__ insts,
+                                               const Work *__restrict__ work, int nwork,
+                                               int su1, int su2, int out) {
+  using C = Central<CO>;
+  constexpr int R = C::R;
+  const Work wk = work[blockIdx.x];
+  const Inst &I = insts[wk.inst];
+  const int nx = I.nx, ny = I.ny;
+  const int gx = wk.a + (threadIdx.x & 63);
+  if (gx >= nx) return;
+  const Gp<const double> p1 = dplane(I, su1), p2 = dplane(I, su2);
+  const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+  for (int ly = threadIdx.x >> 6; ly < 16; ly += 4) {
+    const int gy = wk.b + ly;
+    if (gy >= ny) break;
+    double wx[2 * R + 1], wy[2 * R + 1];
+#pragma unroll
+    for (int k = -R; k <= R; ++k) {
+      wx[k + R] = p1[(long long)gy * nx + wrap(gx + k, nx)];
+      wy[k + R] = p2[(long long)wrap(gy + k, ny) * nx + gx];
+    }
+    const Cell g = cell_at<double>(gy * nx + gx);
+    *dcell(I, out, g) = d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y);
+  }
+}
+
 // ------------------------------------------------------------------ stage terms
 
 // Completion of a stage and the terms of it that later stages reuse:
@@ -785,15 +1012,19 @@ template <typename T, int TY, int NT, int WO, int CO>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
+  // FP32-split form: u^n in float64, stage velocities as float increments on it; the
+  // staged velocity and the fluxes of E in float64 (TU)
+  constexpr bool INC = sizeof(T) == 4;
+  using TU = std::conditional_t<INC, double, T>;
   using Gm = Geo<TY, NT>;
   using C = Central<CO>;
   using SU = Stage<TY, NT, 2, T>;                  // u*
   using SW = Stage<TY, NT, 1, double, kHalo + C::R>;  // theta(i), wide halo
   constexpr int FN = Gm::FXN + Gm::FYN;
-  constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(T));
-  __shared__ T sU1[Gm::PL], sU2[Gm::PL];
-  __shared__ __align__(16) T sF[FN > FT ? FN : FT];
-  T *fx = sF, *fy = sF + Gm::FXN;
+  constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(TU));
+  __shared__ TU sU1[Gm::PL], sU2[Gm::PL];
+  __shared__ __align__(16) TU sF[FN > FT ? FN : FT];
+  TU *fx = sF, *fy = sF + Gm::FXN;
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
   const int nx = I.nx, ny = I.ny;
@@ -831,6 +1062,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     __syncthreads();
     const double cth = I.dt * a.aii;
     const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+    if constexpr (INC) {
+      stage_increment<T, TY, NT, CO>(I, wk, a, su, sT, sU1, sU2, hv1, hv2, dd, want_hu, want_lt,
+                                     cth, f1x, f1y);
+    } else {
 #pragma unroll
     for (int it = 0; it < SU::IT; ++it) {
       const int idx = threadIdx.x + it * NT;
@@ -866,6 +1101,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
         }
       }
     }
+    }  // !INC
+  } else if constexpr (INC) {  // the terms of a state: its float64 velocity
+    Stage<TY, NT, 2, double> su;
+    const Gp<const double> g2[2] = {dplane(I, a.ub[0]), dplane(I, a.ub[1])};
+    su.load(g2, nx, ny, wk.a, wk.b);
+    double *l2[2] = {sU1, sU2};
+    su.store(l2, 0.5);
   } else {
     Stage<TY, NT, 2, T> su;
     const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};
@@ -874,15 +1116,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     su.store(l2, T(0.5));
   }
   __syncthreads();
-  const T ihx = T(I.ihx), ihy = T(I.ihy);
+  const TU ihx = TU(I.ihx), ihy = TU(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
   const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
-  const T qt = T(0.25 * I.tau);
+  const TU qt = TU(0.25 * I.tau);
   // first component of (tau/4) D0_W.B(u); E is assembled at the end
-  T e1[Gm::ROWS];
+  TU e1[Gm::ROWS];
   // first row of B(u) = (-u1, u2), no dissipation
-  constexpr int FPT = faces_per_thread<T, WO, TY, NT, true>();
-  faces<TY, NT, WO, T, false, false, FPT>(fx, fy, sU1, sU1, T(-1), sU2, sU2, T(1));
+  constexpr int FPT = faces_per_thread<TU, WO, TY, NT, true>();
+  faces<TY, NT, WO, TU, false, false, FPT>(fx, fy, sU1, sU1, TU(-1), sU2, sU2, TU(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -891,7 +1133,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
   __syncthreads();
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
-  faces<TY, NT, WO, T, false, false, FPT>(fx, fy, sU2, sU2, T(1), sU1, sU1, T(1));
+  faces<TY, NT, WO, TU, false, false, FPT>(fx, fy, sU2, sU2, TU(1), sU1, sU1, TU(1));
   __syncthreads();
   if (!col) return;
   // pointwise inputs of E and of the fused step 1: G, v, and
@@ -932,14 +1174,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     if (gy >= ny) break;
     const Cell g = cell_at<T>(gy * nx + gx);
     const int c = Gm::at(tx, ly);
-    const T u1 = T(2) * sU1[c], u2 = T(2) * sU2[c];
-    const T E1 = (e1[r] - T(0.5) * (u2 * u2 - u1 * u1)) + g1[r];
-    const T E2 = (qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2) +
-                 g2[r];
-    *tcell<T>(I, a.out_du, g) = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
+    const TU u1 = TU(2) * sU1[c], u2 = TU(2) * sU2[c];
+    const TU E1 = (e1[r] - TU(0.5) * (u2 * u2 - u1 * u1)) + TU(g1[r]);
+    const TU E2 =
+        (qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2) +
+        TU(g2[r]);
+    if constexpr (!INC)  // the split form stores D0 of the increment, formed above
+      *tcell<T>(I, a.out_du, g) = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
     if (a.out_e[0] != kNoSlot) {
-      *tcell<T>(I, a.out_e[0], g) = E1;
-      *tcell<T>(I, a.out_e[1], g) = E2;
+      *tcell<T>(I, a.out_e[0], g) = (T)E1;
+      *tcell<T>(I, a.out_e[1], g) = (T)E2;
     }
     if (nv.stage > 0) {
       // step 1 of the next stage; its newest history terms are this E and this v
@@ -1047,6 +1291,16 @@ hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const W
 }
 #undef APDVM_DISPATCH
 #undef APDVM_ONE
+
+// tiles: the 64 x 16 tile table (nwork entries, 256 threads each).
+hipError_t launch_div_u(int co, const Inst *insts, const Work *tiles, int nwork, int su1, int su2,
+                        int out, hipStream_t st) {
+  if (co == 4)
+    hipLaunchKernelGGL(k_div_u<4>, dim3(nwork), dim3(256), 0, st, insts, tiles, nwork, su1, su2, out);
+  else
+    hipLaunchKernelGGL(k_div_u<2>, dim3(nwork), dim3(256), 0, st, insts, tiles, nwork, su1, su2, out);
+  return hipGetLastError();
+}
 
 #define APDVM_INST(T)                                                                           \
   template hipError_t launch_helmholtz_rhs<T>(int, int, int, const Inst *, const Work *, int,  \

@@ -9,8 +9,8 @@ symbols depend on k h only, so a field made of m x m copies of a periodic n x n 
 (domain m times larger, same h, same dt) stays m x m copies of the n x n solution.  The
 oracle computes the n x n run; the HIP path runs the full grid (row and column FFT
 kernels at their full lengths, the full tile grids) and must match every copy: relative
-L-infinity <= 1e-11 per field in float64, relative L2 <= 1e-5 for velocity and density in
-the FP32-split form.  The batched workload is checked on one instance of every grid side."""
+L-infinity <= 1e-11 per field in float64, relative L2 <= 1e-5 for velocity, theta and
+density in the FP32-split form.  The batched workload is checked on one instance of every grid side."""
 
 import sys
 
@@ -79,7 +79,8 @@ def _linf(got, ref, tile):
 
 
 def _l2(got, ref, eps, tile):
-    """Relative L2 of velocity and of the density 1 + 2 eps^2 theta over every copy."""
+    """Relative L2 of velocity, of theta (the density fluctuation (rho - 1) / (2 eps^2))
+    and of the density 1 + 2 eps^2 theta over every copy."""
     gu = [_copies(g, tile) for g in got[:2]]
     du = sum(np.sum((g - r[None, :, None, :]) ** 2) for g, r in zip(gu, ref[:2]))
     nu = tile * tile * sum(np.sum(r ** 2) for r in ref[:2])
@@ -87,7 +88,10 @@ def _l2(got, ref, eps, tile):
     rho_r = 1 + 2 * eps * eps * ref[2]
     dr = np.sum((1 + 2 * eps * eps * gth - rho_r[None, :, None, :]) ** 2)
     nr = tile * tile * np.sum(rho_r ** 2)
-    return dict(u=float(np.sqrt(du / nu)), rho=float(np.sqrt(dr / nr)))
+    dth = np.sum((gth - ref[2][None, :, None, :]) ** 2)
+    nth = tile * tile * np.sum(ref[2] ** 2)
+    return dict(u=float(np.sqrt(du / nu)), theta=float(np.sqrt(dth / nth)),
+                rho=float(np.sqrt(dr / nr)))
 
 
 @pytest.fixture(scope="module")
@@ -121,7 +125,7 @@ def test_shear_layer_8192(shear_8192, precision):
     else:
         err = _l2(got, ref, case.eps, tile)
         _say(f"  rel L2 {err}")
-        assert err["u"] <= TOL_L2 and err["rho"] <= TOL_L2, err
+        assert max(err.values()) <= TOL_L2, err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32split"])
@@ -138,7 +142,7 @@ def test_random_field_2048(random_2048, precision):
     else:
         err = _l2(got, ref, case.eps, tile)
         _say(f"  rel L2 {err}")
-        assert err["u"] <= TOL_L2 and err["rho"] <= TOL_L2, err
+        assert max(err.values()) <= TOL_L2, err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32split"])
@@ -161,4 +165,4 @@ def test_batched_256_sampled_instances(precision):
         else:
             err = _l2(got[k], ref, cases[k].eps, 1)
             _say(f"  instance {k} ({n}^2, eps={cases[k].eps:.3g}) rel L2 {err}")
-            assert err["u"] <= TOL_L2 and err["rho"] <= TOL_L2, (k, err)
+            assert max(err.values()) <= TOL_L2, (k, err)

@@ -1,15 +1,16 @@
-"""FP32-split form: u, v, q and the stage terms stored and transported in float32,
-history sums, theta and the Helmholtz solve in float64.  Checked against the float64
-GPU path (relative L2 <= 1e-5 for velocity and density) and against the oracle on a
-small case.
+"""FP32-split form: v, q, the stage increments of u and the stage terms stored and
+transported in float32; the velocity state u^n, its central divergence, theta, the
+history sums and the Helmholtz solve in float64.  Checked against the float64 GPU path
+(relative L2 <= 1e-5 for the velocity, for theta -- the density fluctuation
+rho - 1 = 2 eps^2 theta -- and for the density itself) and against the oracle on a small
+case.
 
-theta is not a target quantity of the split form and is held to a regression bound
-only: at eps -> 0 theta is the pressure that removes the discrete divergence of the
-velocity (the Helmholtz right-hand side carries D0.u / (dt a_ii)), so the float32
-rounding of u at every stage, whose divergence is amplified by 1/(dt a_ii), moves theta
-by orders more than u itself (u stays at ~2e-7).  Rounding only the initial fields to
-float32 and running in float64 moves theta by ~5e-9: the effect comes from the
-per-stage rounding, not from the inputs."""
+theta is the sensitive quantity: at eps -> 0 it is the pressure that removes the
+discrete divergence of the velocity (the Helmholtz right-hand side carries
+D0.u / (dt a_ii^2)), so any rounding of u enters theta amplified by 1 / dt.  Rounding u
+itself to float at every stage moved theta by 1e-3 .. 8e-3 (relative L2); with u^n kept
+in float64 and only the stage increments u(i) - u^n (of size dt |Hu|) in float, the
+rounding that reaches D0.u is smaller by |u(i) - u^n| / |u|."""
 
 import sys
 
@@ -36,8 +37,8 @@ def _run(cases, tab, nsteps, precision, round_inputs=False):
                            tableau=tab, precision=precision)
     for k, c in enumerate(cases):
         st = c.state
-        if round_inputs:  # the float32 rounding the split form applies to u, v, q
-            st = [f if i == 2 else f.astype(np.float32).astype(np.float64)
+        if round_inputs:  # the float32 rounding the split form applies to v and q
+            st = [f if i < 3 else f.astype(np.float32).astype(np.float64)
                   for i, f in enumerate(st)]
         sim.set_fields(k, *st)
     sim.step(nsteps)
@@ -68,9 +69,32 @@ def test_split_vs_fp64_random_field():
     twin = _run([case], "ars443", 300, apdvm.FP64, round_inputs=True)[0]
     err = _errors(a, b, case.eps)
     floor = _errors(twin, b, case.eps)
-    _say(f"  rel L2 {err}\n  float64 run from float32-rounded inputs {floor}")
-    assert err["u"] <= TOL_L2 and err["rho"] <= TOL_L2, err
-    assert err["theta"] <= 1e-2, err  # regression bound, see the module docstring
+    _say(f"  rel L2 {err}\n  float64 run from float32-rounded v, q {floor}")
+    assert max(err.values()) <= TOL_L2, err
+
+
+def test_split_vs_fp64_random_2048_stated_steps():
+    """The 2048^2 random-field workload as stated: eps = 1e-6, Ma = 0.01, ARS(4,4,3),
+    1000 steps, in the benchmark's launch configuration (autotuned shapes, graph replay)."""
+    import torch
+
+    from paper_2512_19847_amd import apdvm
+    case = wl.random_2048()
+    _say(f"case split random2048 1000 steps dt={case.dt}")
+    out = []
+    for prec in (apdvm.FP32_SPLIT, apdvm.FP64):
+        sim = apdvm.Simulation([dict(nx=case.nx, ny=case.ny, eps=case.eps, tau=case.tau,
+                                     dt=case.dt)], tableau="ars443", precision=prec,
+                               stream=torch.cuda.Stream())
+        sim.set_fields(0, *case.state)
+        sim.set_graph(True)
+        sim.autotune(1)
+        sim.step(1000)
+        out.append(sim.get_fields(0))
+        sim.close()
+    err = _errors(out[0], out[1], case.eps)
+    _say(f"  rel L2 {err}")
+    assert max(err.values()) <= TOL_L2, err
 
 
 def test_split_vs_fp64_batched_mixed():
@@ -85,7 +109,7 @@ def test_split_vs_fp64_batched_mixed():
     for k, c in enumerate(cases):
         err = _errors(a[k], b[k], c.eps)
         _say(f"  instance {k} rel L2 {err}")
-        assert err["u"] <= TOL_L2 and err["rho"] <= TOL_L2, (k, err)
+        assert max(err.values()) <= TOL_L2, (k, err)
 
 
 def test_split_vs_oracle_taylor_green():
