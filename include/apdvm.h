@@ -198,6 +198,18 @@ apdvm_status apdvm_set_step(apdvm_ctx *ctx, int64_t step);
  * value of the six fields is finite else 0. */
 apdvm_status apdvm_diagnostics(apdvm_ctx *ctx, int32_t k, double out[8]);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops):
+ * apdvm_diagnostics of instance k with the eight values written to the device array
+ * dev_out[8] (caller-owned) in the same order, enqueued on the context's stream and not
+ * synchronised; no allocation, memset or host copy.  The per-workgroup partials live in
+ * a static device array of the library (64 KiB, 1024 records, one per GPU, held until
+ * the process ends): the workgroups loop over the tiles of larger instances, so every
+ * instance size fits, and APDVM_ERR_ARG would report a record count beyond 1024.  Every
+ * call on a GPU uses that GPU's array and overwrites the records it reads, so calls that
+ * overlap on one GPU (other contexts or streams) race; calls in stream order do not.
+ * The values equal those of apdvm_diagnostics bit for bit. */
+apdvm_status apdvm_diagnostics_device(apdvm_ctx *ctx, int32_t k, double *dev_out);
+
 /* Number of kernel launches one apdvm_step(ctx, 1) enqueues (for profiling). */
 apdvm_status apdvm_launches_per_step(apdvm_ctx *ctx, int32_t *count);
 

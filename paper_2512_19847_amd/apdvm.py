@@ -109,6 +109,7 @@ def _declare(L):
     L.apdvm_autotune.argtypes = [P, c_int32, POINTER(c_int32)]
     L.apdvm_set_tuning.argtypes = [P, POINTER(c_int32)]
     L.apdvm_set_finite_check.argtypes = [P, c_int32]
+    L.apdvm_diagnostics_device.argtypes = [P, c_int32, P]
     L.apdvm_batch_create.argtypes = [c_int32, POINTER(Config), P, c_size_t, P, POINTER(P)]
     L.apdvm_batch_set_fields.argtypes = [P, c_int32] + [P] * 6
     L.apdvm_batch_step.argtypes = [P, c_int64]
@@ -125,6 +126,7 @@ def _declare(L):
                  "apdvm_set_overlap", "apdvm_get_overlap",
                  "apdvm_timing_enable", "apdvm_timing_read", "apdvm_timing_stride", "apdvm_traffic",
                  "apdvm_autotune", "apdvm_set_tuning", "apdvm_set_finite_check",
+                 "apdvm_diagnostics_device",
                  "apdvm_batch_create", "apdvm_batch_set_fields", "apdvm_batch_step",
                  "apdvm_batch_get_fields"):
         getattr(L, name).restype = ctypes.c_int
@@ -325,6 +327,17 @@ class Simulation:
         out = np.empty(8)
         _check(lib().apdvm_diagnostics(self.ctx, k, c_void_p(out.ctypes.data)), "diagnostics")
         return out
+
+    def diagnostics_device(self, k, out):
+        """apdvm_diagnostics into a float64 device tensor of 8 values (enqueued on the
+        library's stream; the caller's current stream waits for it)."""
+        if out.dtype != self.torch.float64 or out.numel() != 8 or not out.is_cuda:
+            raise ValueError("out must be a float64 device tensor of 8 values")
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _check(lib().apdvm_diagnostics_device(self.ctx, k, c_void_p(out.data_ptr())),
+               "diagnostics_device")
+        cur.wait_stream(self.stream)
 
     def set_graph(self, on):
         _check(lib().apdvm_set_graph(self.ctx, 1 if on else 0), "set_graph")

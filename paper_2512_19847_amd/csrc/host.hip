@@ -55,6 +55,11 @@ hipError_t launch_snapshot(int split, const Inst *, const Work *, int, int, cons
                            const StateSet &, const unsigned *flag, long long *ck_step,
                            long long step, hipStream_t);
 hipError_t launch_div_u(int co, const Inst *, const Work *, int, int, int, int, hipStream_t);
+hipError_t scratch_init(int device);
+double *scratch_ptr(int device);
+int scratch_blocks();
+hipError_t launch_diag_finish(const double *partials, int nblocks, double area, double *out,
+                              hipStream_t st);
 
 namespace {
 
@@ -1094,7 +1099,7 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->L = make_layout(c->s, c->split);
   c->has_fields.assign(n, 0);
   c->umax.assign(n, 0.0);
-  if (hipGetDevice(&c->device) != hipSuccess ||
+  if (hipGetDevice(&c->device) != hipSuccess || scratch_init(c->device) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -1492,6 +1497,29 @@ apdvm_status apdvm_diagnostics(apdvm_ctx *c, int32_t k, double out[8]) {
   out[0] = acc[0] * area; out[1] = acc[1] * area; out[2] = acc[2] * area;
   out[3] = acc[3]; out[4] = acc[4]; out[5] = acc[5];
   out[6] = 0.5 * acc[6] * area; out[7] = acc[7];
+  return APDVM_OK;
+}
+
+apdvm_status apdvm_diagnostics_device(apdvm_ctx *c, int32_t k, double *dev_out) {
+  if (!c || k < 0 || k >= c->n || !dev_out) return APDVM_ERR_ARG;
+  if (!c->has_fields[k]) return APDVM_ERR_STATE;
+  double *part = scratch_ptr(c->device);
+  if (!part) return APDVM_ERR_HIP;
+  const Layout &L = c->L;
+  const int P = c->parity;
+  const int nblk = c->tile_count[k];
+  // one partial record per workgroup, at most scratch_blocks() of them (the workgroups
+  // loop over the tiles of larger instances), so no instance size exceeds the scratch
+  const int used = nblk < scratch_blocks() ? nblk : scratch_blocks();
+  if (used < 1 || used > scratch_blocks()) return APDVM_ERR_ARG;
+  const int su1 = c->split ? L.ud[P][0] : L.st[P][0], su2 = c->split ? L.ud[P][1] : L.st[P][1];
+  const Inst &I = c->inst[k];
+  const double area = (1.0 / I.ihx) * (1.0 / I.ihy);
+  if (launch_diagnostics(c->d_inst, c->d_tiles[1] + c->tile_first[k], nblk, kTileRows[1],
+                         c->split ? 1 : 0, su1, su2, L.th[P], L.st[P][2], L.st[P][3], L.st[P][4],
+                         c->co, part, used, c->stream) != hipSuccess ||
+      launch_diag_finish(part, used, area, dev_out, c->stream) != hipSuccess)
+    return APDVM_ERR_HIP;
   return APDVM_OK;
 }
 

@@ -6,6 +6,8 @@
 // records (deterministic: no atomics).
 #include "common.hpp"
 
+#include <mutex>
+
 namespace apdvm {
 
 __device__ __forceinline__ int wrapi(int g, int n) {
@@ -127,6 +129,75 @@ hipError_t launch_diagnostics(const Inst *insts, const Work *tiles, int ntiles, 
   else
     hipLaunchKernelGGL(k_diag<double>, dim3(nblocks), dim3(256), 0, st, insts, tiles, ntiles, ty,
                        su1, su2, dth, sv1, sv2, sq, co, partials);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ static scratch
+
+// Scratch of apdvm_diagnostics_device: up to kScratchBlocks records of eight partials
+// (64 KiB), one set per GPU, held until the process ends.  In host code the name
+// `scratch` is a host-side stand-in: kernels receive the device address that
+// hipGetSymbolAddress returned for the current device (scratch_init).
+constexpr int kScratchBlocks = 1024;
+static __device__ __align__(256) double scratch[8 * kScratchBlocks];
+
+constexpr int kMaxDevices = 64;
+static double *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Once per device, with that device current: resolve the device address of `scratch`.
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = static_cast<double *>(p);
+  return hipSuccess;
+}
+
+// Device address of the scratch of `device` (nullptr before scratch_init succeeded).
+double *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
+
+int scratch_blocks() { return kScratchBlocks; }
+
+// Combines the nblocks partial records in block order, as the host does in
+// apdvm_diagnostics, and writes the eight diagnostics (area = hx hy).  One thread: the
+// records are few and the fixed order keeps the result identical to the host's.
+__global__ __launch_bounds__(64) void k_diag_finish(const double *__restrict__ partials,
+                                                    int nblocks, double area,
+                                                    double *__restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 1e300, -1e300, 0.0, 1.0};
+  for (int b = 0; b < nblocks; ++b) {
+    const double *q = partials + 8 * b;
+    acc[0] += q[0];
+    acc[1] += q[1];
+    acc[2] += q[2];
+    acc[3] = fmax(acc[3], q[3]);
+    acc[4] = fmin(acc[4], q[4]);
+    acc[5] = fmax(acc[5], q[5]);
+    acc[6] += q[6];
+    acc[7] = fmin(acc[7], q[7]);
+  }
+  out[0] = acc[0] * area;
+  out[1] = acc[1] * area;
+  out[2] = acc[2] * area;
+  out[3] = acc[3];
+  out[4] = acc[4];
+  out[5] = acc[5];
+  out[6] = 0.5 * acc[6] * area;
+  out[7] = acc[7];
+}
+
+hipError_t launch_diag_finish(const double *partials, int nblocks, double area, double *out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(64), 0, st, partials, nblocks, area, out);
   return hipGetLastError();
 }
 
