@@ -253,20 +253,29 @@ def random_2048(n=2048):
                      1e-6, 0.01, "ars443", cfl=CFL_ARS)
 
 
-def batched_256(count=256, seed=4, sides=(64, 96, 128, 192, 256, 384, 512)):
-    """256 independent instances: side uniform over sides, eps log-uniform in
-    [1e-6, 1], Ma uniform in [0.01, 0.1], random divergence-free fields with |k| <= 4
-    (rms 0.1, seed 1000 + k)."""
+BATCH_SIDES = (64, 96, 128, 192, 256, 384, 512)
+
+
+def _batch_params(count, seed, sides):
     rng = np.random.default_rng(seed)
     ns = rng.choice(np.array(sides), count)
     epss = 10.0 ** rng.uniform(-6.0, 0.0, count)
     machs = rng.uniform(0.01, 0.1, count)
-    cases = []
-    for k in range(count):
-        st = random_divfree(int(ns[k]), kmax=4, rms=0.1, seed=1000 + k)
-        cases.append(make_case(f"batch_{k}", st, float(epss[k]), float(machs[k]), "ars443",
-                               cfl=CFL_ARS))
-    return cases
+    return ns, epss, machs
+
+
+def batched_256_instance(k, count=256, seed=4, sides=BATCH_SIDES):
+    """Instance k of batched_256 alone (the same draws)."""
+    ns, epss, machs = _batch_params(count, seed, sides)
+    st = random_divfree(int(ns[k]), kmax=4, rms=0.1, seed=1000 + k)
+    return make_case(f"batch_{k}", st, float(epss[k]), float(machs[k]), "ars443", cfl=CFL_ARS)
+
+
+def batched_256(count=256, seed=4, sides=BATCH_SIDES):
+    """256 independent instances: side uniform over sides, eps log-uniform in
+    [1e-6, 1], Ma uniform in [0.01, 0.1], random divergence-free fields with |k| <= 4
+    (rms 0.1, seed 1000 + k)."""
+    return [batched_256_instance(k, count, seed, sides) for k in range(count)]
 
 
 # Long runs of Section 4.1 and the Kelvin-Helmholtz test: (generator, box side, final
