@@ -76,6 +76,8 @@ struct FftPlan {
   int radix[kMaxPasses];  // radices (2, 3, 4 or 8), first pass first
   const double2 *tw2;     // two-level table (device), ntw entries
   int lb, ntw;
+  int tsc;                // table index scale: the table is of length tsc n (1, or 2 for a
+                          // half-length plan that shares the table of its full length)
 };
 
 struct Inst {
@@ -88,6 +90,7 @@ struct Inst {
   double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
   double inv_nxny;           // 1 / (nx ny)
   FftPlan fx, fy;            // lengths nx and ny
+  FftPlan fyh;               // length ny / 2 on the table of fy (the split column kernel)
   const double *lam_x;       // nx/2 + 1 values of the x symbol of D_Delta
   const double *lam_y;       // ny values of the y symbol
   void *tbase;               // transport arena

@@ -132,10 +132,14 @@ __device__ __forceinline__ P at_byte(P base, unsigned b) {
   return (P)((C)base + b);
 }
 
-// LDS layout of the FFT buffers: one padding element after every 8, so the strided
-// writes of the early Stockham passes (stride R Ns elements of 16 bytes) spread over the
-// banks instead of hitting the same few.
-__device__ __forceinline__ int lp(int i) { return i + (i >> 3); }
+// LDS layout of the FFT buffers: one padding element after every 2^SH (none for SH = 0),
+// so the strided writes of the early Stockham passes (stride R Ns elements of 16 bytes)
+// spread over the banks instead of hitting the same few.  SH = 3 for the whole-row and
+// whole-column kernels; the split column kernel measured fastest without padding.
+template <int SH = 3>
+__device__ __forceinline__ int lp(int i) {
+  return SH ? i + (i >> SH) : i;
+}
 
 // exp(-2 pi i m / n) from the two-level table staged in LDS (lo at t, hi at t + 2^lb).
 __device__ __forceinline__ double2 tw_at(const double2 *t, int lb, int m) {
@@ -167,9 +171,9 @@ struct TwStage {
 // One Stockham pass over nb transforms of length n held in LDS, element j of transform b
 // at buf[lp(b n + j)]; consecutive threads take consecutive butterflies of a transform.
 // The first pass (Ns = 1) has unit twiddles and skips them.
-template <int R, int DIR, int CAP, int NT>
+template <int R, int DIR, int CAP, int NT, int SH>
 __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const double2 *tws,
-                                     int lb) {
+                                     int lb, int tsc) {
   constexpr int NPER = (CAP + R * NT - 1) / (R * NT);
   const int nbf = n / R;
   const int total = nbf * nb;
@@ -186,11 +190,11 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const 
       const int jq = dns.q(j), k = j - jq * Ns;
       const int src = b * n + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = buf[lp(src + r * nbf)];
+      for (int r = 0; r < R; ++r) v[p][r] = buf[lp<SH>(src + r * nbf)];
       if (Ns > 1) {
         // w^r for r = 1..R-1 from one table lookup: powers by products of depth <= 3
         double2 w[R];
-        w[1] = tw_at(tws, lb, k * twstep);
+        w[1] = tw_at(tws, lb, k * twstep * tsc);
         if (DIR > 0) w[1].y = -w[1].y;
         if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
         if constexpr (R >= 4) w[3] = cmul(w[2], w[1]);
@@ -212,24 +216,24 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const 
   for (int p = 0; p < NPER; ++p) {
     if (dst[p] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lp(dst[p] + r * Ns)] = v[p][r];
+      for (int r = 0; r < R; ++r) buf[lp<SH>(dst[p] + r * Ns)] = v[p][r];
     }
   }
   __syncthreads();
 }
 
 // Length-n transforms (plan P) of nb contiguous runs of n values in LDS.
-template <int DIR, int CAP, int NT>
+template <int DIR, int CAP, int NT, int SH = 3>
 __device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb,
                                         const double2 *tws) {
   int Ns = 1;
   for (int ps = 0; ps < P.npass; ++ps) {
     const int R = P.radix[ps];
     switch (R) {
-      case 8: pass<8, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
-      case 4: pass<4, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
-      case 3: pass<3, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
-      default: pass<2, DIR, CAP, NT>(buf, P.n, nb, Ns, tws, P.lb); break;
+      case 8: pass<8, DIR, CAP, NT, SH>(buf, P.n, nb, Ns, tws, P.lb, P.tsc); break;
+      case 4: pass<4, DIR, CAP, NT, SH>(buf, P.n, nb, Ns, tws, P.lb, P.tsc); break;
+      case 3: pass<3, DIR, CAP, NT, SH>(buf, P.n, nb, Ns, tws, P.lb, P.tsc); break;
+      default: pass<2, DIR, CAP, NT, SH>(buf, P.n, nb, Ns, tws, P.lb, P.tsc); break;
     }
     Ns *= R;
   }
@@ -417,6 +421,138 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   }
 }
 
+// Columns of length ny > kColMidCap (the largest form) with half the LDS: a radix-2
+// decimation in frequency in registers splits each length-ny transform into two
+// independent transforms of length h = ny / 2,
+//   X[2k] = FFT_h(x[y] + x[y + h])[k],  X[2k + 1] = FFT_h((x[y] - x[y + h]) w^y)[k],
+// w = exp(-2 pi i / ny).  The even half is transformed, divided and inverted in LDS while
+// the odd half waits in registers; the two then swap places element by element; the odd
+// half is transformed, divided and inverted; and the inverse recombines
+//   y[t] = ya[t] + w^-t yb[t],  y[t + h] = ya[t] - w^-t yb[t]
+// (ya, yb the inverse transforms of the even and odd modes; unnormalised, the divisors
+// carry 1 / (nx ny)).  A workgroup of kColSplitThreads holds C h <= kFftCap / 2 values in
+// LDS, so two workgroups share a CU and one loads or stores while the other transforms.
+// Four waves per SIMD cap the registers at 128 (the two halves in flight spill a little);
+// the buffer is not padded, which measured fastest for this kernel.
+// Work item (inst, k0) with C = cols_per_block columns.
+constexpr int kColSplitThreads = 512;
+constexpr int kColSplitCap = kFftCap / 2;
+
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cols_split(
+    const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
+  constexpr int CAP = kColSplitCap;
+  constexpr int E = CAP / NT;  // elements of a half per thread
+  __shared__ double2 buf[CAP];
+  __shared__ double2 tws[kTwCap];
+  const Work wk = work[xcd_item_fft(nwork)];
+  const Inst &I = insts[wk.inst];
+  const int ny = I.ny, K = I.nx / 2, hx = I.nx / 2, h = ny / 2;
+  const int k0 = wk.a;
+  const int C = min(I.cols_per_block, K - k0);
+  const int cnt = C * h;
+  const Gp<dv2> S = cslot(I, a.spec) + (long long)k0 * ny;
+  const double sig = I.sigma[a.stage];
+  const Div dh(h);
+  TwStage<NT> tw;
+  tw.load(I.fy);
+  double2 x0[E], x1[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int c = dh.q(idx), y = idx - c * h;
+      const unsigned b = (unsigned)(c * ny + y) * 16u;
+      x0[e] = ldc(at_byte(S, b));
+      x1[e] = ldc(at_byte(S, b + (unsigned)h * 16u));
+    }
+  }
+  tw.store(tws, I.fy);
+  __syncthreads();  // the table is read below
+  // radix-2 step: the even-mode half to LDS, the odd-mode half (times w^y) in x1
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int c = dh.q(idx), y = idx - c * h;
+      buf[lp<0>(idx)] = cadd(x0[e], x1[e]);
+      x1[e] = cmul(csub(x0[e], x1[e]), tw_at(tws, I.fy.lb, y));
+    }
+  }
+  __syncthreads();
+  // mode ky = 2m + par of column c at position c h + m of the half in LDS
+  auto divide = [&](int par) {
+    fft_lds<-1, CAP, NT, 0>(buf, I.fyh, C, tws);
+    double2 o[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cnt) {
+        const int c = dh.q(idx), m = idx - c * h;
+        const int ky = 2 * m + par;
+        const double lyy = gp(I.lam_y)[ky];
+        const double lxx = gp(I.lam_x)[k0 + c];
+        const double2 z = buf[lp<0>(idx)];
+        if (k0 + c == 0) {
+          // Z = F0 + i Fh for the real columns kx = 0 and kx = nx/2: F0 = (Z[ky] +
+          // conj Z[-ky]) / 2, Fh = (Z[ky] - conj Z[-ky]) / 2i; -ky has the parity of ky,
+          // at position (h - m - par) mod h of the same half
+          const int mm = par ? h - 1 - m : (m == 0 ? 0 : h - m);
+          const double2 zm = buf[lp<0>(mm)];
+          double2 f0 = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+          double2 fh = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+          const double dhh = mode_div(I, sig, gp(I.lam_x)[hx], lyy);
+          if (ky == 0) {
+            f0 = make_double2(I.theta_mean, 0.0);  // the (0,0) rule
+          } else {
+            const double d0 = mode_div(I, sig, lxx, lyy);
+            f0 = make_double2(f0.x * d0, f0.y * d0);
+          }
+          fh = make_double2(fh.x * dhh, fh.y * dhh);
+          o[e] = make_double2(f0.x - fh.y, f0.y + fh.x);
+        } else {
+          const double d = mode_div(I, sig, lxx, lyy);
+          o[e] = make_double2(z.x * d, z.y * d);
+        }
+      }
+    }
+    __syncthreads();  // column 0 reads mirrored elements of other threads
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cnt) buf[lp<0>(idx)] = o[e];
+    }
+    __syncthreads();
+    fft_lds<1, CAP, NT, 0>(buf, I.fyh, C, tws);
+  };
+  divide(0);
+  // swap: each thread takes its elements of ya and puts its odd half in their place
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const double2 ya = buf[lp<0>(idx)];
+      buf[lp<0>(idx)] = x1[e];
+      x1[e] = ya;
+    }
+  }
+  __syncthreads();
+  divide(1);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int c = dh.q(idx), y = idx - c * h;
+      double2 w = tw_at(tws, I.fy.lb, y);
+      w.y = -w.y;  // w^-y
+      const double2 yb = cmul(buf[lp<0>(idx)], w);
+      const unsigned b = (unsigned)(c * ny + y) * 16u;
+      stc(at_byte(S, b), cadd(x1[e], yb));
+      stc(at_byte(S, b + (unsigned)h * 16u), csub(x1[e], yb));
+    }
+  }
+}
+
 // ------------------------------------------------------------------ rows inverse
 
 template <int CAP, int NT>
@@ -502,7 +638,13 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
                              hipStream_t st, const Ev &ev) {
   switch (part) {
     case 0: APDVM_FFT_FORM(rowv, k_rows_forward, rows, nrows); break;
-    case 1: APDVM_FFT_FORM(colv, k_cols, cols, ncols); break;
+    case 1:
+      if (colv == 2)  // the largest columns: half the LDS, two workgroups per CU
+        APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads>), dim3(ncols), dim3(kColSplitThreads),
+                     st, insts, cols, ncols, a);
+      else
+        APDVM_FFT_FORM(colv, k_cols, cols, ncols);
+      break;
     default: APDVM_FFT_FORM(rowv, k_rows_inverse, rows, nrows); break;
   }
   return hipGetLastError();

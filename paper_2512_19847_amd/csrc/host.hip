@@ -1165,7 +1165,13 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     for (int q = 0; q < 2; ++q) {
       plans[q]->ntw = twiddles2(plans[q]->n, htw2 + q * kTwCap, &plans[q]->lb);
       plans[q]->tw2 = tw2 + q * kTwCap;
+      plans[q]->tsc = 1;
     }
+    // half-length column plan on the column table (length ny = 2 (ny / 2))
+    I.fyh = I.fy;
+    I.fyh.n = cf.ny / 2;
+    I.fyh.npass = fft_radices(cf.ny / 2, I.fyh.radix);
+    I.fyh.tsc = 2;
     uploads.push_back(std::move(u3));
     // symbols
     double *lam = reinterpret_cast<double *>(p);
@@ -1656,7 +1662,6 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
   }
   if (!cached) {
     // snapshot the current state of every instance
-    const Layout &L = c->L;
     const int P = c->parity;
     const size_t tsz = c->split ? sizeof(float) : sizeof(double);
     size_t total = 0;
