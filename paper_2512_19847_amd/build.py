@@ -41,5 +41,35 @@ def build(verbose=False):
     return LIB
 
 
+CHECK = os.path.join(HERE, "apdvm_hostcheck")
+
+
+def hostcheck_command(out=CHECK):
+    """The bounds-checked CPU build: the host runtime (host.hip as C++) against a host-only
+    stand-in of the HIP runtime and launch functions that check every launch's index space
+    instead of running kernels (csrc/hostcheck/), with AddressSanitizer and
+    UndefinedBehaviorSanitizer.  Host code only: no device code is built."""
+    d = os.path.join(HERE, "csrc", "hostcheck")
+    srcs = [os.path.join(d, f) for f in ("host_unit.cpp", "hip_host.cpp", "launch_check.cpp",
+                                         "driver.cpp")]
+    return (["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+             "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-DAPDVM_HOSTCHECK", "-Wall", "-Wno-attributes", "-Wno-unused-function",
+             "-I", d, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+            + srcs + ["-o", out])
+
+
+def build_hostcheck():
+    cmd = hostcheck_command()
+    tmp = CHECK + ".tmp"
+    cmd[-1] = tmp
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hostcheck build failed:\n" + res.stderr)
+    os.replace(tmp, CHECK)
+    return CHECK
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_hostcheck())

@@ -46,6 +46,45 @@ struct Ev {
       hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                      \
   } while (0)
 
+// ---------------------------------------------------------------- index maps
+// Host and device: the kernels use them, and the host-side bounds check (built with
+// APDVM_HOSTCHECK) walks every launch's index space through the same functions.
+
+// Work item of workgroup b out of nwork.  The hardware hands consecutive workgroups to
+// the 8 XCDs in turn; this remap gives each XCD a contiguous run of work items, so tiles
+// sharing halo rows (and FFT blocks sharing spectrum lines) meet in the same L2.
+// A bijection of [0, nwork).
+__host__ __device__ inline int xcd_remap(int b, int nwork) {
+  const int x = b & 7, i = b >> 3;
+  const int q = nwork >> 3, r = nwork & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Periodic index in [0, n).  A staged tile reaches at most its width plus the halo past
+// either end of the grid, so one add or subtract of n wraps every index of a grid of 72
+// cells or more; the division remains for smaller grids, whose halos can wrap several
+// times.
+__host__ __device__ inline int wrap_index(int g, int n) {
+  g += g < 0 ? n : (g >= n ? -n : 0);
+  if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
+  return g;
+}
+
+// Cell (row-major index y * nx + x) of element idx of the staged (TY + 2H) x (W = 64 + 2H)
+// region of the tile at (x0, y0): cell (x0 + lx - H, y0 + ly - H) taken periodically.
+// inner: the region lies inside the grid, so no index wraps.
+__host__ __device__ inline int staged_cell(int idx, int W, int H, int nx, int ny, int x0,
+                                           int y0, bool inner) {
+  const int ly = idx / W;
+  const int lx = idx - ly * W;
+  int gx = x0 + lx - H, gy = y0 + ly - H;
+  if (!inner) {
+    gx = wrap_index(gx, nx);
+    gy = wrap_index(gy, ny);
+  }
+  return gy * nx + gx;
+}
+
 constexpr int kMaxStages = 8;
 constexpr int kMaxPasses = 16;
 constexpr int kNoSlot = -1;
@@ -97,6 +136,8 @@ struct Inst {
   double *dbase;             // float64 arena
   int row_pairs_per_block;   // FFT row kernels: row pairs per workgroup
   int cols_per_block;        // FFT column kernel: whole columns per workgroup
+  int nt_slots, nd_slots;    // planes of the transport and float64 arenas
+  int tbytes;                // bytes of a transport value (8, or 4 in the FP32-split form)
 };
 
 // Work table entry: instance and the first cell / row pair / column of the block.

@@ -28,12 +28,7 @@
 
 namespace apdvm {
 
-__device__ __forceinline__ int xcd_item_fft(int nwork) {
-  const int b = blockIdx.x;
-  const int x = b & 7, i = b >> 3;
-  const int q = nwork >> 3, r = nwork & 7;
-  return x * q + (x < r ? x : r) + i;
-}
+__device__ __forceinline__ int xcd_item_fft(int nwork) { return xcd_remap(blockIdx.x, nwork); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

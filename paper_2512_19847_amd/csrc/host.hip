@@ -5,6 +5,8 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -68,6 +70,25 @@ constexpr int kStatBlocks = 512;    // workgroups of the input-field statistics 
 constexpr size_t kFlagBytes = 256;  // finite flag (unsigned) at 0, snapshot step (int64) at 8
 constexpr int kDefaultFiniteEvery = 64;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Opt-in log on stderr (environment variable APDVM_LOG set and not "0"): context creation,
+// derived time steps, autotuner choices and failed finite checks.
+bool log_on() {
+  static const bool on = [] {
+    const char *e = std::getenv("APDVM_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  return on;
+}
+__attribute__((format(printf, 1, 2))) void apdvm_log(const char *fmt, ...) {
+  if (!log_on()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[apdvm] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+}
 
 // ----------------------------------------------------------- validation helpers
 
@@ -1026,6 +1047,7 @@ apdvm_status after_fields(apdvm_ctx *c, int k, double um) {
     }
     if (ct <= 0.0) ct = 1.0;
     set_dt(c, k, derive_dt(cf, I.tau, um, ct));
+    apdvm_log("instance %d: dt %.6g derived from max |u| %.6g", k, I.dt, um);
   }
   c->has_fields[k] = 1;
   c->terms_ready = false;
@@ -1148,6 +1170,9 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.te2 = I.tau * cf.eps * cf.eps;
     I.inv_nxny = 1.0 / ((double)cf.nx * cf.ny);
     const size_t plane = (size_t)I.plane;
+    I.tbytes = (int)tsize;
+    I.nt_slots = c->L.ntrans;
+    I.nd_slots = c->L.ndbl;
     I.tbase = p;
     p += align_up(c->L.ntrans * plane * tsize);
     I.dbase = reinterpret_cast<double *>(p);
@@ -1251,6 +1276,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     apdvm_destroy(c);
     return APDVM_ERR_HIP;
   }
+  apdvm_log("create: %d instance(s), %s, %d internal stages, %zu workspace bytes (%s)", n,
+            c->split ? "FP32-split" : "FP64", c->s, c->ws_bytes, c->own_ws ? "library" : "caller");
   *out = c;
   return APDVM_OK;
 }
@@ -1368,6 +1395,8 @@ static apdvm_status collect_checks(apdvm_ctx *c) {
           hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return APDVM_ERR_HIP;
+  apdvm_log("finite check failed: state of every instance restored to step %lld (was %lld)",
+            step, (long long)c->step);
   c->step = step;
   c->terms_ready = false;
   return APDVM_ERR_NONFINITE;
@@ -1768,6 +1797,13 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     }
   }
   drop_graphs(c);  // the graphs captured the old launch shapes
+  apdvm_log("autotune (%s): tile rows / threads %d/%d %d/%d %d/%d %d/%d for classes 0 4 5 6, "
+            "solve beside the update %d", cached ? "cache" : "timed",
+            kShapeRows[c->shape[classes[0]]], kShapeThreads[c->shape[classes[0]]],
+            kShapeRows[c->shape[classes[1]]], kShapeThreads[c->shape[classes[1]]],
+            kShapeRows[c->shape[classes[2]]], kShapeThreads[c->shape[classes[2]]],
+            kShapeRows[c->shape[classes[3]]], kShapeThreads[c->shape[classes[3]]],
+            c->overlap ? 1 : 0);
   if (choice) {
     for (int k = 0; k < kNumClasses; ++k) choice[k] = 1;
     for (int m = 0; m < kNumTuned; ++m) {

@@ -10,14 +10,9 @@
 
 namespace apdvm {
 
-__device__ __forceinline__ int wrapi(int g, int n) {
-  if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
-  return g;
-}
-
 template <typename T>
 __device__ __forceinline__ double at(const T *p, int nx, int ny, int x, int y) {
-  return (double)p[(long long)wrapi(y, ny) * nx + wrapi(x, nx)];
+  return (double)p[(long long)wrap_index(y, ny) * nx + wrap_index(x, nx)];
 }
 
 // Central first derivative along (ox, oy); f = 1/(12h) for order 4, 1/(2h) for order 2.

@@ -48,24 +48,8 @@ constexpr int weno_waves_per_eu() {
   return TY == 8 || NT == 512 ? 6 : 1;
 }
 
-// Work item of this workgroup.  The hardware hands consecutive workgroups to the 8
-// XCDs in turn; this remap gives each XCD a contiguous run of work items so tiles
-// sharing halo rows meet in the same L2.
-__device__ __forceinline__ int xcd_item(int nwork) {
-  const int b = blockIdx.x;
-  const int x = b & 7, i = b >> 3;
-  const int q = nwork >> 3, r = nwork & 7;
-  return x * q + (x < r ? x : r) + i;
-}
-
-// Periodic index.  A staged tile reaches at most its width plus the halo past either end
-// of the grid, so one add or subtract of n wraps every index of a grid of 72 cells or
-// more; the division remains for smaller grids, whose halos can wrap several times.
-__device__ __forceinline__ int wrap(int g, int n) {
-  g += g < 0 ? n : (g >= n ? -n : 0);
-  if ((unsigned)g >= (unsigned)n) g = ((g % n) + n) % n;
-  return g;
-}
+__device__ __forceinline__ int xcd_item(int nwork) { return xcd_remap(blockIdx.x, nwork); }
+__device__ __forceinline__ int wrap(int g, int n) { return wrap_index(g, n); }
 
 // WENO5 of Jiang and Shu, written through 3-cell windows.  For cells g_{k-1}, g_k,
 // g_{k+1} let S = g_{k-1} - 2 g_k + g_{k+1} and D = g_{k+1} - g_{k-1}.  The Jiang-Shu
@@ -369,17 +353,12 @@ struct Stage {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * NT;
-      const int ly = idx / W;
-      const int lx = idx - ly * W;
-      int gx = x0 + lx - H, gy = y0 + ly - H;
-      if (!inner) {
-        gx = wrap(gx, nx);
-        gy = wrap(gy, ny);
-      }
       // byte offset in 32 bits (a plane holds at most 8192^2 float64 values, 512 MiB),
       // so each load takes the plane base as a scalar and this offset as its only
       // per-lane address
-      const unsigned boff = idx < PL ? (unsigned)(gy * nx + gx) * (unsigned)sizeof(G) : 0u;
+      const unsigned boff =
+          idx < PL ? (unsigned)staged_cell(idx, W, H, nx, ny, x0, y0, inner) * (unsigned)sizeof(G)
+                   : 0u;
 #pragma unroll
       for (int p = 0; p < NP; ++p) v[p][it] = ld_byte(plane[p], boff);
     }
