@@ -14,9 +14,11 @@ and the reference is sampled at the coarse cell centres through its interpolant 
 is smooth at t = 1); L1 = h^2 sum |e|, L2 = (h^2 sum e^2)^(1/2), Linf = max |e|.  Under
 these readings the space error dominates at every N (halving dt changes the errors by a
 few per cent), so both tableaux converge at the WENO3 rate, at least second order on the
-finer grids; the printed tables report much smaller errors (1e-2 in L1 at N = 33) with
-orders near 1 and 2, which these readings do not reproduce: the magnitudes are parity
-unpinned.  The printed tables are in tests/golden/convergence_tables.json."""
+finer grids.  Against the printed tables (tests/golden/convergence_tables.json): the L1
+and L2 orders of Table 2's finest pair are reproduced; the magnitudes (printed errors
+90x to 650x smaller) and Table 1's orders near one are not, under these readings or the
+others tried (the layer profile tanh(rho (y - pi/2)), alpha = 0, which is unstable): they
+stay parity unpinned."""
 
 import json
 import math
@@ -114,24 +116,64 @@ def test_fixed_grid_time_order_of_the_printed_operators():
     assert 10.0 < res[64][1] / res[128][1] < 30.0, res
 
 
-@pytest.mark.parametrize("tab", ["euler1", "paper2"])
-def test_space_time_study_of_the_tables(tab):
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
-                                       "convergence_tables.json")))[tab]
+def _table(tab):
     ref = _solve(1024, tab, _steps(1024, tab))
     w_ref = _vorticity(ref[0], ref[1])
     rows = []
-    _say(f"space-time {tab} (ref 1024^2): N, L1, L2, Linf, orders | printed N, orders")
-    for i, n in enumerate((32, 64, 128, 256, 512)):
+    for n in (32, 64, 128, 256, 512):
         u = _solve(n, tab, _steps(n, tab))
         rows.append((n,) + _norms(_vorticity(u[0], u[1]) - _sample(w_ref, n), n))
-        o = _orders(rows)
-        fmt = lambda x: "   --" if x is None else f"{x:5.2f}"
-        g = gold[i] if i < len(gold) else None
-        ptxt = "" if g is None else f" | {g[0]:4d} {fmt(g[2])} {fmt(g[4])} {fmt(g[6])}"
-        _say(f"  {n:5d} {rows[-1][1]:.4e} {rows[-1][2]:.4e} {rows[-1][3]:.4e}  "
-             + " ".join(fmt(x) for x in o) + ptxt)
-    # at least second order in L1 and L2 on the finer grids (space error dominates)
-    for r0, r1 in zip(rows[2:-1], rows[3:]):
-        assert math.log2(r0[1] / r1[1]) >= 1.8, rows
-        assert math.log2(r0[2] / r1[2]) >= 1.8, rows
+    return rows
+
+
+@pytest.fixture(scope="module")
+def tables():
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "convergence_tables.json")))
+    out = {}
+    fmt = lambda x: "   --" if x is None else f"{x:5.2f}"
+    for tab in ("euler1", "paper2"):
+        rows = _table(tab)
+        out[tab] = rows
+        _say(f"space-time {tab} (ref 1024^2): N, L1, L2, Linf, orders | printed N, L1, "
+             f"orders | ours / printed L1")
+        for i, r in enumerate(rows):
+            o = _orders(rows[:i + 1])
+            g = gold[tab][i] if i < len(gold[tab]) else None
+            ptxt = "" if g is None else (f" | {g[0]:4d} {g[1]:.3e} {fmt(g[2])} {fmt(g[4])} "
+                                         f"{fmt(g[6])} | {r[1] / g[1]:7.1f}")
+            _say(f"  {r[0]:5d} {r[1]:.4e} {r[2]:.4e} {r[3]:.4e}  "
+                 + " ".join(fmt(x) for x in o) + ptxt)
+    return gold, out
+
+
+def test_second_order_tableau_orders_match_the_printed_table(tables):
+    """Table 2 (the second-order tableau): the L1 and L2 orders of the finest printed pair
+    (129 -> 257 points, 2.02 and 1.95) are reproduced by the 128 -> 256 pair within 0.25.
+    The printed L-infinity order (2.13) is not: the layer is resolved by a few cells at
+    these N, and the maximum error sits where the WENO3 weights switch stencils."""
+    gold, rows = tables
+    g = gold["paper2"]
+    ours = _orders(rows["paper2"][:4])
+    assert abs(ours[0] - g[3][2]) <= 0.25, (ours, g[3])
+    assert abs(ours[1] - g[3][4]) <= 0.25, (ours, g[3])
+
+
+def test_space_error_dominates_under_these_readings(tables):
+    """Under the readings of the module docstring the space error dominates: the GSA Euler
+    and the second-order tableau give L1 and L2 errors within 15% of each other at every N,
+    and both converge at the WENO3 rate (at least 1.8 on the finer pairs).  The printed
+    tables differ here: there the first-order tableau's errors are 1.6x (N = 33) to 12.6x
+    (N = 257) the second-order ones and its orders stay near one, a time-error-dominated
+    study, at errors 90x to 650x smaller than these.  Which setting produces that is not
+    stated; the magnitudes and the Table 1 orders stay parity unpinned."""
+    gold, rows = tables
+    for a, b in zip(rows["euler1"], rows["paper2"]):
+        assert abs(a[1] / b[1] - 1.0) <= 0.15 and abs(a[2] / b[2] - 1.0) <= 0.15, (a, b)
+    for tab in ("euler1", "paper2"):
+        r = rows[tab]
+        for r0, r1 in zip(r[2:-1], r[3:]):
+            assert math.log2(r0[1] / r1[1]) >= 1.8, r
+            assert math.log2(r0[2] / r1[2]) >= 1.8, r
+    ratios = [gold["euler1"][i][1] / gold["paper2"][i][1] for i in range(4)]
+    assert ratios[0] > 1.5 and ratios[-1] > 10.0, ratios  # the printed tables, as stored
