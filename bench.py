@@ -52,13 +52,15 @@ sys.path.insert(0, ROOT)
 METRIC = "IMEX-RK cell-pop updates/s + %HBM roofline; FP32-split/batched vs FP64"
 UNIT = "cell-population updates/s"
 HBM_PEAK_GBS = 8000.0
+STRUCTURES = {0: "one stream", 1: "solve beside the update", 2: "one stream, theta fused into the update"}
 TIMING_STRIDE = 32
 
 
-def recorded_traffic(kernel_class, workload_name, precision, shape):
+def recorded_traffic(kernel_class, workload_name, precision, shape, structure):
     """HBM bytes per launch from the recorded counter runs, or None when they do not
-    apply to this kernel, launch shape (tile rows, threads) and workload or the kernel
-    sources changed since."""
+    apply to this kernel, launch shape (tile rows, threads), stream structure (the fused
+    one changes what the update and stage-terms launches move) and workload, or the
+    kernel sources changed since."""
     import glob
     import hashlib
 
@@ -67,7 +69,8 @@ def recorded_traffic(kernel_class, workload_name, precision, shape):
             rec = json.load(f)
         if (rec.get("kernel_class") != kernel_class or rec.get("workload") != workload_name
                 or rec.get("precision") != precision
-                or (rec.get("tile_rows"), rec.get("threads")) != shape):
+                or (rec.get("tile_rows"), rec.get("threads")) != shape
+                or (rec.get("structure", 0) == 2) != (structure == 2)):
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
@@ -249,8 +252,8 @@ def main():
     sim.set_graph(args.graph)
     cells = sum(c.nx * c.ny for c in cases)
     tiles = sim.autotune(3)
-    if args.one_stream:
-        sim.set_overlap(False)
+    if args.one_stream and sim.overlap() == 1:
+        sim.set_overlap(0)  # the same kernels, every launch on one stream
 
     # warm-up, then find the kernel class with the largest share of a step (timed steps
     # run every launch by itself)
@@ -281,7 +284,7 @@ def main():
 
     dname = apdvm.KERNEL_CLASSES[dom]
     traffic = recorded_traffic(dname, cfg["workload"], args.precision,
-                               (tiles.get(dname), tiles.get("threads_" + dname)))
+                               (tiles.get(dname), tiles.get("threads_" + dname)), sim.overlap())
     bytes_step, launches = sim.traffic(dom)
     per_launch = bytes_step / launches
     mean_s = ms_dom / n_dom / 1e3
@@ -311,7 +314,7 @@ def main():
         "config": dict(cfg, precision=args.precision,
                        tile_rows={k: tiles[k] for k in apdvm.TUNED_STENCIL},
                        threads={k: tiles["threads_" + k] for k in apdvm.TUNED_STENCIL},
-                       graph=bool(args.graph), solve_beside_update=bool(sim.overlap())),
+                       graph=bool(args.graph), stream_structure=STRUCTURES[sim.overlap()]),
         "roofline": {"bound": "hbm", "kernel": apdvm.KERNEL_CLASSES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

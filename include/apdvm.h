@@ -223,11 +223,18 @@ apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
  * side and solve (classes 0-3) run on the context's second stream while the theta-free
  * part of steps 3 and 4 (class 4) and the q part of the stage terms (class 6) run on the
  * creation stream; the stage-terms launch (class 5) waits for both.  on = 0: every launch
- * on the creation stream, in the same order.  Results are identical either way.
- * apdvm_autotune picks the faster.  Synchronises both streams when the setting changes. */
+ * on the creation stream, in the same order; results identical to on = 1 bit for bit.
+ * on = 2: every launch on the creation stream, with the update launch (class 4) after
+ * the solve completing u, Hu and L theta of the stage from its theta itself (the
+ * theta part of Algorithm 1, step 3), so the stage-terms launch reads the finished u and
+ * the intermediate u* and hu make no round trip through memory; results equal those of
+ * on = 0 and 1 to rounding (in the FP32-split form the float increment is rounded once,
+ * after the theta part, instead of before it).  apdvm_autotune picks the fastest.
+ * Synchronises both streams when the setting changes. */
 apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
 
-/* Current stream structure (1: solve beside steps 3 and 4, 0: one stream).  Host-only. */
+/* Current stream structure (1: solve beside steps 3 and 4, 0: one stream, 2: one stream
+ * with the theta completion in the update launch).  Host-only. */
 apdvm_status apdvm_get_overlap(apdvm_ctx *ctx, int32_t *on);
 
 /* Kernel classes of a step, used by the profiling and tuning calls below:

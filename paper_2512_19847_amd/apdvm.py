@@ -343,13 +343,16 @@ class Simulation:
         _check(lib().apdvm_set_graph(self.ctx, 1 if on else 0), "set_graph")
 
     def set_overlap(self, on):
-        """Helmholtz solve on a second stream beside the theta-free part of steps 3-4."""
-        _check(lib().apdvm_set_overlap(self.ctx, 1 if on else 0), "set_overlap")
+        """Stream structure: True / 1 the Helmholtz solve on a second stream beside the
+        theta-free part of steps 3-4, False / 0 one stream, 2 one stream with the theta
+        completion fused into the update launch."""
+        _check(lib().apdvm_set_overlap(self.ctx, int(on)), "set_overlap")
 
     def overlap(self):
+        """The stream structure (0, 1 or 2, as set_overlap takes it)."""
         on = c_int32()
         _check(lib().apdvm_get_overlap(self.ctx, ctypes.byref(on)), "get_overlap")
-        return bool(on.value)
+        return on.value
 
     def timing_enable(self, cls):
         _check(lib().apdvm_timing_enable(self.ctx, int(cls)), "timing_enable")

@@ -195,6 +195,10 @@ struct ArgsR {
 // q(i) = [te2 q^n - dt a_ii Hq - dt sum_j cG_j Gq(j)] kinv,   Gq(j) = Hq(j) + q(j)
 // The stage-terms launch of the stage completes u(i) = u*(i) - dt a_ii D0 theta(i) and
 // Hu(i) = hu + D0 theta(i).
+// Fused schedule (th != kNoSlot, after the solve of the stage, one stream): this launch
+// completes them itself from theta(i): out_us receives u(i) (the split form: the
+// increment du(i) = du*(i) - dt a_ii D0 theta(i)), out_hu receives Hu(i), and out_lt
+// Ltheta(i) = D0^2:B(v(i)) + D_Delta theta(i) from ddb; co is the central order.
 struct ArgsUQ {
   int stage;
   double aii;
@@ -208,6 +212,9 @@ struct ArgsUQ {
   int out_us[2];  // u*(i)
   int out_q;
   int out_hu[2], out_gq;  // hu and Gq; kNoSlot when no later stage needs them
+  int th;                 // theta(i) (float64 slot) in the fused schedule, else kNoSlot
+  int ddb, out_lt;        // fused schedule: D0^2:B(v(i)) in, Ltheta(i) out, or kNoSlot
+  int co;                 // central order (fused schedule)
 };
 
 // The q part of the stage terms E (it needs q(i) and v(i) only, so it runs before
@@ -226,8 +233,10 @@ struct ArgsG {
 // float copy to out_u; out_du receives D0.du(i), or in the last stage du0_out receives
 // the float64 D0.u^{n+1} = du0_in + D0.du(s)),
 // E = (tau/4) D0_W.B(u) + G - F(u) with G from ArgsG, D0.u,
-// Ltheta = D0^2:B(v) + D_Delta theta.  With us[0] == kNoSlot (the terms of a state set)
-// u is read from u[] and nothing of theta is used.  The same launch performs step 1 of
+// Ltheta = D0^2:B(v) + D_Delta theta.  With us[0] == kNoSlot (the terms of a state set,
+// or of a stage of the fused schedule, whose update launch completed u(i) from theta(i))
+// u is read from u[] and nothing of theta is used; in the FP32-split form ui[] then holds
+// the complete increment du(i) of a fused stage (kNoSlot for a state set).  The same launch performs step 1 of
 // the next stage (an ArgsV passed beside it); c_e_next and c_v_next are the coefficients
 // of this stage's E and v in that step (at_{k,j} and a_{k,j}), which stay in registers.
 struct ArgsE {
@@ -246,6 +255,7 @@ struct ArgsE {
   int ub[2];          // split form, last stage: float64 u^n (halo 3), else kNoSlot
   int out_ud[2];      // split form, last stage: float64 u^{n+1}
   int du0_in, du0_out;  // split form, last stage: float64 D0.u^n and D0.u^{n+1}
+  int ui[2];          // split form, fused schedule: the increment du(i) (halo 3), else kNoSlot
 };
 
 // The planes that hold one state set (or the snapshot of the finite check): five

@@ -472,6 +472,7 @@ struct apdvm_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
+  bool fused = false;  // one stream, theta completion fused into the update launch
   // Finite check every finite_every steps (0: off): device flag, step of the snapshot.
   double *d_stats = nullptr;
   unsigned *d_flag = nullptr;
@@ -596,6 +597,7 @@ std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
   a.out_du = c->split ? kNoSlot : L.Du[0];
   a.out_lt = kNoSlot;
   a.ub[0] = a.ub[1] = a.out_ud[0] = a.out_ud[1] = a.du0_in = a.du0_out = kNoSlot;
+  a.ui[0] = a.ui[1] = kNoSlot;
   if (c->split) {  // E of the state from its float64 velocity
     a.ub[0] = L.ud[P][0];
     a.ub[1] = L.ud[P][1];
@@ -611,7 +613,10 @@ std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
 // Launch list of one step starting from state set P.  Per stage: the right-hand side and
 // the Helmholtz solve go to the solve stream while the theta-free part of steps 3 and 4
 // and the q part of the stage terms run on the main stream; the stage-terms launch,
-// which completes u(i) with theta(i), joins the two.
+// which completes u(i) with theta(i), joins the two.  Fused schedule (c->fused): every
+// launch on the main stream, the update launch after the solve, completing u(i), Hu(i)
+// and Ltheta(i) from theta(i) itself, so u*(i) and hu make no round trip through memory
+// and the stage-terms launch reads u(i) (the split form: the increment du(i)).
 std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
   const Layout &L = c->L;
   const int s = c->s, Q = 1 - P;
@@ -631,11 +636,12 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     const int th = last ? L.th[Q] : L.Th[i];
     const double aii = c->A[i][i];
     const bool keep = !last && implicit_stored(c, i);
-    sync(kFork);
+    const bool fz = c->fused;
+    if (!fz) sync(kFork);
     // step 2 right-hand side (v(i) comes from the previous stage-terms launch)
     Launch l{};
     l.cls = kHelmRhs;
-    l.side = true;
+    l.side = !fz;
     ArgsR &ar = l.r;
     ar.stage = i; ar.aii = aii; ar.v[0] = v1; ar.v[1] = v2; ar.thn = L.th[P];
     // FP32-split: float64 D0.u^n of this state set; the D slots hold D0 of the increments
@@ -662,7 +668,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
       const int k = parts[m];
       l = Launch{};
       l.cls = k;
-      l.side = true;
+      l.side = !fz;
       l.sv = as;
       l.bytes = (k == kRowsFwd || k == kRowsInv) ? pd + c->spec_bytes : 2 * c->spec_bytes;
       plan.push_back(l);
@@ -690,13 +696,22 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     } else {
       au.out_hu[0] = au.out_hu[1] = au.out_gq = kNoSlot;
     }
+    au.th = au.ddb = au.out_lt = kNoSlot;
+    au.co = c->co;
+    if (fz) {
+      // theta(i) is solved: u(i) (the split form: du(i), in the u* slots), Hu(i), Ltheta(i)
+      au.th = th;
+      if (!c->split) { au.out_us[0] = u1; au.out_us[1] = u2; }
+      if (keep) { au.ddb = L.ddb; au.out_lt = L.Lt[i]; }
+    }
     // the partner is u^n for the first stage: read once with u^n (the split form reads
     // only the partner)
     const int reads = 2 + (i == 1 || c->split ? 0 : 2) + 3 + 2 * au.nH + au.nG;
     l.bytes = (reads + 1 + 2 + (keep ? 3 : 0)) * pt;
+    if (fz) l.bytes += pd + (keep ? 2 * pt : 0);  // theta in; ddb in, Ltheta out
     plan.push_back(l);
     plan.push_back(grad_q_launch(c, qi, v1, v2));
-    sync(kJoin);
+    if (!fz) sync(kJoin);
     // u(i) from theta(i), terms of this stage for later stages, and step 1 of the next
     // stage; the last stage's terms are the next step's stage-0 terms
     l = Launch{};
@@ -704,6 +719,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ArgsE &ae = l.e;
     ae.us[0] = L.Us[0]; ae.us[1] = L.Us[1]; ae.u[0] = ae.u[1] = kNoSlot;
     ae.ub[0] = ae.ub[1] = ae.out_ud[0] = ae.out_ud[1] = ae.du0_in = ae.du0_out = kNoSlot;
+    ae.ui[0] = ae.ui[1] = kNoSlot;
     if (c->split) {
       // increment form on the float64 base u^n; the last stage writes the float64 state
       // u^{n+1} and its D0.u, the next step's D0.u^n
@@ -732,6 +748,21 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
         l.bytes += 6 * pd - pt;
       else  // float64 base u^n
         l.bytes += 2 * pd;
+    }
+    if (fz) {
+      // u(i) (or du(i)) is complete: no theta, no u* and no Hu or Ltheta here
+      ae.us[0] = ae.us[1] = kNoSlot;
+      ae.th = kNoSlot;
+      ae.hu[0] = ae.hu[1] = kNoSlot;
+      ae.ddb = kNoSlot;
+      ae.out_lt = kNoSlot;
+      if (c->split) {  // the increment du(i) on the float64 base; out_u the float u(i)
+        ae.ui[0] = L.Us[0]; ae.ui[1] = L.Us[1];
+      } else {  // u(i) as the update launch wrote it
+        ae.u[0] = u1; ae.u[1] = u2;
+        ae.out_u[0] = ae.out_u[1] = kNoSlot;
+      }
+      l.bytes -= pd + (keep ? 6 : 0) * pt + (c->split ? 0 : 2 * pt);
     }
     if (last)
       fill_relax(c, 1, Q, l.v, ae, pt, l.bytes);  // next step, state set Q
@@ -1574,12 +1605,18 @@ apdvm_status apdvm_set_graph(apdvm_ctx *c, int32_t on) {
 }
 
 apdvm_status apdvm_set_overlap(apdvm_ctx *c, int32_t on) {
-  if (!c || (on != 0 && on != 1)) return APDVM_ERR_ARG;
-  if (c->overlap == (on != 0)) return APDVM_OK;
+  if (!c || on < 0 || on > 2) return APDVM_ERR_ARG;
+  const bool ov = on == 1, fz = on == 2;
+  if (c->overlap == ov && c->fused == fz) return APDVM_OK;
   if (hipStreamSynchronize(c->stream) != hipSuccess ||
       hipStreamSynchronize(c->side) != hipSuccess)
     return APDVM_ERR_HIP;
-  c->overlap = on != 0;
+  c->overlap = ov;
+  if (c->fused != fz) {
+    c->fused = fz;
+    c->plan[0] = build_plan(c, 0);
+    c->plan[1] = build_plan(c, 1);
+  }
   for (int p = 0; p < 2; ++p)  // the graphs captured the other stream structure
     if (c->graph_exec[p]) {
       (void)hipGraphExecDestroy(c->graph_exec[p]);
@@ -1590,7 +1627,7 @@ apdvm_status apdvm_set_overlap(apdvm_ctx *c, int32_t on) {
 
 apdvm_status apdvm_get_overlap(apdvm_ctx *c, int32_t *on) {
   if (!c || !on) return APDVM_ERR_ARG;
-  *on = c->overlap ? 1 : 0;
+  *on = c->fused ? 2 : c->overlap ? 1 : 0;
   return APDVM_OK;
 }
 
@@ -1655,7 +1692,7 @@ static void drop_graphs(apdvm_ctx *c) {
 // tuning.
 static std::string tune_key(const apdvm_ctx *c) {
   std::ostringstream k;
-  k << "gfx950 shapes4 overlap gradq colmajor prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
+  k << "gfx950 shapes4 overlap gradq colmajor fused prec=" << (c->split ? "fp32split" : "fp64") << " s=" << c->s << " n=" << c->n
     << " cells=" << (long long)c->cells << " weno=" << c->wo << " central=" << c->co;
   int mx = 0;
   for (const auto &cf : c->cfg) mx = cf.nx > mx ? cf.nx : mx;
@@ -1683,7 +1720,8 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
         for (int m = 0; m < kNumTuned; ++m) good = good && (rest >> t[m]) && t[m] >= 0 && t[m] < kNumShapes;
         if (good && rest >> ov) {
           for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = t[m];
-          if (apdvm_set_overlap(c, ov ? 1 : 0) != APDVM_OK) return APDVM_ERR_HIP;
+          if (apdvm_set_overlap(c, ov >= 0 && ov <= 2 ? ov : 1) != APDVM_OK)
+            return APDVM_ERR_HIP;
           cached = true;
         }
       }
@@ -1746,21 +1784,22 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       }
       c->shape[cls] = best_si;
     }
-    // the solve beside steps 3 and 4 or after them: whole steps timed on the main stream
+    // the stream structure (one stream, the solve beside steps 3 and 4, or one stream with
+    // the theta completion fused into the update): whole steps timed on the main stream
     ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
     c->use_graph = graph;  // the stream structures compete in the caller's launch mode
     drop_graphs(c);        // graphs of earlier launch shapes
     if (ok) {
-      // two passes over the two structures, interleaved (off, on, off, on) so that a drift
-      // of the clock or of other work on the device hits both alike; each timed run has at
-      // least 2 steps_per_trial steps and, once the step time is known, enough steps for
-      // about 10 ms
-      double tov[2] = {0.0, 0.0};
+      // two passes over the three structures, interleaved (0, 1, 2, 0, 1, 2) so that a
+      // drift of the clock or of other work on the device hits all alike; each timed run
+      // has at least 2 steps_per_trial steps and, once the step time is known, enough
+      // steps for about 10 ms
+      double tov[3] = {0.0, 0.0, 0.0};
       int nsteps = 2 * steps_per_trial;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-      for (int t = 0; ok && t < 4; ++t) {
-        const int on = t & 1;
+      for (int t = 0; ok && t < 6; ++t) {
+        const int on = t % 3;
         // two warm-up steps: in graph mode each parity's graph is captured and uploaded
         // before the timed steps
         ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 2) == APDVM_OK;
@@ -1778,7 +1817,10 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       }
       if (e0) (void)hipEventDestroy(e0);
       if (e1) (void)hipEventDestroy(e1);
-      ok = ok && apdvm_set_overlap(c, tov[1] <= tov[0] ? 1 : 0) == APDVM_OK;
+      int best = 1;  // ties keep the solve beside the update
+      for (int on = 0; on < 3; ++on)
+        if (tov[on] < tov[best]) best = on;
+      ok = ok && apdvm_set_overlap(c, best) == APDVM_OK;
     }
     c->parity = P;
     ok = ok && copy_state(false) && hipStreamSynchronize(c->stream) == hipSuccess;
@@ -1793,17 +1835,17 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       std::ofstream out(cache, std::ios::app);
       out << key << "|";
       for (int m = 0; m < kNumTuned; ++m) out << c->shape[classes[m]] << " ";
-      out << (c->overlap ? 1 : 0) << "\n";
+      out << (c->fused ? 2 : c->overlap ? 1 : 0) << "\n";
     }
   }
   drop_graphs(c);  // the graphs captured the old launch shapes
   apdvm_log("autotune (%s): tile rows / threads %d/%d %d/%d %d/%d %d/%d for classes 0 4 5 6, "
-            "solve beside the update %d", cached ? "cache" : "timed",
+            "stream structure %d", cached ? "cache" : "timed",
             kShapeRows[c->shape[classes[0]]], kShapeThreads[c->shape[classes[0]]],
             kShapeRows[c->shape[classes[1]]], kShapeThreads[c->shape[classes[1]]],
             kShapeRows[c->shape[classes[2]]], kShapeThreads[c->shape[classes[2]]],
             kShapeRows[c->shape[classes[3]]], kShapeThreads[c->shape[classes[3]]],
-            c->overlap ? 1 : 0);
+            c->fused ? 2 : c->overlap ? 1 : 0);
   if (choice) {
     for (int k = 0; k < kNumClasses; ++k) choice[k] = 1;
     for (int m = 0; m < kNumTuned; ++m) {

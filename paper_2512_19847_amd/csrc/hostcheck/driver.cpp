@@ -124,13 +124,18 @@ void run(const Scenario &sc) {
   CALL(apdvm_step(c, 2), APDVM_OK);
   CALL(apdvm_set_overlap(c, 0), APDVM_OK);
   CALL(apdvm_step(c, 1), APDVM_OK);
+  CALL(apdvm_set_overlap(c, 2), APDVM_OK);  // fused schedule
+  CALL(apdvm_step(c, 2), APDVM_OK);
+  CALL(apdvm_set_overlap(c, 3), APDVM_ERR_ARG);
   CALL(apdvm_set_overlap(c, 1), APDVM_OK);
   int32_t ov = -1;
   CALL(apdvm_get_overlap(c, &ov), APDVM_OK);
   CALL(apdvm_set_graph(c, 1), APDVM_OK);
   CALL(apdvm_step(c, 3), APDVM_OK);  // both parities captured, then replayed
   CALL(apdvm_set_overlap(c, 0), APDVM_OK);
-  CALL(apdvm_step(c, 2), APDVM_OK);  // graphs of the other stream structure
+  CALL(apdvm_step(c, 2), APDVM_OK);  // graphs of the other stream structures
+  CALL(apdvm_set_overlap(c, 2), APDVM_OK);
+  CALL(apdvm_step(c, 3), APDVM_OK);
   CALL(apdvm_set_overlap(c, 1), APDVM_OK);
   for (int cls = 0; cls < APDVM_NUM_KERNEL_CLASSES; ++cls) {
     CALL(apdvm_timing_enable(c, cls), APDVM_OK);
@@ -306,6 +311,8 @@ int self_test() {
   a.out_us[1] = s++;
   a.out_q = s++;
   a.out_hu[0] = a.out_hu[1] = a.out_gq = kNoSlot;
+  a.th = a.ddb = a.out_lt = kNoSlot;
+  a.co = 4;
   auto &k = hostcheck::counters();
   int caught = 0, cases = 0;
   auto run = [&](const char *what, bool bad, auto &&fn) {

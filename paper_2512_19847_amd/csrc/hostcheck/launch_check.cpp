@@ -7,7 +7,7 @@
 //    lies in device memory;
 //  * every stencil tile lies on its instance's grid, and the tiles cover every cell of
 //    every instance exactly once;
-//  * every staged halo element (halos of 3, 4 and 5 cells) and every wrapped neighbour
+//  * every staged halo element (halos of 1 to 5 cells) and every wrapped neighbour
 //    index is the periodic image of its cell, inside the plane;
 //  * every plane slot an argument names exists in its arena (transport or float64),
 //    the arenas and tables lie in device memory without overlapping, and no launch
@@ -189,7 +189,7 @@ void check_tiles(const Inst *insts, const Work *work, int nwork, int TY, size_t 
     char &c = cv[(size_t)(y0 / TY) * tx + x0 / kTileX];
     if (c) fail("tile (%d, %d) of instance %d listed twice", x0, y0, w->inst);
     c = 1;
-    for (int H = kHalo; H <= kHalo + 2; ++H) {
+    for (int H = 1; H <= kHalo + 2; ++H) {
       const int W = kTileX + 2 * H, PL = W * (TY + 2 * H);
       const bool inner = x0 >= H && x0 + kTileX + H <= nx && y0 >= H && y0 + TY + H <= ny;
       for (int idx = 0; idx < PL; ++idx) {
@@ -280,6 +280,14 @@ hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Wor
     for (int j = 0; j < a.nG; ++j) s.r(0, a.G[j]);
     s.w(0, a.out_q);
     s.w(0, a.out_gq, true);
+    // fused schedule: theta(i) in, Ltheta(i) from D0^2:B(v(i))
+    s.r(1, a.th, true);
+    if (a.out_lt != kNoSlot) {
+      if (a.th == kNoSlot) fail("update_uq: L theta without theta");
+      s.r(0, a.ddb);
+      s.w(0, a.out_lt);
+    }
+    if (a.th != kNoSlot && a.co != 2 && a.co != 4) fail("update_uq: central order %d", a.co);
     check_tiles(insts, work, nwork, kRowsOfShape[si & 3], sizeof(T), s);
   });
   return hipSuccess;
@@ -318,6 +326,10 @@ hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const W
           s.w(0, a.hu[m]);
           s.inplace.insert({0, a.hu[m]});
         }
+      } else if (a.ui[m] != kNoSlot) {  // split form, fused schedule: du(i) on u^n
+        if (sizeof(T) != 4) fail("stage_terms: an increment in the float64 form");
+        s.r(0, a.ui[m]);
+        s.w(0, a.out_u[m]);
       } else {
         s.r(0, a.u[m]);
       }

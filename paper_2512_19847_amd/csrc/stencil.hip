@@ -663,6 +663,17 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
   }
 }
 
+// D0 theta (both components) and D_Delta theta at staged index c of theta in LDS (row
+// length w), in float64: the same stencils and factors as the stage-terms kernel's.
+template <int CO>
+__device__ __forceinline__ void theta_terms(const double *sT, int c, int w, const Inst &I,
+                                            double &dx, double &dy, double &lap) {
+  using C = Central<CO>;
+  dx = C::d1(sT, c, 1, C::f1(I.ihx));
+  dy = C::d1(sT, c, w, C::f1(I.ihy));
+  lap = C::d2(sT, c, 1, C::f2(I.ihx)) + C::d2(sT, c, w, C::f2(I.ihy));
+}
+
 // ------------------------------------------------------------------ steps 3 and 4
 
 // Everything of steps 3 and 4 that does not involve theta(i): q(i) in full, and u(i)
@@ -679,7 +690,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   using Gm = Geo<TY, NT>;
   // v1, v2 and one partner component at a time, halved for the fluxes (the second
   // component arrives in registers during the first round and replaces the first)
-  __shared__ T sV1[Gm::PL], sV2[Gm::PL], sP[Gm::PL];
+  // (one buffer, which the fused schedule reuses for theta(i) after the flux rounds)
+  using STh = Stage<TY, NT, 1, double, 2>;  // theta(i) with the reach of D0 and D_Delta
+  static_assert(STh::PL * sizeof(double) <= 3 * Gm::PL * sizeof(T), "theta staging");
+  __shared__ __align__(16) T sVP[3 * Gm::PL];
+  T *const sV1 = sVP, *const sV2 = sVP + Gm::PL, *const sP = sVP + 2 * Gm::PL;
   __shared__ T fx[Gm::FXN], fy[Gm::FYN];
   const Work wk = work[xcd_item(nwork)];
   const Inst &I = insts[wk.inst];
@@ -728,6 +743,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     dv[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
+  // fused schedule: theta(i) staged with a halo of 2 into the flux planes, now free
+  const bool fused = a.th != kNoSlot;
+  double *const sT = reinterpret_cast<double *>(sVP);
+  if (fused) {
+    STh sth;
+    const Gp<const double> gt[1] = {dplane(I, a.th)};
+    sth.load(gt, nx, ny, wk.a, wk.b);
+    double *lt[1] = {sT};
+    sth.store(lt, 1.0);
+    __syncthreads();
+  }
 
   if (!col) return;
   // pointwise inputs of the updates (state n and the stage history), loaded after the
@@ -757,6 +783,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
   const double dt = I.dt, te2 = I.te2, kinv = I.kinv[a.stage], aii = a.aii;
   const double htau = 0.5 * I.tau;
+  const double cth = dt * aii;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int gy = wk.b + ty0 + Gm::WV * r;
@@ -764,14 +791,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const Cell g = cell_at<T>(gy * nx + gx);
     const double Hq = htau * (double)dv[r];
     const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
-    *tcell<T>(I, a.out_us[0], g) = (T)(un1[r] - dt * (h1[r] + aii * (double)hu1[r]));
-    *tcell<T>(I, a.out_us[1], g) = (T)(un2[r] - dt * (h2[r] + aii * (double)hu2[r]));
-    *tcell<T>(I, a.out_q, g) = (T)q;
-    if (a.out_hu[0] != kNoSlot) {
-      *tcell<T>(I, a.out_hu[0], g) = hu1[r];
-      *tcell<T>(I, a.out_hu[1], g) = hu2[r];
-      *tcell<T>(I, a.out_gq, g) = (T)(Hq + q);
+    const double us1 = un1[r] - dt * (h1[r] + aii * (double)hu1[r]);
+    const double us2 = un2[r] - dt * (h2[r] + aii * (double)hu2[r]);
+    if (fused) {
+      // the theta part of step 3, with theta(i) of this stage already solved
+      double d0x, d0y, lap;
+      const int ct = (ty0 + Gm::WV * r + 2) * STh::W + tx + 2;
+      if (a.co == 2)
+        theta_terms<2>(sT, ct, STh::W, I, d0x, d0y, lap);
+      else
+        theta_terms<4>(sT, ct, STh::W, I, d0x, d0y, lap);
+      *tcell<T>(I, a.out_us[0], g) = (T)(us1 - cth * d0x);
+      *tcell<T>(I, a.out_us[1], g) = (T)(us2 - cth * d0y);
+      if (a.out_hu[0] != kNoSlot) {
+        *tcell<T>(I, a.out_hu[0], g) = (T)((double)hu1[r] + d0x);
+        *tcell<T>(I, a.out_hu[1], g) = (T)((double)hu2[r] + d0y);
+      }
+      if (a.out_lt != kNoSlot)
+        *tcell<T>(I, a.out_lt, g) = (T)((double)*tcell<T>(I, a.ddb, g) + lap);
+    } else {
+      *tcell<T>(I, a.out_us[0], g) = (T)us1;
+      *tcell<T>(I, a.out_us[1], g) = (T)us2;
+      if (a.out_hu[0] != kNoSlot) {
+        *tcell<T>(I, a.out_hu[0], g) = hu1[r];
+        *tcell<T>(I, a.out_hu[1], g) = hu2[r];
+      }
     }
+    *tcell<T>(I, a.out_q, g) = (T)q;
+    if (a.out_hu[0] != kNoSlot) *tcell<T>(I, a.out_gq, g) = (T)(Hq + q);
   }
 }
 
@@ -814,6 +861,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   }
 }
 
+template <typename T, int TY, int NT, int CO, typename SU>
+__device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, const ArgsE &a,
+                                               double *sU1, double *sU2, double f1x,
+                                               double f1y);
+
 // FP32-split completion of a stage (the increment form of k_stage_terms, below), with
 // the staged velocity in float64.  Phase 1 writes the theta terms of the interior cells
 // (Hu, Ltheta) and stages the increment du(i) = du*(i) - dt a_ii D0 theta(i).  Phase 2
@@ -838,7 +890,6 @@ __device__ __forceinline__ void stage_increment(const Inst &I, const Work &wk, c
   const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
   const int gx = wk.a + tx;
   const bool col = gx < nx;
-  const bool last = a.out_ud[0] != kNoSlot;
   // phase 1
   if (col) {
     const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
@@ -869,6 +920,23 @@ __device__ __forceinline__ void stage_increment(const Inst &I, const Work &wk, c
     sU2[idx] = (double)su.v[1][it] - cth * C::d1(sT, c, SWW, f1y);
   }
   __syncthreads();
+  increment_tail<T, TY, NT, CO, SU>(I, wk, a, sU1, sU2, f1x, f1y);
+}
+
+// Phases 2 and 3 of the FP32-split completion, on the staged increment du(i) in sU1, sU2
+// (from phase 1, or in the fused schedule the increment the update launch completed).
+template <typename T, int TY, int NT, int CO, typename SU>
+__device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, const ArgsE &a,
+                                               double *sU1, double *sU2, double f1x,
+                                               double f1y) {
+  using Gm = Geo<TY, NT>;
+  using C = Central<CO>;
+  constexpr int R = C::R;
+  const int nx = I.nx, ny = I.ny;
+  const int tx = threadIdx.x & 63, ty0 = threadIdx.x >> 6;
+  const int gx = wk.a + tx;
+  const bool col = gx < nx;
+  const bool last = a.out_ud[0] != kNoSlot;
   // phase 2: u^n on the staged region (float64, or its float copy when no float64 base
   // is given)
   double b1[SU::IT], b2[SU::IT];
@@ -1081,12 +1149,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       }
     }
     }  // !INC
-  } else if constexpr (INC) {  // the terms of a state: its float64 velocity
-    Stage<TY, NT, 2, double> su;
-    const Gp<const double> g2[2] = {dplane(I, a.ub[0]), dplane(I, a.ub[1])};
-    su.load(g2, nx, ny, wk.a, wk.b);
-    double *l2[2] = {sU1, sU2};
-    su.store(l2, 0.5);
+  } else if constexpr (INC) {
+    if (a.ui[0] != kNoSlot) {
+      // a stage of the fused schedule: the update launch completed the increment du(i)
+      SU su;
+      const Gp<const T> g2[2] = {tplane<T>(I, a.ui[0]), tplane<T>(I, a.ui[1])};
+      su.load(g2, nx, ny, wk.a, wk.b);
+      double *l2[2] = {sU1, sU2};
+      su.store(l2, 1.0);
+      __syncthreads();
+      increment_tail<T, TY, NT, CO, SU>(I, wk, a, sU1, sU2, C::f1(I.ihx), C::f1(I.ihy));
+    } else {  // the terms of a state: its float64 velocity
+      Stage<TY, NT, 2, double> su;
+      const Gp<const double> g2[2] = {dplane(I, a.ub[0]), dplane(I, a.ub[1])};
+      su.load(g2, nx, ny, wk.a, wk.b);
+      double *l2[2] = {sU1, sU2};
+      su.store(l2, 0.5);
+    }
   } else {
     Stage<TY, NT, 2, T> su;
     const Gp<const T> g2[2] = {tplane<T>(I, a.u[0]), tplane<T>(I, a.u[1])};

@@ -239,19 +239,22 @@ def test_timing_hooks_and_traffic():
 
 def test_autotune_restores_state():
     """After autotuning, stepping gives bitwise the run of a fresh context forced to the
-    same launch shapes (the tuner restored state, step counter and parity)."""
+    same launch shapes and stream structure (the tuner restored state, step counter and
+    parity)."""
     import torch
 
     st = _state()
     sim = _sim(stream=torch.cuda.Stream())
     sim.set_fields(0, *st)
     choice = sim.autotune(2)
+    structure = sim.overlap()
     assert sim.info(0)[2] == 0
     sim.step(3)
     a = sim.get_fields(0)
     sim.close()
     sim = _sim()
     sim.set_tuning(choice)
+    sim.set_overlap(structure)
     sim.set_fields(0, *st)
     sim.step(3)
     b = sim.get_fields(0)

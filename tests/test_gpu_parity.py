@@ -56,15 +56,25 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _run_gpu(cases, tab, nsteps, precision=0, shape=None, wo=5, co=4):
+def _stream():
+    import torch
+    return torch.cuda.Stream()
+
+
+def _run_gpu(cases, tab, nsteps, precision=0, shape=None, wo=5, co=4, structure=None,
+             graph=False):
     apdvm = _apdvm()
     sim = apdvm.Simulation([dict(nx=c["state"][0].shape[1], ny=c["state"][0].shape[0],
                                  eps=c["eps"], tau=c["tau"], dt=c["dt"],
                                  lx=c.get("lx", 2 * np.pi), ly=c.get("ly", 2 * np.pi))
                             for c in cases], tableau=tab, precision=precision,
-                           weno_order=wo, central_order=co)
+                           weno_order=wo, central_order=co,
+                           stream=_stream() if graph else None)
     if shape is not None:
         sim.set_tuning(*shape)
+    if structure is not None:
+        sim.set_overlap(structure)
+    sim.set_graph(graph)
     for k, c in enumerate(cases):
         sim.set_fields(k, *c["state"])
     sim.step(nsteps)
@@ -308,3 +318,24 @@ def test_ill_prepared_data(tab):
     _say(f"  after one step max|div u| {div(got1):.3e}; relerr after three {err}")
     assert max(err.values()) <= TOL, err
     assert div(got1) < 1e-2 * div(st)
+
+
+@pytest.mark.parametrize("tab,wo,co", [("ars443", 5, 4), ("paper2", 5, 4), ("euler1", 3, 2),
+                                       ("typea2", 5, 4), ("ars443", 3, 4)])
+@pytest.mark.parametrize("graph", [False, True])
+def test_fused_schedule_matches_oracle(tab, wo, co, graph):
+    """Stream structure 2: the update launch completes u, Hu and L theta from theta after
+    the solve (one stream).  Ragged 96 x 72 and 64 x 48 instances in one context, kinetic
+    and stiff, every stage kind of the tableau (stored Hu and L theta, the last stage),
+    launched directly and replayed as graphs."""
+    cases = []
+    for k, (nx, ny, eps, tau) in enumerate([(96, 72, 0.05, 0.3), (64, 48, 1e-6, 0.05)]):
+        st = wl.random_divfree(nx, ny, kmax=4, rms=0.1, seed=70 + k)
+        cases.append(dict(state=st, eps=eps, tau=tau, dt=0.01))
+    _say(f"case fused schedule {tab} weno{wo} central{co} graph={graph}")
+    got = _run_gpu(cases, tab, 5, wo=wo, co=co, structure=2, graph=graph)
+    for k, c in enumerate(cases):
+        ref = _oracle(c["state"], c["eps"], c["tau"], c["dt"], tab, 5, wo=wo, co=co)
+        err = _relerr(got[k], ref, kinetic_floor=tab == "typea2")
+        _say(f"  instance {k} relerr {err}")
+        assert max(err.values()) <= TOL, (k, err)
