@@ -1765,25 +1765,36 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
     c->use_graph = false;
     c->timed_stride = 1;
     bool ok = copy_state(true);
-    for (int m = 0; ok && m < kNumTuned; ++m) {
-      const int cls = classes[m];
-      double best = 1e300;
-      int best_si = 1;
-      for (int si = 0; ok && si < kNumShapes; ++si) {
-        c->shape[cls] = si;
-        ok = apdvm_step(c, 1) == APDVM_OK;  // warm-up with this choice
-        ok = ok && apdvm_timing_enable(c, cls) == APDVM_OK;
-        ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
-        int64_t nl = 0;
-        double ms = 0.0;
-        ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
-        if (ok && ms < best) {
-          best = ms;
-          best_si = si;
+    // launch shapes, once with the split kernels (structures 0 and 1) and once with the
+    // fused update and stage-terms kernels of structure 2, whose registers and bytes differ
+    int shp[2][kNumTuned];
+    for (int f = 0; f < 2; ++f) {
+      ok = ok && apdvm_set_overlap(c, f ? 2 : 1) == APDVM_OK;
+      for (int m = 0; ok && m < kNumTuned; ++m) {
+        const int cls = classes[m];
+        double best = 1e300;
+        int best_si = 1;
+        for (int si = 0; ok && si < kNumShapes; ++si) {
+          c->shape[cls] = si;
+          ok = apdvm_step(c, 1) == APDVM_OK;  // warm-up with this choice
+          ok = ok && apdvm_timing_enable(c, cls) == APDVM_OK;
+          ok = ok && apdvm_step(c, steps_per_trial) == APDVM_OK;
+          int64_t nl = 0;
+          double ms = 0.0;
+          ok = ok && apdvm_timing_read(c, &nl, &ms) == APDVM_OK;
+          if (ok && ms < best) {
+            best = ms;
+            best_si = si;
+          }
         }
+        c->shape[cls] = best_si;
+        shp[f][m] = best_si;
       }
-      c->shape[cls] = best_si;
+      ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
     }
+    auto use_shapes = [&](int structure) {
+      for (int m = 0; m < kNumTuned; ++m) c->shape[classes[m]] = shp[structure == 2][m];
+    };
     // the stream structure (one stream, the solve beside steps 3 and 4, or one stream with
     // the theta completion fused into the update): whole steps timed on the main stream
     ok = ok && apdvm_timing_enable(c, -1) == APDVM_OK;
@@ -1802,6 +1813,8 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
         const int on = t % 3;
         // two warm-up steps: in graph mode each parity's graph is captured and uploaded
         // before the timed steps
+        use_shapes(on);
+        drop_graphs(c);
         ok = apdvm_set_overlap(c, on) == APDVM_OK && apdvm_step(c, 2) == APDVM_OK;
         ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
         ok = ok && apdvm_step(c, nsteps) == APDVM_OK;
@@ -1820,6 +1833,7 @@ apdvm_status apdvm_autotune(apdvm_ctx *c, int32_t steps_per_trial, int32_t *choi
       int best = 1;  // ties keep the solve beside the update
       for (int on = 0; on < 3; ++on)
         if (tov[on] < tov[best]) best = on;
+      use_shapes(best);
       ok = ok && apdvm_set_overlap(c, best) == APDVM_OK;
     }
     c->parity = P;

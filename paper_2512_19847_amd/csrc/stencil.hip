@@ -683,7 +683,7 @@ __device__ __forceinline__ void theta_terms(const double *sT, int c, int w, cons
 // The stage-terms kernel of the stage subtracts dt a_ii D0 theta(i) from u*(i).  In the
 // FP32-split form (a.un[0] == kNoSlot) the kernel stores the increment u*(i) - u^n: it is
 // of size dt |Hu|, so its float rounding is that much smaller than the rounding of u.
-template <typename T, int TY, int NT, int WO>
+template <typename T, int TY, int NT, int WO, bool FUSED>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_update_uq(const Inst *__restrict__ insts,
                                                                const Work *__restrict__ work,
                                                                int nwork, ArgsUQ a) {
@@ -737,19 +737,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     keep(hu2[r]);
   }
   __syncthreads();
+  // fused schedule: theta(i) staged with a halo of 2 into the flux planes once they are
+  // free; its loads are issued before the last flux round, which hides their latency
+  constexpr bool fused = FUSED;  // a.th != kNoSlot (the launch picks the instantiation)
+  double *const sT = reinterpret_cast<double *>(sVP);
+  STh sth;
+  if constexpr (fused) {
+    const Gp<const double> gt[1] = {dplane(I, a.th)};
+    sth.load(gt, nx, ny, wk.a, wk.b);
+  }
   // div v without dissipation
   faces<TY, NT, WO, T, false, false>(fx, fy, sV1, sV1, T(1), sV2, sV2, T(1));
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r)
     dv[r] = face_dx<TY>(fx, tx, ty0 + Gm::WV * r, ihx) + face_dy<TY>(fy, tx, ty0 + Gm::WV * r, ihy);
-  // fused schedule: theta(i) staged with a halo of 2 into the flux planes, now free
-  const bool fused = a.th != kNoSlot;
-  double *const sT = reinterpret_cast<double *>(sVP);
-  if (fused) {
-    STh sth;
-    const Gp<const double> gt[1] = {dplane(I, a.th)};
-    sth.load(gt, nx, ny, wk.a, wk.b);
+  if constexpr (fused) {
     double *lt[1] = {sT};
     sth.store(lt, 1.0);
     __syncthreads();
@@ -793,7 +796,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     const double q = (te2 * qn[r] - dt * aii * Hq - dt * hg[r]) * kinv;
     const double us1 = un1[r] - dt * (h1[r] + aii * (double)hu1[r]);
     const double us2 = un2[r] - dt * (h2[r] + aii * (double)hu2[r]);
-    if (fused) {
+    if constexpr (fused) {
       // the theta part of step 3, with theta(i) of this stage already solved
       double d0x, d0y, lap;
       const int ct = (ty0 + Gm::WV * r + 2) * STh::W + tx + 2;
@@ -1308,19 +1311,29 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
 template <typename T>
 hipError_t launch_update_uq(int si, int wo, int co, const Inst *insts, const Work *work,
                             int nwork, const ArgsUQ &a, hipStream_t st, const Ev &ev) {
-  (void)co;  // no central difference in this kernel
+  (void)co;  // the central order of the fused theta part travels in a.co
   const dim3 g(nwork);
   const int key = si * 2 + (wo == 5 ? 0 : 1);
+#define APDVM_UQ(TY, NT, WO)                                                                   \
+  do {                                                                                         \
+    if (a.th != kNoSlot)                                                                       \
+      APDVM_LAUNCH(ev, (k_update_uq<T, TY, NT, WO, true>), g, dim3(NT), st, insts, work, nwork, \
+                   a);                                                                         \
+    else                                                                                       \
+      APDVM_LAUNCH(ev, (k_update_uq<T, TY, NT, WO, false>), g, dim3(NT), st, insts, work,      \
+                   nwork, a);                                                                  \
+  } while (0)
   switch (key) {
-    case 0: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
-    case 1: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
-    case 2: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 256, 5>), g, dim3(256), st, insts, work, nwork, a); break;
-    case 3: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 256, 3>), g, dim3(256), st, insts, work, nwork, a); break;
-    case 4: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
-    case 5: APDVM_LAUNCH(ev, (k_update_uq<T, 16, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
-    case 6: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 512, 5>), g, dim3(512), st, insts, work, nwork, a); break;
-    default: APDVM_LAUNCH(ev, (k_update_uq<T, 8, 512, 3>), g, dim3(512), st, insts, work, nwork, a); break;
+    case 0: APDVM_UQ(8, 256, 5); break;
+    case 1: APDVM_UQ(8, 256, 3); break;
+    case 2: APDVM_UQ(16, 256, 5); break;
+    case 3: APDVM_UQ(16, 256, 3); break;
+    case 4: APDVM_UQ(16, 512, 5); break;
+    case 5: APDVM_UQ(16, 512, 3); break;
+    case 6: APDVM_UQ(8, 512, 5); break;
+    default: APDVM_UQ(8, 512, 3); break;
   }
+#undef APDVM_UQ
   return hipGetLastError();
 }
 template <typename T>
