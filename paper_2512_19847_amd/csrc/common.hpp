@@ -256,6 +256,8 @@ struct ArgsE {
   int out_ud[2];      // split form, last stage: float64 u^{n+1}
   int du0_in, du0_out;  // split form, last stage: float64 D0.u^n and D0.u^{n+1}
   int ui[2];          // split form, fused schedule: the increment du(i) (halo 3), else kNoSlot
+  int q;              // split form, fused schedule: q(i) (halo 3), G formed here from q and
+                      // v (g[] unused); else kNoSlot
 };
 
 // The planes that hold one state set (or the snapshot of the finite check): five

@@ -598,6 +598,7 @@ std::vector<Launch> stage0_launches(const apdvm_ctx *c, int P) {
   a.out_lt = kNoSlot;
   a.ub[0] = a.ub[1] = a.out_ud[0] = a.out_ud[1] = a.du0_in = a.du0_out = kNoSlot;
   a.ui[0] = a.ui[1] = kNoSlot;
+  a.q = kNoSlot;
   if (c->split) {  // E of the state from its float64 velocity
     a.ub[0] = L.ud[P][0];
     a.ub[1] = L.ud[P][1];
@@ -710,7 +711,10 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     l.bytes = (reads + 1 + 2 + (keep ? 3 : 0)) * pt;
     if (fz) l.bytes += pd + (keep ? 2 * pt : 0);  // theta in; ddb in, Ltheta out
     plan.push_back(l);
-    plan.push_back(grad_q_launch(c, qi, v1, v2));
+    // the q part G of E: its own launch, or (split form, fused schedule) inside the
+    // stage-terms launch
+    const bool gq_here = fz && c->split;
+    if (!gq_here) plan.push_back(grad_q_launch(c, qi, v1, v2));
     if (!fz) sync(kJoin);
     // u(i) from theta(i), terms of this stage for later stages, and step 1 of the next
     // stage; the last stage's terms are the next step's stage-0 terms
@@ -720,6 +724,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
     ae.us[0] = L.Us[0]; ae.us[1] = L.Us[1]; ae.u[0] = ae.u[1] = kNoSlot;
     ae.ub[0] = ae.ub[1] = ae.out_ud[0] = ae.out_ud[1] = ae.du0_in = ae.du0_out = kNoSlot;
     ae.ui[0] = ae.ui[1] = kNoSlot;
+    ae.q = kNoSlot;
     if (c->split) {
       // increment form on the float64 base u^n; the last stage writes the float64 state
       // u^{n+1} and its D0.u, the next step's D0.u^n
@@ -758,6 +763,9 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
       ae.out_lt = kNoSlot;
       if (c->split) {  // the increment du(i) on the float64 base; out_u the float u(i)
         ae.ui[0] = L.Us[0]; ae.ui[1] = L.Us[1];
+        ae.q = qi;  // G from q(i) and v(i) here: q in, no G
+        ae.g[0] = ae.g[1] = kNoSlot;
+        l.bytes += pt - 2 * pt;
       } else {  // u(i) as the update launch wrote it
         ae.u[0] = u1; ae.u[1] = u2;
         ae.out_u[0] = ae.out_u[1] = kNoSlot;

@@ -333,13 +333,17 @@ hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const W
       } else {
         s.r(0, a.u[m]);
       }
-      s.r(0, a.g[m]);
+      s.r(0, a.g[m], a.q != kNoSlot);  // no G input when it is formed here from q
       s.r(0, a.v[m]);
       s.w(0, a.out_e[m], true);
       s.r(1, a.ub[m], true);
       s.w(1, a.out_ud[m], true);
     }
     if (with_us) s.r(1, a.th);
+    if (a.q != kNoSlot) {
+      if (sizeof(T) != 4 || a.ui[0] == kNoSlot) fail("stage_terms: G formed outside the split fused stage");
+      s.r(0, a.q);
+    }
     if (a.out_lt != kNoSlot) {
       if (!with_us) fail("stage_terms: L theta without theta");
       s.r(0, a.ddb);

@@ -1058,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_div_u(const Inst *__restrict__ insts,
 // redundantly, in the same arithmetic as their owner), then u, Hu and Ltheta are written
 // for the interior cells.  theta uses the face buffers, which the flux rounds only need
 // later.
-template <typename T, int TY, int NT, int WO, int CO>
+template <typename T, int TY, int NT, int WO, int CO, bool GQ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_per_eu<TY, NT>()))) void k_stage_terms(const Inst *__restrict__ insts,
                                                                  const Work *__restrict__ work,
                                                                  int nwork, ArgsE a, ArgsV nv) {
@@ -1072,7 +1072,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   using SW = Stage<TY, NT, 1, double, kHalo + C::R>;  // theta(i), wide halo
   constexpr int FN = Gm::FXN + Gm::FYN;
   constexpr int FT = SW::PL * (int)(sizeof(double) / sizeof(TU));
-  __shared__ TU sU1[Gm::PL], sU2[Gm::PL];
+  static_assert(!GQ || INC, "G is formed here only in the FP32-split form");
+  // (one buffer for u: the split form's fused schedule stages q and v into it for G)
+  __shared__ __align__(16) TU sUb[2 * Gm::PL];
+  TU *const sU1 = sUb, *const sU2 = sUb + Gm::PL;
+  static_assert(!GQ || 3 * Gm::PL * sizeof(T) <= 2 * Gm::PL * sizeof(TU), "q, v staging");
   __shared__ __align__(16) TU sF[FN > FT ? FN : FT];
   TU *fx = sF, *fy = sF + Gm::FXN;
   const Work wk = work[xcd_item(nwork)];
@@ -1193,9 +1197,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     keep(e1[r]);
   }
   __syncthreads();
+  // GQ (split form, fused schedule): G = te2 D_W q[v] is formed here as k_grad_q forms it,
+  // from q(i) and v(i) staged after the E rounds
   // second row of B(u) = (u2, u1); D0.u and F(u) from the staged u
   faces<TY, NT, WO, TU, false, false, FPT>(fx, fy, sU2, sU2, TU(1), sU1, sU1, TU(1));
   __syncthreads();
+  TU e2[Gm::ROWS], us1[Gm::ROWS], us2[Gm::ROWS];
+  T gq1[Gm::ROWS], gq2[Gm::ROWS];
+  if constexpr (GQ) {
+    // second component of E and the staged u of this thread's cells into registers: the
+    // G round reuses both buffers
+#pragma unroll
+    for (int r = 0; r < Gm::ROWS; ++r) {
+      const int ly = ty0 + Gm::WV * r;
+      const int c = Gm::at(tx, ly);
+      e2[r] = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy));
+      us1[r] = TU(2) * sU1[c];
+      us2[r] = TU(2) * sU2[c];
+    }
+    Stage<TY, NT, 3, T> sg;
+    const Gp<const T> g3[3] = {tplane<T>(I, a.q), tplane<T>(I, a.v[0]), tplane<T>(I, a.v[1])};
+    sg.load(g3, nx, ny, wk.a, wk.b);
+    __syncthreads();
+    T *const sQ = reinterpret_cast<T *>(sUb), *const sW1 = sQ + Gm::PL,
+             *const sW2 = sQ + 2 * Gm::PL;
+    {
+      T *l3[3] = {sQ, sW1, sW2};
+      sg.store(l3, T(0.5));
+    }
+    __syncthreads();
+    T *const gfx = reinterpret_cast<T *>(sF), *const gfy = gfx + Gm::FXN;
+    faces<TY, NT, WO, T, true, true>(gfx, gfy, sQ, sW1, T(1), sQ, sW2, T(1));
+    __syncthreads();
+    const T ihxT = T(I.ihx), ihyT = T(I.ihy), te2 = T(I.te2);
+#pragma unroll
+    for (int r = 0; r < Gm::ROWS; ++r) {
+      const int ly = ty0 + Gm::WV * r;
+      gq1[r] = te2 * face_dx<TY>(gfx, tx, ly, ihxT);
+      gq2[r] = te2 * face_dy<TY>(gfy, tx, ly, ihyT);
+    }
+  }
   if (!col) return;
   // pointwise inputs of E and of the fused step 1: G, v, and
   // rv = te2 v^n - dt * (its history), formed in float64
@@ -1209,8 +1250,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     rv1[r] = rv2[r] = 0.0;
     if (gy < ny) {
       const Cell g = cell_at<T>(gy * nx + gx);
-      g1[r] = *tcell<T>(I, a.g[0], g);
-      g2[r] = *tcell<T>(I, a.g[1], g);
+      if constexpr (GQ) {
+        g1[r] = gq1[r];
+        g2[r] = gq2[r];
+      } else {
+        g1[r] = *tcell<T>(I, a.g[0], g);
+        g2[r] = *tcell<T>(I, a.g[1], g);
+      }
       if (nv.stage > 0) {
         Hist<T, 2> HE, HV;
         HE.load(I, &nv.E[0][0], nv.nE, g);
@@ -1235,11 +1281,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     if (gy >= ny) break;
     const Cell g = cell_at<T>(gy * nx + gx);
     const int c = Gm::at(tx, ly);
-    const TU u1 = TU(2) * sU1[c], u2 = TU(2) * sU2[c];
+    TU u1, u2, ex2;
+    if constexpr (GQ) {
+      u1 = us1[r];
+      u2 = us2[r];
+      ex2 = e2[r];
+    } else {
+      u1 = TU(2) * sU1[c];
+      u2 = TU(2) * sU2[c];
+      ex2 = qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy));
+    }
     const TU E1 = (e1[r] - TU(0.5) * (u2 * u2 - u1 * u1)) + TU(g1[r]);
-    const TU E2 =
-        (qt * (face_dx<TY>(fx, tx, ly, ihx) + face_dy<TY>(fy, tx, ly, ihy)) - u1 * u2) +
-        TU(g2[r]);
+    const TU E2 = (ex2 - u1 * u2) + TU(g2[r]);
     if constexpr (!INC)  // the split form stores D0 of the increment, formed above
       *tcell<T>(I, a.out_du, g) = C::d1(sU1, c, 1, ihx6) + C::d1(sU2, c, Gm::W, ihy6);
     if (a.out_e[0] != kNoSlot) {
@@ -1283,7 +1336,7 @@ hipError_t launch_helmholtz_rhs(int si, int wo, int co, const Inst *insts, const
 }
 
 #define APDVM_ONE(KERNEL, TY, NT, WO, CO, ...) \
-  APDVM_LAUNCH(ev, (KERNEL<T, TY, NT, WO, CO>), g, dim3(NT), st, __VA_ARGS__)
+  APDVM_LAUNCH(ev, (KERNEL<T, TY, NT, WO, CO, APDVM_GQ>), g, dim3(NT), st, __VA_ARGS__)
 #define APDVM_DISPATCH(KERNEL, ...)                                                       \
   do {                                                                                    \
     const dim3 g(nwork);                                                                  \
@@ -1357,7 +1410,17 @@ template <typename T>
 hipError_t launch_stage_terms(int si, int wo, int co, const Inst *insts, const Work *work,
                               int nwork, const ArgsE &a, const ArgsV &nv, hipStream_t st,
                               const Ev &ev) {
+  if constexpr (sizeof(T) == 4) {
+    if (a.q != kNoSlot) {  // the split form's fused schedule forms G here
+#define APDVM_GQ true
+      APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
+#undef APDVM_GQ
+      return hipGetLastError();
+    }
+  }
+#define APDVM_GQ false
   APDVM_DISPATCH(k_stage_terms, insts, work, nwork, a, nv);
+#undef APDVM_GQ
   return hipGetLastError();
 }
 #undef APDVM_DISPATCH
