@@ -31,6 +31,10 @@ device copy of known size), reported only for the workload, precision and kernel
 were taken on and while the kernel sources still hash to the recorded value; else null.
 roofline.traffic_frac: that measured traffic / the kernel's mean duration / 8 TB/s;
 roofline.step_frac: algorithmic bytes of the whole step / step time / 8 TB/s.
+roofline.valu_issue_frac: the time the kernel's VALU instructions alone occupy the SIMDs
+(waves x instructions per wave x 4 cycles / 1024 SIMDs / 2.4 GHz, from the rocprofv3 SQ
+counter run recorded under profiles/, on the same conditions as traffic) / its mean
+duration: near 1 the kernel is bound by instruction issue rather than by HBM.
 cpu_baseline: the FP64 NumPy oracle on a bounded sample of the same workload, on the
 host (one core: NumPy's elementwise kernels and pocketfft are single-threaded).  For the
 8192^2 workload one oracle step takes minutes, so the sample is whole steps of the same
@@ -78,6 +82,30 @@ def recorded_traffic(kernel_class, workload_name, precision, shape, structure):
                 h.update(f.read())
         if h.hexdigest() == rec["source_sha256"]:
             return rec["traffic_bytes_per_launch"]
+    return None
+
+
+def recorded_valu_issue_us(kernel_class, workload_name, precision, shape, structure):
+    """VALU issue time per launch (waves x VALU instructions x 4 cycles / 1024 SIMDs /
+    2.4 GHz) from the recorded SQ counter run, or None when it does not apply (other
+    kernel, launch shape, stream structure or workload, or changed kernel sources)."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "sq_counters_*.json"))):
+        with open(path) as f:
+            rec = json.load(f)
+        if (rec.get("kernel_class") != kernel_class or rec.get("workload") != workload_name
+                or rec.get("precision") != precision
+                or (rec.get("tile_rows"), rec.get("threads")) != shape
+                or (rec.get("structure", 0) == 2) != (structure == 2)):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["source_sha256"]:
+            return rec["valu_issue_us_per_launch"]
     return None
 
 
@@ -283,8 +311,10 @@ def main():
     sec = t1 - t0
 
     dname = apdvm.KERNEL_CLASSES[dom]
-    traffic = recorded_traffic(dname, cfg["workload"], args.precision,
-                               (tiles.get(dname), tiles.get("threads_" + dname)), sim.overlap())
+    shape = (tiles.get(dname), tiles.get("threads_" + dname))
+    traffic = recorded_traffic(dname, cfg["workload"], args.precision, shape, sim.overlap())
+    valu_us = recorded_valu_issue_us(dname, cfg["workload"], args.precision, shape,
+                                     sim.overlap())
     bytes_step, launches = sim.traffic(dom)
     per_launch = bytes_step / launches
     mean_s = ms_dom / n_dom / 1e3
@@ -321,6 +351,7 @@ def main():
                      "traffic": traffic,
                      # measured HBM bytes (rocprofv3 counters) / mean launch time / peak
                      "traffic_frac": traffic / mean_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     "valu_issue_frac": valu_us * 1e-6 / mean_s if valu_us else None,
                      "bytes_per_launch": per_launch, "mean_launch_us": mean_s * 1e6,
                      "launches_timed": n_dom,
                      # every kernel of the step: algorithmic bytes / step time
