@@ -83,8 +83,8 @@ def test_device_fields_reject_non_finite_and_change_nothing():
     sim.close()
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_step_returns_nonfinite_and_keeps_last_checked_state(graph):
+@pytest.mark.parametrize("graph,structure", [(False, 1), (True, 1), (True, 2)])
+def test_step_returns_nonfinite_and_keeps_last_checked_state(graph, structure):
     """A run whose time step is far beyond the stability limit (dt = 0.1 on 32^2 at
     eps = 1: the values overflow after about twenty steps) with a check every 4 steps:
     the call returns APDVM_ERR_NONFINITE, the step counter is back at the last check that
@@ -93,11 +93,12 @@ def test_step_returns_nonfinite_and_keeps_last_checked_state(graph):
     import torch
 
     from paper_2512_19847_amd import apdvm
-    _say(f"case blow-up with finite check every 4 steps, graph={graph}")
+    _say(f"case blow-up with finite check every 4 steps, graph={graph} structure={structure}")
     st = wl.random_divfree(32, kmax=4, rms=0.1, seed=21)
     kw = dict(n=32, eps=1.0, tau=0.3, dt=0.1)
     sim = _sim(apdvm.FP64, stream=torch.cuda.Stream(), **kw)
     sim.set_graph(graph)
+    sim.set_overlap(structure)
     sim.set_finite_check(4)
     sim.set_fields(0, *st)
     with pytest.raises(apdvm.ApdvmError) as e:
@@ -113,6 +114,7 @@ def test_step_returns_nonfinite_and_keeps_last_checked_state(graph):
     sim.close()
 
     plain = _sim(apdvm.FP64, **kw)
+    plain.set_overlap(structure)
     plain.set_finite_check(0)
     plain.set_fields(0, *st)
     plain.step(s_ck)
