@@ -129,7 +129,7 @@ struct Inst {
   double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
   double inv_nxny;           // 1 / (nx ny)
   FftPlan fx, fy;            // lengths nx and ny
-  FftPlan fyh;               // length ny / 2 on the table of fy (the split column kernel)
+  FftPlan fxh, fyh;          // lengths nx / 2, ny / 2 on the tables of fx, fy (split kernels)
   const double *lam_x;       // nx/2 + 1 values of the x symbol of D_Delta
   const double *lam_y;       // ny values of the y symbol
   void *tbase;               // transport arena

@@ -19,6 +19,9 @@
 //                 spectra by their Hermitian symmetry, each with its own divisor), inverse
 //                 FFT, in place.
 //  rows inverse   Hermitian extension of the half spectra, inverse FFT, two real rows.
+// The largest column form, and the inverse rows of the largest row form when every nx is
+// a multiple of 4, run split: a radix-2 step in registers leaves two half-length
+// transforms, done one after the other in half the LDS, so two workgroups share a CU.
 //
 // Every FFT is a mixed-radix (8, 4, 3, 2) Stockham autosort transform in LDS: each pass
 // reads R strided inputs per butterfly, applies twiddles from a float64 table of
@@ -611,6 +614,116 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   }
 }
 
+// ------------------------------------------------------------------ rows inverse, split
+
+// Inverse rows of the largest form in half the LDS, as the split column kernel does for
+// columns (n = nx, h = n / 2, w = exp(-2 pi i / n)): the even modes Z[2m] and the odd modes
+// Z[2m + 1] of the Hermitian extension of a row pair's half spectra go through two
+// length-h inverse transforms, ya and yb, and a radix-2 step in registers gives
+//   z[t] = ya[t] + w^-t yb[t],  z[t + h] = ya[t] - w^-t yb[t],
+// with ya held in registers while yb is transformed.  The extension pairs Z[k] with Z[n - k],
+// a mode of the same parity when h is even (the host takes this form only when every nx
+// is a multiple of 4): Z[2m] with Z[2(h - m)] (Z[h] = the even mode h / 2 shares column 0
+// with Z[0]), Z[2m + 1] with Z[2(h - 1 - m) + 1].  A workgroup holds C h <= kFftCap / 2
+// values (C the row pairs of a block, as in the whole-row form), so two workgroups share a
+// CU and one loads or stores while the other transforms.  (The forward rows keep the
+// whole-row form: split the same way, with the odd half held in registers through the
+// even half's transform, that kernel spilled 0.45 GB of registers per 8192^2 launch and
+// measured no faster.)
+constexpr int kRowSplitThreads = 512;
+// LDS padding of the split row kernel (lp): none, as the split column kernel (one in 8
+// measured no faster).
+constexpr int kRowSplitPad = 0;
+
+// Even (par 0) or odd (par 1) modes of the Hermitian extensions of C row pairs' half
+// spectra into buf (pair p at p h), from the loaded column-major values A, B of rows 2p and
+// 2p + 1 at k = 2m + par, item idx = m C + p of the h / 2 C items.
+template <int SH>
+__device__ __forceinline__ void put_modes(double2 *buf, int h, int par, int m, int p,
+                                          double2 A, double2 B) {
+  if (par == 0 && m == 0) {
+    // kx = 0 and kx = nx/2 (real for a real row) share column 0; Z[h] = even mode h / 2
+    buf[lp<SH>(p * h)] = make_double2(A.x, B.x);
+    buf[lp<SH>(p * h + h / 2)] = make_double2(A.y, B.y);
+  } else {
+    buf[lp<SH>(p * h + m)] = make_double2(A.x - B.y, A.y + B.x);  // A + i B
+    // conj A + i conj B at n - k: even mode h - m, odd mode h - 1 - m
+    buf[lp<SH>(p * h + (par ? h - 1 - m : h - m))] = make_double2(A.x + B.y, B.x - A.y);
+  }
+}
+
+template <int NT, int SH>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_inverse_split(
+    const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
+  constexpr int CAP = kFftCap / 2;
+  constexpr int E = CAP / NT;       // output elements of a half per thread
+  constexpr int EI = CAP / (2 * NT);  // loaded modes of a half per thread
+  __shared__ double2 buf[SH ? CAP + (CAP >> SH) : CAP];
+  __shared__ double2 tws[kTwCap];
+  const Work wk = work[xcd_item_fft(nwork)];
+  const Inst &I = insts[wk.inst];
+  const int n = I.nx, h = n / 2, ny = I.ny;
+  const int p0 = wk.a;
+  const int np = min(I.row_pairs_per_block, I.ny / 2 - p0);
+  const int cnt = np * h, cin = np * (h / 2);
+  const Gp<const dv2> S = cslot(I, a.spec) + 2LL * p0;
+  const Div dp(np), dh(h);
+  TwStage<NT> tw;
+  tw.load(I.fx);
+  // modes k = 2m + par of rows 2p and 2p + 1 into LDS as the half par of the extension
+  auto load_half = [&](int par, bool with_table) {
+    double2 A[EI], B[EI];
+#pragma unroll
+    for (int e = 0; e < EI; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cin) {
+        const int m = dp.q(idx), p = idx - m * np;
+        const unsigned b = (unsigned)((2 * m + par) * ny + 2 * p) * 16u;
+        A[e] = ldc(at_byte(S, b));
+        B[e] = ldc(at_byte(S, b + 16u));
+      }
+    }
+    if (with_table) tw.store(tws, I.fx);
+#pragma unroll
+    for (int e = 0; e < EI; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cin) {
+        const int m = dp.q(idx), p = idx - m * np;
+        put_modes<SH>(buf, h, par, m, p, A[e], B[e]);
+      }
+    }
+    __syncthreads();
+  };
+  load_half(0, true);
+  fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
+  double2 ya[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) ya[e] = buf[lp<SH>(idx)];
+  }
+  __syncthreads();
+  load_half(1, false);
+  fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
+  const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int p = dh.q(idx), t = idx - p * h;
+      double2 w = tw_at(tws, I.fx.lb, t);
+      w.y = -w.y;  // w^-t
+      const double2 yb = cmul(buf[lp<SH>(idx)], w);
+      const double2 lo = cadd(ya[e], yb), hi = csub(ya[e], yb);
+      const unsigned o = (unsigned)(2 * p * n + t) * 8u;
+      *at_byte(T, o) = lo.x;
+      *at_byte(T, o + (unsigned)n * 8u) = lo.y;
+      *at_byte(T, o + (unsigned)h * 8u) = hi.x;
+      *at_byte(T, o + (unsigned)(n + h) * 8u) = hi.y;
+    }
+  }
+}
+
 // Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values
 // (the launch takes ev, st, insts and a of the calling function).
 #define APDVM_FFT_FORM(V, KERNEL, WORK, NWORK)                                             \
@@ -627,12 +740,13 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   } while (0)
 
 // part 0: rows forward, 1: columns, 2: rows inverse; rowv and colv the kernel forms
-// (the smallest that holds a whole row, a whole column).
+// (the smallest that holds a whole row, a whole column; rowv 3: the largest row form,
+// with the inverse rows split in halves).
 hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, const Work *rows,
                              int nrows, const Work *cols, int ncols, const ArgsSolve &a,
                              hipStream_t st, const Ev &ev) {
   switch (part) {
-    case 0: APDVM_FFT_FORM(rowv, k_rows_forward, rows, nrows); break;
+    case 0: APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, k_rows_forward, rows, nrows); break;
     case 1:
       if (colv == 2)  // the largest columns: half the LDS, two workgroups per CU
         APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads>), dim3(ncols), dim3(kColSplitThreads),
@@ -640,7 +754,13 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
       else
         APDVM_FFT_FORM(colv, k_cols, cols, ncols);
       break;
-    default: APDVM_FFT_FORM(rowv, k_rows_inverse, rows, nrows); break;
+    default:
+      if (rowv == 3)  // the largest rows, nx a multiple of 4: half the LDS, two per CU
+        APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad>), dim3(nrows),
+                     dim3(kRowSplitThreads), st, insts, rows, nrows, a);
+      else
+        APDVM_FFT_FORM(rowv, k_rows_inverse, rows, nrows);
+      break;
   }
   return hipGetLastError();
 }

@@ -447,6 +447,7 @@ struct apdvm_ctx {
   Work *d_rows = nullptr, *d_cols = nullptr;
   int nrows = 0, ncols = 0;
   int row_v = 0, col_v = 0;  // FFT kernel forms of the rows and columns (fft_form)
+  bool row_split = false;    // rows in the split form (largest form, every nx % 4 == 0)
   int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
@@ -809,7 +810,8 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
     case kRowsFwd:
     case kCols:
     case kRowsInv:
-      return launch_solve_part(l.cls - kRowsFwd, c->row_v, c->col_v, c->d_inst, c->d_rows,
+      return launch_solve_part(l.cls - kRowsFwd, c->row_split ? 3 : c->row_v, c->col_v,
+                               c->d_inst, c->d_rows,
                                c->nrows, c->d_cols, c->ncols, l.sv, st, ev);
     case kUpdateUQ:
       return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st, ev);
@@ -1182,6 +1184,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   // carve the workspace
   const size_t tsize = c->split ? sizeof(float) : sizeof(double);
   c->row_v = row_form(n, cfgs);
+  c->row_split = c->row_v == 2;
+  for (int k = 0; k < n; ++k) c->row_split = c->row_split && cfgs[k].nx % 4 == 0;
   c->col_v = col_form(n, cfgs);
   for (int k = 0; k < kNumClasses; ++k) c->shape[k] = 1;
   c->wo = weno_order_of(cfgs[0]);
@@ -1231,7 +1235,11 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
       plans[q]->tw2 = tw2 + q * kTwCap;
       plans[q]->tsc = 1;
     }
-    // half-length column plan on the column table (length ny = 2 (ny / 2))
+    // half-length plans on the row and column tables (length n = 2 (n / 2))
+    I.fxh = I.fx;
+    I.fxh.n = cf.nx / 2;
+    I.fxh.npass = fft_radices(cf.nx / 2, I.fxh.radix);
+    I.fxh.tsc = 2;
     I.fyh = I.fy;
     I.fyh.n = cf.ny / 2;
     I.fyh.npass = fft_radices(cf.ny / 2, I.fyh.radix);

@@ -402,7 +402,7 @@ hipError_t launch_div_u(int co, const Inst *insts, const Work *tiles, int nwork,
 hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, const Work *rows,
                              int nrows, const Work *cols, int ncols, const ArgsSolve &a,
                              hipStream_t st, const Ev &) {
-  if (part < 0 || part > 2 || rowv < 0 || rowv > 2 || colv < 0 || colv > 2)
+  if (part < 0 || part > 2 || rowv < 0 || rowv > 3 || colv < 0 || colv > 2)
     fail("solve: part %d, forms %d %d", part, rowv, colv);
   hostcheck::enqueue(st, [=] {
     ++cnt().launches;
@@ -410,7 +410,7 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
     const Work *work = is_rows ? rows : cols;
     const int nwork = is_rows ? nrows : ncols;
     const int v = is_rows ? rowv : colv;
-    const int cap = v == 0 ? kRowSmallCap : v == 1 ? kColMidCap : kFftCap;
+    const int cap = v == 0 ? kRowSmallCap : v == 1 ? kColMidCap : kFftCap;  // v 3: halved
     static std::set<std::tuple<const void *, unsigned long long, int, int, int>> walked;
     const bool walk =
         !in_device(work, (size_t)nwork * sizeof(Work)) ||
@@ -440,9 +440,13 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
       }
       const int cnt_lines = std::min(per, lines - x0);
       const bool split_cols = !is_rows && v == 2;  // the largest column form halves
-      const long long need = split_cols ? (long long)cnt_lines * (I.ny / 2)
-                                        : (long long)cnt_lines * len / (is_rows ? 2 : 1);
-      const long long have = split_cols ? kFftCap / 2 : cap;
+      const bool split_rows = part == 2 && v == 3;  // so do the largest inverse rows
+      if (split_rows && I.nx % 4)
+        fail("solve part %d: split rows of instance %d with nx = %d", part, w->inst, I.nx);
+      const long long need = split_cols   ? (long long)cnt_lines * (I.ny / 2)
+                             : split_rows ? (long long)cnt_lines * (I.nx / 2)
+                                          : (long long)cnt_lines * len / (is_rows ? 2 : 1);
+      const long long have = split_cols || split_rows ? kFftCap / 2 : cap;
       if (need > have)
         fail("solve part %d: block of instance %d needs %lld LDS values, form holds %lld", part,
              w->inst, need, have);

@@ -6,7 +6,8 @@ grid and covering it once, staged halo cells the periodic images of their cells,
 slots inside their arenas, no launch writing a plane it reads, FFT blocks fitting their
 LDS form and covering every line once).  Scenarios: both precisions, every tableau
 family, WENO3 / second-order operators, ragged and batched instances, and the long thin
-grids that take every FFT form (including the split 8192-value column form)."""
+grids that take every FFT form (including the split 8192-value column and inverse-row
+forms, and the whole-row form that rows of nx = 2 mod 4 keep)."""
 
 import os
 import subprocess
@@ -28,6 +29,11 @@ SCENARIOS = [
                                      (16, 2048, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("thin_8192_split", 1, "ars443", [(8192, 8, 0.05, 0.05, -1.0, 0.0, 5, 4),
                                       (8, 8192, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("split_rows_radix3_fp64", 0, "ars443", [(3072, 8, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                             (12, 4096, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                             (6144, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("whole_rows_nx_2mod4", 1, "ars443", [(4374, 8, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                          (8, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("batch_sizes_split", 1, "ars443",
      [(n, n, 10.0 ** -(k % 7), 0.01 + 0.01 * k, -1.0, 0.0, 5, 4)
       for k, n in enumerate((64, 96, 128, 192, 64, 96, 8, 16, 24, 48))]),
