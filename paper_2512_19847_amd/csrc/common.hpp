@@ -85,6 +85,18 @@ __host__ __device__ inline int staged_cell(int idx, int W, int H, int nx, int ny
   return gy * nx + gx;
 }
 
+// Factors of the central differences for 1/h = ih: order 4 (the high-order extension of
+// Section 3.2) D f = (f-2 - 8 f-1 + 8 f+1 - f+2) ih / 12, L f = (-f-2 + 16 f-1 - 30 f0 +
+// 16 f+1 - f+2) ih^2 / 12; order 2 (as printed in Section 3.2) D f = (f+1 - f-1) ih / 2,
+// L f = (f-1 - 2 f0 + f+1) ih^2.  The host evaluates them once per instance (a float64
+// division on the device is a dozen vector instructions in every thread).
+__host__ __device__ inline double central_f1(int co, double ih) {
+  return co == 2 ? 0.5 * ih : ih / 12.0;
+}
+__host__ __device__ inline double central_f2(int co, double ih) {
+  return co == 2 ? ih * ih : ih * ih / 12.0;
+}
+
 constexpr int kMaxStages = 8;
 constexpr int kMaxPasses = 16;
 constexpr int kNoSlot = -1;
@@ -123,10 +135,13 @@ struct Inst {
   int nx, ny;
   long long plane;           // nx * ny
   double ihx, ihy;           // 1 / h
+  double f1x, f1y, f2x, f2y; // central-difference factors central_f1, central_f2 of 1 / h
   double eps, tau, dt, te2;  // te2 = tau * eps^2
   double theta_mean;         // value imposed on the (0,0) Helmholtz mode
   double kinv[kMaxStages];   // 1 / (tau eps^2 + dt a_ii)
   double sigma[kMaxStages];  // 2 eps^2 / (dt a_ii)^2
+  double rdt2[kMaxStages];   // 1 / (dt a_ii^2)
+  double rdt[kMaxStages];    // 1 / (dt a_ii)
   double inv_nxny;           // 1 / (nx ny)
   FftPlan fx, fy;            // lengths nx and ny
   FftPlan fxh, fyh;          // lengths nx / 2, ny / 2 on the tables of fx, fy (split kernels)
@@ -184,6 +199,7 @@ struct ArgsR {
   double cL[kMaxStages];
   int out_r;      // R (float64 slot)
   int out_ddb;    // D0^2:B(v(i))
+  double c_l;     // 1 / a_ii
 };
 
 // Steps 3 and 4 short of theta(i), which the Helmholtz solve of the same stage is still

@@ -514,6 +514,8 @@ void set_dt(apdvm_ctx *c, int k, double dt) {
     const double aii = c->A[i][i];
     I.kinv[i] = 1.0 / (I.te2 + dt * aii);
     I.sigma[i] = 2.0 * I.eps * I.eps / ((dt * aii) * (dt * aii));
+    I.rdt2[i] = 1.0 / (dt * aii * aii);
+    I.rdt[i] = 1.0 / (dt * aii);
   }
 }
 
@@ -658,6 +660,7 @@ std::vector<Launch> build_plan(const apdvm_ctx *c, int P) {
       }
     }
     ar.out_r = L.R; ar.out_ddb = L.ddb;
+    ar.c_l = 1.0 / aii;
     // v in (2), D0^2:B out (1), histories, D0.u^n (transport or float64); theta^n in, R out
     l.bytes = (2 + ar.nD + ar.nL + 1) * pt + (c->split ? pd : pt) + 2 * pd;
     plan.push_back(l);
@@ -1208,6 +1211,13 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
     I.plane = (long long)cf.nx * cf.ny;
     I.ihx = cf.nx / cf.lx;
     I.ihy = cf.ny / cf.ly;
+    {
+      const int co = central_order_of(cf);
+      I.f1x = central_f1(co, I.ihx);
+      I.f1y = central_f1(co, I.ihy);
+      I.f2x = central_f2(co, I.ihx);
+      I.f2y = central_f2(co, I.ihy);
+    }
     I.eps = cf.eps;
     I.tau = resolved_tau(cf);
     I.te2 = I.tau * cf.eps * cf.eps;

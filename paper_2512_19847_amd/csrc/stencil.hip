@@ -447,14 +447,13 @@ __device__ __forceinline__ T face_dy(const T *fy, int lx, int ly, T ihy) {
 //   D f = (f-2 - 8 f-1 + 8 f+1 - f+2) / (12 h),
 //   L f = (-f-2 + 16 f-1 - 30 f0 + 16 f+1 - f+2) / (12 h^2),
 // order 2 (as printed in Section 3.2) D f = (f+1 - f-1) / (2 h), L f = (f-1 - 2 f0 + f+1)
-// / h^2; D_xy = D_x D_y in both.  f1(ih) and f2(ih) give the factors for 1/h = ih.
+// / h^2; D_xy = D_x D_y in both.  The factors (central_f1, central_f2 of 1/h) come with
+// the instance (Inst::f1x ... f2y), evaluated once on the host.
 template <int CO>
 struct Central;
 template <>
 struct Central<4> {
   static constexpr int R = 2;  // reach
-  __host__ __device__ static double f1(double ih) { return ih / 12.0; }
-  __host__ __device__ static double f2(double ih) { return ih * ih / 12.0; }
   template <typename S>
   __device__ static S d1(const S *p, int c, int st, S f) {
     return (p[c - 2 * st] - S(8) * p[c - st] + S(8) * p[c + st] - p[c + 2 * st]) * f;
@@ -504,8 +503,6 @@ struct Central<4> {
 template <>
 struct Central<2> {
   static constexpr int R = 1;
-  __host__ __device__ static double f1(double ih) { return 0.5 * ih; }
-  __host__ __device__ static double f2(double ih) { return ih * ih; }
   template <typename S>
   __device__ static S d1(const S *p, int c, int st, S f) {
     return (p[c + st] - p[c - st]) * f;
@@ -616,7 +613,7 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
   const bool col = gx < I.nx;
   // pointwise inputs of the right-hand side, loaded while the tile arrives
   const double sig = I.sigma[a.stage];
-  const double c_d = 1.0 / (I.dt * a.aii * a.aii), c_0 = 1.0 / (I.dt * a.aii), c_l = 1.0 / a.aii;
+  const double c_d = I.rdt2[a.stage], c_0 = I.rdt[a.stage], c_l = a.c_l;
   double base[Gm::ROWS];
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
@@ -643,8 +640,8 @@ __global__ __launch_bounds__(NT) void k_helmholtz_rhs(const Inst *__restrict__ i
   __syncthreads();
   if (!col) return;
   using C = Central<CO>;
-  const double ihx12 = C::f1(I.ihx), ihy12 = C::f1(I.ihy);
-  const double ihx2 = C::f2(I.ihx), ihy2 = C::f2(I.ihy);
+  const double ihx12 = I.f1x, ihy12 = I.f1y;
+  const double ihx2 = I.f2x, ihy2 = I.f2y;
 #pragma unroll
   for (int r = 0; r < Gm::ROWS; ++r) {
     const int ly = ty0 + Gm::WV * r;
@@ -669,9 +666,9 @@ template <int CO>
 __device__ __forceinline__ void theta_terms(const double *sT, int c, int w, const Inst &I,
                                             double &dx, double &dy, double &lap) {
   using C = Central<CO>;
-  dx = C::d1(sT, c, 1, C::f1(I.ihx));
-  dy = C::d1(sT, c, w, C::f1(I.ihy));
-  lap = C::d2(sT, c, 1, C::f2(I.ihx)) + C::d2(sT, c, w, C::f2(I.ihy));
+  dx = C::d1(sT, c, 1, I.f1x);
+  dy = C::d1(sT, c, w, I.f1y);
+  lap = C::d2(sT, c, 1, I.f2x) + C::d2(sT, c, w, I.f2y);
 }
 
 // ------------------------------------------------------------------ steps 3 and 4
@@ -895,7 +892,7 @@ __device__ __forceinline__ void stage_increment(const Inst &I, const Work &wk, c
   const bool col = gx < nx;
   // phase 1
   if (col) {
-    const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+    const double f2x = I.f2x, f2y = I.f2y;
 #pragma unroll
     for (int r = 0; r < Gm::ROWS; ++r) {
       const int ly = ty0 + Gm::WV * r;
@@ -1029,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_div_u(const Inst *__restrict__ insts,
   const int gx = wk.a + (threadIdx.x & 63);
   if (gx >= nx) return;
   const Gp<const double> p1 = dplane(I, su1), p2 = dplane(I, su2);
-  const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+  const double f1x = I.f1x, f1y = I.f1y;
   for (int ly = threadIdx.x >> 6; ly < 16; ly += 4) {
     const int gy = wk.b + ly;
     if (gy >= ny) break;
@@ -1115,7 +1112,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     }
     __syncthreads();
     const double cth = I.dt * a.aii;
-    const double f1x = C::f1(I.ihx), f1y = C::f1(I.ihy);
+    const double f1x = I.f1x, f1y = I.f1y;
     if constexpr (INC) {
       stage_increment<T, TY, NT, CO>(I, wk, a, su, sT, sU1, sU2, hv1, hv2, dd, want_hu, want_lt,
                                      cth, f1x, f1y);
@@ -1134,7 +1131,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
     __syncthreads();
     // u, Hu and Ltheta of this thread's interior cells (the staged u is halved exactly)
     if (col) {
-      const double f2x = C::f2(I.ihx), f2y = C::f2(I.ihy);
+      const double f2x = I.f2x, f2y = I.f2y;
 #pragma unroll
       for (int r = 0; r < Gm::ROWS; ++r) {
         const int ly = ty0 + Gm::WV * r;
@@ -1165,7 +1162,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
       double *l2[2] = {sU1, sU2};
       su.store(l2, 1.0);
       __syncthreads();
-      increment_tail<T, TY, NT, CO, SU>(I, wk, a, sU1, sU2, C::f1(I.ihx), C::f1(I.ihy));
+      increment_tail<T, TY, NT, CO, SU>(I, wk, a, sU1, sU2, I.f1x, I.f1y);
     } else {  // the terms of a state: its float64 velocity
       Stage<TY, NT, 2, double> su;
       const Gp<const double> g2[2] = {dplane(I, a.ub[0]), dplane(I, a.ub[1])};
@@ -1183,7 +1180,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(weno_waves_p
   __syncthreads();
   const TU ihx = TU(I.ihx), ihy = TU(I.ihy);
   // the staged u is halved: its central derivative carries a factor 2
-  const T ihx6 = T(2.0 * C::f1(I.ihx)), ihy6 = T(2.0 * C::f1(I.ihy));
+  const T ihx6 = T(2.0 * I.f1x), ihy6 = T(2.0 * I.f1y);
   const TU qt = TU(0.25 * I.tau);
   // first component of (tau/4) D0_W.B(u); E is assembled at the end
   TU e1[Gm::ROWS];
