@@ -191,19 +191,26 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const 
       for (int r = 0; r < R; ++r) v[p][r] = buf[lp<SH>(src + r * nbf)];
       if (Ns > 1) {
         // w^r for r = 1..R-1 from one table lookup: powers by products of depth <= 3
-        double2 w[R];
-        w[1] = tw_at(tws, lb, k * twstep * tsc);
-        if (DIR > 0) w[1].y = -w[1].y;
-        if constexpr (R >= 3) w[2] = cmul(w[1], w[1]);
-        if constexpr (R >= 4) w[3] = cmul(w[2], w[1]);
-        if constexpr (R == 8) {
-          w[4] = cmul(w[2], w[2]);
-          w[5] = cmul(w[4], w[1]);
-          w[6] = cmul(w[4], w[2]);
-          w[7] = cmul(w[4], w[3]);
+        // (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, w^(4+j) = w^4 w^j), each applied as soon
+        // as it is formed, so at most w, w^2, w^3 and w^4 are live at once
+        double2 w1 = tw_at(tws, lb, k * twstep * tsc);
+        if (DIR > 0) w1.y = -w1.y;
+        v[p][1] = cmul(v[p][1], w1);
+        if constexpr (R >= 3) {
+          const double2 w2 = cmul(w1, w1);
+          v[p][2] = cmul(v[p][2], w2);
+          if constexpr (R >= 4) {
+            const double2 w3 = cmul(w2, w1);
+            v[p][3] = cmul(v[p][3], w3);
+            if constexpr (R == 8) {
+              const double2 w4 = cmul(w2, w2);
+              v[p][4] = cmul(v[p][4], w4);
+              v[p][5] = cmul(v[p][5], cmul(w4, w1));
+              v[p][6] = cmul(v[p][6], cmul(w4, w2));
+              v[p][7] = cmul(v[p][7], cmul(w4, w3));
+            }
+          }
         }
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], w[r]);
       }
       dft<R, DIR>(v[p]);
       dst[p] = b * n + jq * Ns * R + k;
