@@ -227,10 +227,11 @@ apdvm_status apdvm_set_graph(apdvm_ctx *ctx, int32_t on);
  * on = 2: every launch on the creation stream, with the update launch (class 4) after
  * the solve completing u, Hu and L theta of the stage from its theta itself (the
  * theta part of Algorithm 1, step 3), so the stage-terms launch reads the finished u and
- * the intermediate u* and hu make no round trip through memory; results equal those of
- * on = 0 and 1 to rounding (in the FP32-split form the float increment is rounded once,
- * after the theta part, instead of before it).  apdvm_autotune picks the fastest.
- * Synchronises both streams when the setting changes. */
+ * the intermediate u* and hu make no round trip through memory; in the FP32-split form
+ * the stage-terms launch also forms te2 D_W q (so class 6 is not launched); results
+ * equal those of on = 0 and 1 to rounding (in the FP32-split form the float increment is
+ * rounded once, after the theta part, instead of before it).  apdvm_autotune picks the
+ * fastest.  Synchronises both streams when the setting changes. */
 apdvm_status apdvm_set_overlap(apdvm_ctx *ctx, int32_t on);
 
 /* Current stream structure (1: solve beside steps 3 and 4, 0: one stream, 2: one stream
@@ -277,15 +278,18 @@ apdvm_status apdvm_traffic(apdvm_ctx *ctx, int32_t cls, double *bytes_per_step,
  * Shapes: 64 x 8 or 64 x 16 tiles on 256 or 512 threads. */
 #define APDVM_TUNING_LEN 11
 
-/* Autotune the launch shapes: for the stencil kernel classes (0, 4, 5, 6) each shape is
- * timed with HIP events over steps_per_trial steps of the live simulation; the fastest is
- * kept.  Then whole steps with and without the second stream (apdvm_set_overlap) are
- * timed in the context's launch mode, twice each and interleaved, each run at least
- * 2 steps_per_trial steps and about 10 ms, and the faster kept.  The state, the step counter and the launch mode are restored afterwards
- * (this call allocates a temporary device copy of the state).  If the environment variable APDVM_TUNE_CACHE names a file, a previous
- * choice for the same context shape is read from it and no trial runs; new choices are
- * appended to it.  choice (NULL, or APDVM_TUNING_LEN entries) receives the choice.
- * Needs fields on every instance. */
+/* Autotune the launch shapes and the stream structure: for the stencil kernel classes (0,
+ * 4, 5, 6) each shape is timed with HIP events over steps_per_trial steps of the live
+ * simulation, once with the kernels of structures 0 and 1 and once with those of
+ * structure 2 (apdvm_set_overlap), and the fastest of each set is kept.  Then whole steps
+ * of the three structures, each with its shapes, are timed in the context's launch mode,
+ * twice each and interleaved, each run at least 2 steps_per_trial steps and about 10 ms,
+ * and the fastest kept.  The state, the step counter and the launch mode are restored
+ * afterwards (this call allocates a temporary device copy of the state).  If the
+ * environment variable APDVM_TUNE_CACHE names a file, a previous choice for the same
+ * context shape is read from it and no trial runs; new choices are appended to it.
+ * choice (NULL, or APDVM_TUNING_LEN entries) receives the shape choice.  Needs fields on
+ * every instance. */
 apdvm_status apdvm_autotune(apdvm_ctx *ctx, int32_t steps_per_trial, int32_t *choice);
 
 /* Set the launch shapes directly (APDVM_TUNING_LEN entries, the format apdvm_autotune

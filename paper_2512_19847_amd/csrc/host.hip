@@ -447,7 +447,7 @@ struct apdvm_ctx {
   Work *d_rows = nullptr, *d_cols = nullptr;
   int nrows = 0, ncols = 0;
   int row_v = 0, col_v = 0;  // FFT kernel forms of the rows and columns (fft_form)
-  bool row_split = false;    // rows in the split form (largest form, every nx % 4 == 0)
+  bool row_split = false;    // inverse rows split in halves (largest form, every nx % 4 == 0)
   int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
