@@ -869,13 +869,14 @@ __device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, co
 // FP32-split completion of a stage (the increment form of k_stage_terms, below), with
 // the staged velocity in float64.  Phase 1 writes the theta terms of the interior cells
 // (Hu, Ltheta) and stages the increment du(i) = du*(i) - dt a_ii D0 theta(i).  Phase 2
-// forms D0.du(i) at the interior cells, or in the last stage the float64 D0.u^{n+1} of
-// the new state from the values phase 3 stores (so it equals D0 of the stored state bit
-// for bit, as k_div_u forms it after a restart).  Phase 3 stages u(i) = u^n + du(i),
-// halved, for the flux rounds (in float64: the viscous term (tau/4) D0_W.B(u) of E would
-// otherwise carry the float rounding of u divided by h), and writes the interior
-// velocities: float u(i) and, in the last stage, the float64 state u^{n+1} = u^n + du(s)
-// with its float copy.  Only the float rounding of du*(i), of size dt |Hu|, reaches D0.u.
+// forms D0.du(i) at the interior cells (the stages before the last).  Phase 3 stages
+// u(i) = u^n + du(i), halved, for the flux rounds (in float64: the viscous term
+// (tau/4) D0_W.B(u) of E would otherwise carry the float rounding of u divided by h), and
+// writes the interior velocities: float u(i) and, in the last stage, the float64 state
+// u^{n+1} = u^n + du(s) with its float copy; the last stage then forms the float64
+// D0.u^{n+1} from the staged values, which are the stored state (so it equals D0 of the
+// stored state bit for bit, as k_div_u forms it after a restart).  Only the float
+// rounding of du*(i), of size dt |Hu|, reaches D0.u.
 template <typename T, int TY, int NT, int CO, typename SU>
 __device__ __forceinline__ void stage_increment(const Inst &I, const Work &wk, const ArgsE &a,
                                                 const SU &su, const double *sT, double *sU1,
@@ -937,8 +938,7 @@ __device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, co
   const int gx = wk.a + tx;
   const bool col = gx < nx;
   const bool last = a.out_ud[0] != kNoSlot;
-  // phase 2: u^n on the staged region (float64, or its float copy when no float64 base
-  // is given)
+  // u^n on the staged region (float64, or its float copy when no float64 base is given)
   double b1[SU::IT], b2[SU::IT];
   if (a.ub[0] != kNoSlot) {
     Stage<TY, NT, 2, double> sb;
@@ -959,7 +959,8 @@ __device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, co
       b2[it] = (double)sb.v[1][it];
     }
   }
-  if (col) {
+  // phase 2: D0 of the increment (the stages before the last)
+  if (col && !last && a.out_du != kNoSlot) {
 #pragma unroll
     for (int r = 0; r < Gm::ROWS; ++r) {
       const int ly = ty0 + Gm::WV * r;
@@ -967,24 +968,13 @@ __device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, co
       if (gy >= ny) break;
       const int c = Gm::at(tx, ly);
       double wx[2 * R + 1], wy[2 * R + 1];
-      if (last) {
-        const Gp<const double> p1 = dplane(I, a.ub[0]), p2 = dplane(I, a.ub[1]);
 #pragma unroll
-        for (int k = -R; k <= R; ++k) {
-          wx[k + R] = p1[(long long)gy * nx + wrap(gx + k, nx)] + sU1[c + k];
-          wy[k + R] = p2[(long long)wrap(gy + k, ny) * nx + gx] + sU2[c + k * Gm::W];
-        }
-        const Cell g = cell_at<T>(gy * nx + gx);
-        *dcell(I, a.du0_out, g) = d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y);
-      } else if (a.out_du != kNoSlot) {
-#pragma unroll
-        for (int k = -R; k <= R; ++k) {
-          wx[k + R] = sU1[c + k];
-          wy[k + R] = sU2[c + k * Gm::W];
-        }
-        const Cell g = cell_at<T>(gy * nx + gx);
-        *tcell<T>(I, a.out_du, g) = (T)(d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y));
+      for (int k = -R; k <= R; ++k) {
+        wx[k + R] = sU1[c + k];
+        wy[k + R] = sU2[c + k * Gm::W];
       }
+      const Cell g = cell_at<T>(gy * nx + gx);
+      *tcell<T>(I, a.out_du, g) = (T)(d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y));
     }
   }
   __syncthreads();
@@ -1006,6 +996,28 @@ __device__ __forceinline__ void increment_tail(const Inst &I, const Work &wk, co
       if (last) {
         *dcell(I, a.out_ud[0], g) = u1;
         *dcell(I, a.out_ud[1], g) = u2;
+      }
+    }
+  }
+  if (last) {
+    // the float64 D0.u of the new state from the staged u (halved exactly, so twice a
+    // staged value is the u formed above)
+    __syncthreads();
+    if (col) {
+#pragma unroll
+      for (int r = 0; r < Gm::ROWS; ++r) {
+        const int ly = ty0 + Gm::WV * r;
+        const int gy = wk.b + ly;
+        if (gy >= ny) break;
+        const int c = Gm::at(tx, ly);
+        double wx[2 * R + 1], wy[2 * R + 1];
+#pragma unroll
+        for (int k = -R; k <= R; ++k) {
+          wx[k + R] = 2.0 * sU1[c + k];
+          wy[k + R] = 2.0 * sU2[c + k * Gm::W];
+        }
+        const Cell g = cell_at<T>(gy * nx + gx);
+        *dcell(I, a.du0_out, g) = d0_fixed<CO>(wx, f1x) + d0_fixed<CO>(wy, f1y);
       }
     }
   }
