@@ -166,6 +166,32 @@ struct TwStage {
   }
 };
 
+// Twiddles w^r (r = 1..R-1, w = tws entry m, conjugated for DIR > 0) of one butterfly,
+// from one table lookup: the powers by products of depth <= 3 (w^2 = w w, w^3 = w^2 w,
+// w^4 = w^2 w^2, w^(4+j) = w^4 w^j), each applied as soon as it is formed, so at most w,
+// w^2, w^3 and w^4 are live at once.
+template <int R, int DIR>
+__device__ __forceinline__ void twiddle(double2 *v, const double2 *tws, int lb, int m) {
+  double2 w1 = tw_at(tws, lb, m);
+  if (DIR > 0) w1.y = -w1.y;
+  v[1] = cmul(v[1], w1);
+  if constexpr (R >= 3) {
+    const double2 w2 = cmul(w1, w1);
+    v[2] = cmul(v[2], w2);
+    if constexpr (R >= 4) {
+      const double2 w3 = cmul(w2, w1);
+      v[3] = cmul(v[3], w3);
+      if constexpr (R == 8) {
+        const double2 w4 = cmul(w2, w2);
+        v[4] = cmul(v[4], w4);
+        v[5] = cmul(v[5], cmul(w4, w1));
+        v[6] = cmul(v[6], cmul(w4, w2));
+        v[7] = cmul(v[7], cmul(w4, w3));
+      }
+    }
+  }
+}
+
 // One Stockham pass over nb transforms of length n held in LDS, element j of transform b
 // at buf[lp(b n + j)]; consecutive threads take consecutive butterflies of a transform.
 // The first pass (Ns = 1) has unit twiddles and skips them.
@@ -189,29 +215,7 @@ __device__ __forceinline__ void pass(double2 *buf, int n, int nb, int Ns, const 
       const int src = b * n + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[p][r] = buf[lp<SH>(src + r * nbf)];
-      if (Ns > 1) {
-        // w^r for r = 1..R-1 from one table lookup: powers by products of depth <= 3
-        // (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, w^(4+j) = w^4 w^j), each applied as soon
-        // as it is formed, so at most w, w^2, w^3 and w^4 are live at once
-        double2 w1 = tw_at(tws, lb, k * twstep * tsc);
-        if (DIR > 0) w1.y = -w1.y;
-        v[p][1] = cmul(v[p][1], w1);
-        if constexpr (R >= 3) {
-          const double2 w2 = cmul(w1, w1);
-          v[p][2] = cmul(v[p][2], w2);
-          if constexpr (R >= 4) {
-            const double2 w3 = cmul(w2, w1);
-            v[p][3] = cmul(v[p][3], w3);
-            if constexpr (R == 8) {
-              const double2 w4 = cmul(w2, w2);
-              v[p][4] = cmul(v[p][4], w4);
-              v[p][5] = cmul(v[p][5], cmul(w4, w1));
-              v[p][6] = cmul(v[p][6], cmul(w4, w2));
-              v[p][7] = cmul(v[p][7], cmul(w4, w3));
-            }
-          }
-        }
-      }
+      if (Ns > 1) twiddle<R, DIR>(v[p], tws, lb, k * twstep * tsc);
       dft<R, DIR>(v[p]);
       dst[p] = b * n + jq * Ns * R + k;
     }
@@ -244,6 +248,88 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb,
   }
 }
 
+// One transform that fills the buffer (n = CAP, nb = 1, CAP = 8 NT, so n is a power of two
+// and every radix R of its plan is 8, 4 or 2 with R NT dividing CAP) with its values in
+// registers at either end: thread t holds element t + e NT in v[e], e < 8.  A pass takes
+// butterfly j = t + p NT (p < NPER = CAP / (R NT)) from elements j + r CAP / R =
+// t + (p + r NPER) NT, all of them thread t's own: the first pass (Ns = 1, unit twiddles,
+// outputs at j R + r) reads them from registers instead of LDS, and the last (Ns = CAP / R,
+// k = j, twiddle index j) writes its outputs j + r Ns = t + (p + r NPER) NT to registers.
+// The operations are those of fft_lds in the same order; the compiler may still fuse a
+// multiply into an addition differently where values no longer pass through LDS (the
+// forward rows and the columns give the same bits as their LDS forms, the split inverse
+// rows differ in the last bits).  The first pass begins with a barrier when sync_first
+// (buf still being read); the last leaves none (the caller syncs before buf is written).
+template <int R, int DIR, int CAP, int NT, int SH>
+__device__ __forceinline__ void pass_first_reg(const double2 *in, double2 *buf, bool sync_first) {
+  constexpr int NPER = CAP / (R * NT);
+  static_assert(NPER * R * NT == CAP, "radix and threads must tile the buffer");
+  double2 v[NPER][R];
+#pragma unroll
+  for (int p = 0; p < NPER; ++p) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[p][r] = in[p + r * NPER];
+    dft<R, DIR>(v[p]);
+  }
+  if (sync_first) __syncthreads();
+#pragma unroll
+  for (int p = 0; p < NPER; ++p) {
+    const int j = threadIdx.x + p * NT;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[lp<SH>(j * R + r)] = v[p][r];
+  }
+  __syncthreads();
+}
+template <int R, int DIR, int CAP, int NT, int SH>
+__device__ __forceinline__ void pass_last_reg(const double2 *buf, double2 *out, const double2 *tws,
+                                              int lb, int tsc) {
+  constexpr int NPER = CAP / (R * NT);
+  static_assert(NPER * R * NT == CAP, "radix and threads must tile the buffer");
+#pragma unroll
+  for (int p = 0; p < NPER; ++p) {
+    const int j = threadIdx.x + p * NT;
+    double2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = buf[lp<SH>(j + r * (CAP / R))];
+    twiddle<R, DIR>(v, tws, lb, j * tsc);
+    dft<R, DIR>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[p + r * NPER] = v[r];
+  }
+}
+// Radix of the last pass of a length-n plan, n = 2^k: the plans take as many radix-8 passes
+// as fit, first, then one of 4 (k mod 3 = 2) or 2 (k mod 3 = 1).
+constexpr int last_radix_pow2(int n) {
+  int k = 0;
+  while ((1 << k) < n) ++k;
+  return k % 3 == 0 ? 8 : (k % 3 == 2 ? 4 : 2);
+}
+template <int DIR, int CAP, int NT, int SH, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void fft_one(double2 *v, double2 *buf, const FftPlan &P,
+                                        const double2 *tws, bool sync_first) {
+  static_assert(CAP == 8 * NT && (CAP & (CAP - 1)) == 0, "eight values per thread, n = 2^k");
+  // the radices of the register passes are fixed by n = CAP (a switch over the plan's
+  // would make the register arrays dynamically indexed)
+  constexpr int RL = last_radix_pow2(CAP);
+  int Ns = 1, ps = 0;
+  if constexpr (IN_REGS) {
+    pass_first_reg<8, DIR, CAP, NT, SH>(v, buf, sync_first);
+    Ns = 8;
+    ps = 1;
+  }
+  const int last = OUT_REGS ? P.npass - 1 : P.npass;
+  for (; ps < last; ++ps) {
+    const int R = P.radix[ps];
+    switch (R) {
+      case 8: pass<8, DIR, CAP, NT, SH>(buf, CAP, 1, Ns, tws, P.lb, P.tsc); break;
+      case 4: pass<4, DIR, CAP, NT, SH>(buf, CAP, 1, Ns, tws, P.lb, P.tsc); break;
+      default: pass<2, DIR, CAP, NT, SH>(buf, CAP, 1, Ns, tws, P.lb, P.tsc); break;
+    }
+    Ns *= R;
+  }
+  if constexpr (OUT_REGS) pass_last_reg<RL, DIR, CAP, NT, SH>(buf, v, tws, P.lb, P.tsc);
+}
+
 __device__ __forceinline__ Gp<double> dslot(const Inst &I, int slot) {
   return gp(I.dbase + (long long)slot * I.plane);
 }
@@ -260,7 +346,7 @@ __device__ __forceinline__ Gp<dv2> cslot(const Inst &I, int slot) {
 
 // ------------------------------------------------------------------ rows forward
 
-template <int CAP, int NT>
+template <int CAP, int NT, bool DIRECT>
 __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
@@ -288,13 +374,20 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
     }
   }
   tw.store(tws, I.fx);
+  if constexpr (DIRECT) {  // one row pair fills the buffer: the first pass takes the loads
+    double2 z[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) buf[lp(idx)] = make_double2(ra[e], rb[e]);
+    for (int e = 0; e < E; ++e) z[e] = make_double2(ra[e], rb[e]);
+    fft_one<-1, CAP, NT, 3, true, false>(z, buf, I.fx, tws, false);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cnt) buf[lp(idx)] = make_double2(ra[e], rb[e]);
+    }
+    __syncthreads();
+    fft_lds<-1, CAP, NT>(buf, I.fx, np, tws);
   }
-  __syncthreads();
-  fft_lds<-1, CAP, NT>(buf, I.fx, np, tws);
   // column-major half spectra S[k][y] for the 2 np rows y = 2 p0 .. of the block:
   // consecutive threads write consecutive rows of one column
   const int ny = I.ny, m = 2 * np;
@@ -326,7 +419,7 @@ __device__ __forceinline__ double mode_div(const Inst &I, double sig, double lx,
 // The C = cols_per_block columns kx = k0.. of the column-major spectrum, one contiguous
 // run of C ny complex values: forward FFT along y, symbol divide with the (0,0) rule,
 // inverse FFT, stored in place.  Work item (inst, k0).
-template <int CAP, int NT>
+template <int CAP, int NT, bool DIRECT>
 __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
                                              const Work *__restrict__ work, int nwork,
                                              ArgsSolve a) {
@@ -366,13 +459,26 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   }
   if (PRE && k0 == 0) lxh = gp(I.lam_x)[h];
   tw.store(tws, I.fy);
+  // one column fills the buffer: both transforms take and leave their values in registers
+  // (the column-0 block puts the spectrum in LDS too, for the mirrored modes it pairs)
+  constexpr bool direct = DIRECT;
+  if constexpr (direct) {
+    fft_one<-1, CAP, NT, 3, true, true>(v, buf, I.fy, tws, false);
+    if (k0 == 0) {
+      __syncthreads();
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) buf[lp(idx)] = v[e];
+      for (int e = 0; e < E; ++e) buf[lp(threadIdx.x + e * NT)] = v[e];
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cnt) buf[lp(idx)] = v[e];
+    }
+    __syncthreads();
+    fft_lds<-1, CAP, NT>(buf, I.fy, C, tws);
   }
-  __syncthreads();
-  fft_lds<-1, CAP, NT>(buf, I.fy, C, tws);
   double2 o[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -389,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
         lxx = gp(I.lam_x)[k0 + c];
         lxn = k0 + c == 0 ? gp(I.lam_x)[h] : 0.0;
       }
-      const double2 z = buf[lp(idx)];
+      const double2 z = direct ? v[e] : buf[lp(idx)];
       if (k0 + c == 0) {
         // Z = F0 + i Fh with F0, Fh the (Hermitian) y spectra of the real columns kx = 0
         // and kx = nx/2: F0 = (Z[ky] + conj Z[-ky]) / 2, Fh = (Z[ky] - conj Z[-ky]) / 2i
@@ -410,6 +516,14 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
         o[e] = make_double2(z.x * d, z.y * d);
       }
     }
+  }
+  if constexpr (direct) {
+    // (the first inverse pass syncs before it writes: column 0 reads mirrored modes)
+    fft_one<1, CAP, NT, 3, true, true>(o, buf, I.fy, tws, true);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      stc(at_byte(S, (unsigned)(threadIdx.x + e * NT) * 16u), o[e]);
+    return;
   }
   __syncthreads();  // column 0 reads mirrored elements of other threads
 #pragma unroll
@@ -443,7 +557,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
 constexpr int kColSplitThreads = 512;
 constexpr int kColSplitCap = kFftCap / 2;
 
-template <int NT>
+template <int NT, bool DIRECT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cols_split(
     const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
   constexpr int CAP = kColSplitCap;
@@ -474,20 +588,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
   tw.store(tws, I.fy);
   __syncthreads();  // the table is read below
-  // radix-2 step: the even-mode half to LDS, the odd-mode half (times w^y) in x1
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) {
-      const int c = dh.q(idx), y = idx - c * h;
-      buf[lp<0>(idx)] = cadd(x0[e], x1[e]);
-      x1[e] = cmul(csub(x0[e], x1[e]), tw_at(tws, I.fy.lb, y));
-    }
-  }
-  __syncthreads();
-  // mode ky = 2m + par of column c at position c h + m of the half in LDS
-  auto divide = [&](int par) {
-    fft_lds<-1, CAP, NT, 0>(buf, I.fyh, C, tws);
+  // one column per workgroup whose half fills the buffer: each half's two transforms take
+  // and leave their values in registers (the column-0 block puts each spectrum in LDS too,
+  // for the mirrored modes it pairs), and the halves swap places in registers
+  constexpr bool direct = DIRECT;
+  // mode ky = 2m + par of column c at position c h + m of the half; z: its value in v[e]
+  // (direct) or in LDS
+  auto divide_modes = [&](int par, double2 *v) {
     double2 o[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -497,7 +604,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int ky = 2 * m + par;
         const double lyy = gp(I.lam_y)[ky];
         const double lxx = gp(I.lam_x)[k0 + c];
-        const double2 z = buf[lp<0>(idx)];
+        const double2 z = direct ? v[e] : buf[lp<0>(idx)];
         if (k0 + c == 0) {
           // Z = F0 + i Fh for the real columns kx = 0 and kx = nx/2: F0 = (Z[ky] +
           // conj Z[-ky]) / 2, Fh = (Z[ky] - conj Z[-ky]) / 2i; -ky has the parity of ky,
@@ -521,6 +628,67 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
       }
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = o[e];
+  };
+  if constexpr (direct) {
+    // radix-2 step: the even-mode half in v, the odd-mode half (times w^y) in x1 (pinned
+    // there: left alone, the compiler sinks the step to the swap and keeps both loaded
+    // halves live through the even half's transforms instead, which spills them)
+    double2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int y = threadIdx.x + e * NT;
+      v[e] = cadd(x0[e], x1[e]);
+      x1[e] = cmul(csub(x0[e], x1[e]), tw_at(tws, I.fy.lb, y));
+      asm volatile("" : "+v"(x1[e].x), "+v"(x1[e].y));
+    }
+    auto half = [&](int par) {
+      fft_one<-1, CAP, NT, 0, true, true>(v, buf, I.fyh, tws, par == 1);
+      if (k0 == 0) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf[lp<0>(threadIdx.x + e * NT)] = v[e];
+        __syncthreads();
+      }
+      divide_modes(par, v);
+      fft_one<1, CAP, NT, 0, true, true>(v, buf, I.fyh, tws, true);
+    };
+    half(0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {  // ya to x1, the odd half to v
+      const double2 t = x1[e];
+      x1[e] = v[e];
+      v[e] = t;
+    }
+    half(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int y = threadIdx.x + e * NT;
+      double2 w = tw_at(tws, I.fy.lb, y);
+      w.y = -w.y;  // w^-y
+      const double2 yb = cmul(v[e], w);
+      const unsigned b = (unsigned)y * 16u;
+      stc(at_byte(S, b), cadd(x1[e], yb));
+      stc(at_byte(S, b + (unsigned)h * 16u), csub(x1[e], yb));
+    }
+    return;
+  }
+  // radix-2 step: the even-mode half to LDS, the odd-mode half (times w^y) in x1
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (idx < cnt) {
+      const int c = dh.q(idx), y = idx - c * h;
+      buf[lp<0>(idx)] = cadd(x0[e], x1[e]);
+      x1[e] = cmul(csub(x0[e], x1[e]), tw_at(tws, I.fy.lb, y));
+    }
+  }
+  __syncthreads();
+  auto divide = [&](int par) {
+    fft_lds<-1, CAP, NT, 0>(buf, I.fyh, C, tws);
+    double2 o[E];
+    divide_modes(par, o);
     __syncthreads();  // column 0 reads mirrored elements of other threads
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -560,7 +728,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ------------------------------------------------------------------ rows inverse
 
-template <int CAP, int NT>
+template <int CAP, int NT, bool DIRECT>
 __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
@@ -606,8 +774,19 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
     }
   }
   __syncthreads();
-  fft_lds<1, CAP, NT>(buf, I.fx, np, tws);
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
+  if constexpr (DIRECT) {  // one row pair fills the buffer: the last pass leaves it in registers
+    double2 z[EO];
+    fft_one<1, CAP, NT, 3, false, true>(z, buf, I.fx, tws, false);
+#pragma unroll
+    for (int e = 0; e < EO; ++e) {
+      const unsigned o = (unsigned)(threadIdx.x + e * NT) * 8u;
+      *at_byte(T, o) = z[e].x;
+      *at_byte(T, o + (unsigned)n * 8u) = z[e].y;
+    }
+    return;
+  }
+  fft_lds<1, CAP, NT>(buf, I.fx, np, tws);
   const Div dn(n);
 #pragma unroll
   for (int e = 0; e < EO; ++e) {
@@ -659,7 +838,7 @@ __device__ __forceinline__ void put_modes(double2 *buf, int h, int par, int m, i
   }
 }
 
-template <int NT, int SH>
+template <int NT, int SH, bool DIRECT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_inverse_split(
     const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
   constexpr int CAP = kFftCap / 2;
@@ -701,17 +880,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     __syncthreads();
   };
+  // one row pair whose half fills the buffer: the last pass of each half transform leaves
+  // it in registers
+  constexpr bool direct = DIRECT;
   load_half(0, true);
-  fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
-  double2 ya[E];
+  double2 ya[E], yb[E];
+  if constexpr (direct) {
+    fft_one<1, CAP, NT, SH, false, true>(ya, buf, I.fxh, tws, false);
+  } else {
+    fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
-    if (idx < cnt) ya[e] = buf[lp<SH>(idx)];
+    for (int e = 0; e < E; ++e) {
+      const int idx = threadIdx.x + e * NT;
+      if (idx < cnt) ya[e] = buf[lp<SH>(idx)];
+    }
   }
   __syncthreads();
   load_half(1, false);
-  fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
+  if constexpr (direct)
+    fft_one<1, CAP, NT, SH, false, true>(yb, buf, I.fxh, tws, false);
+  else
+    fft_lds<1, CAP, NT, SH>(buf, I.fxh, np, tws);
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -720,8 +909,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const int p = dh.q(idx), t = idx - p * h;
       double2 w = tw_at(tws, I.fx.lb, t);
       w.y = -w.y;  // w^-t
-      const double2 yb = cmul(buf[lp<SH>(idx)], w);
-      const double2 lo = cadd(ya[e], yb), hi = csub(ya[e], yb);
+      const double2 yb_t = cmul(direct ? yb[e] : buf[lp<SH>(idx)], w);
+      const double2 lo = cadd(ya[e], yb_t), hi = csub(ya[e], yb_t);
       const unsigned o = (unsigned)(2 * p * n + t) * 8u;
       *at_byte(T, o) = lo.x;
       *at_byte(T, o + (unsigned)n * 8u) = lo.y;
@@ -731,42 +920,62 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values
-// (the launch takes ev, st, insts and a of the calling function).
-#define APDVM_FFT_FORM(V, KERNEL, WORK, NWORK)                                             \
-  do {                                                                                     \
-    if ((V) == 2)                                                                          \
-      APDVM_LAUNCH(ev, (KERNEL<kFftCap, kFftThreads>), dim3(NWORK), dim3(kFftThreads), st, \
-                   insts, WORK, NWORK, a);                                                 \
-    else if ((V) == 1)                                                                     \
-      APDVM_LAUNCH(ev, (KERNEL<kColMidCap, kColMidThreads>), dim3(NWORK),                  \
-                   dim3(kColMidThreads), st, insts, WORK, NWORK, a);                       \
-    else                                                                                   \
-      APDVM_LAUNCH(ev, (KERNEL<kRowSmallCap, kRowSmallThreads>), dim3(NWORK),              \
-                   dim3(kRowSmallThreads), st, insts, WORK, NWORK, a);                     \
+// Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values;
+// D: the register form (every line of the launch fills the form's buffer) (the launch
+// takes ev, st, insts and a of the calling function).
+#define APDVM_FFT_FORM_D(V, D, KERNEL, WORK, NWORK)                                           \
+  do {                                                                                       \
+    if ((V) == 2)                                                                            \
+      APDVM_LAUNCH(ev, (KERNEL<kFftCap, kFftThreads, D>), dim3(NWORK), dim3(kFftThreads), st, \
+                   insts, WORK, NWORK, a);                                                   \
+    else if ((V) == 1)                                                                       \
+      APDVM_LAUNCH(ev, (KERNEL<kColMidCap, kColMidThreads, D>), dim3(NWORK),                 \
+                   dim3(kColMidThreads), st, insts, WORK, NWORK, a);                         \
+    else                                                                                     \
+      APDVM_LAUNCH(ev, (KERNEL<kRowSmallCap, kRowSmallThreads, D>), dim3(NWORK),             \
+                   dim3(kRowSmallThreads), st, insts, WORK, NWORK, a);                       \
+  } while (0)
+#define APDVM_FFT_FORM(V, FULL, KERNEL, WORK, NWORK)                 \
+  do {                                                              \
+    if (FULL)                                                       \
+      APDVM_FFT_FORM_D(V, true, KERNEL, WORK, NWORK);               \
+    else                                                            \
+      APDVM_FFT_FORM_D(V, false, KERNEL, WORK, NWORK);              \
   } while (0)
 
 // part 0: rows forward, 1: columns, 2: rows inverse; rowv and colv the kernel forms
 // (the smallest that holds a whole row, a whole column; rowv 3: the largest row form,
-// with the inverse rows split in halves).
-hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, const Work *rows,
-                             int nrows, const Work *cols, int ncols, const ArgsSolve &a,
-                             hipStream_t st, const Ev &ev) {
+// with the inverse rows split in halves); rowfull (colfull): every row (column) of every
+// instance is as long as its form holds (the largest form: kFftCap), so each workgroup
+// transforms one line with its values in registers at the ends of the transforms.
+hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+                             const Inst *insts, const Work *rows, int nrows, const Work *cols,
+                             int ncols, const ArgsSolve &a, hipStream_t st, const Ev &ev) {
   switch (part) {
-    case 0: APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, k_rows_forward, rows, nrows); break;
+    case 0: APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowfull, k_rows_forward, rows, nrows); break;
     case 1:
-      if (colv == 2)  // the largest columns: half the LDS, two workgroups per CU
-        APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads>), dim3(ncols), dim3(kColSplitThreads),
-                     st, insts, cols, ncols, a);
-      else
-        APDVM_FFT_FORM(colv, k_cols, cols, ncols);
+      if (colv == 2) {  // the largest columns: half the LDS, two workgroups per CU
+        if (colfull)
+          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, true>), dim3(ncols),
+                       dim3(kColSplitThreads), st, insts, cols, ncols, a);
+        else
+          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, false>), dim3(ncols),
+                       dim3(kColSplitThreads), st, insts, cols, ncols, a);
+      } else {
+        APDVM_FFT_FORM(colv, colfull, k_cols, cols, ncols);
+      }
       break;
     default:
-      if (rowv == 3)  // the largest rows, nx a multiple of 4: half the LDS, two per CU
-        APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad>), dim3(nrows),
-                     dim3(kRowSplitThreads), st, insts, rows, nrows, a);
-      else
-        APDVM_FFT_FORM(rowv, k_rows_inverse, rows, nrows);
+      if (rowv == 3) {  // the largest rows, nx a multiple of 4: half the LDS, two per CU
+        if (rowfull)
+          APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad, true>),
+                       dim3(nrows), dim3(kRowSplitThreads), st, insts, rows, nrows, a);
+        else
+          APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad, false>),
+                       dim3(nrows), dim3(kRowSplitThreads), st, insts, rows, nrows, a);
+      } else {
+        APDVM_FFT_FORM(rowv, rowfull, k_rows_inverse, rows, nrows);
+      }
       break;
   }
   return hipGetLastError();

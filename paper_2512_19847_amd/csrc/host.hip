@@ -44,8 +44,9 @@ inline int shape_of(int rows, int threads) {
     if (kShapeRows[si] == rows && kShapeThreads[si] == threads) return si;
   return -1;
 }
-hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *, const Work *, int,
-                             const Work *, int, const ArgsSolve &, hipStream_t, const Ev &);
+hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+                             const Inst *, const Work *, int, const Work *, int,
+                             const ArgsSolve &, hipStream_t, const Ev &);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
                               int, int, double *, int, hipStream_t);
 hipError_t launch_field_stats(int split, const void *const f[6], long long n, double *partials,
@@ -448,6 +449,7 @@ struct apdvm_ctx {
   int nrows = 0, ncols = 0;
   int row_v = 0, col_v = 0;  // FFT kernel forms of the rows and columns (fft_form)
   bool row_split = false;    // inverse rows split in halves (largest form, every nx % 4 == 0)
+  bool row_full = false, col_full = false;  // every nx (ny) is its form's capacity
   int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
@@ -814,7 +816,7 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
     case kCols:
     case kRowsInv:
       return launch_solve_part(l.cls - kRowsFwd, c->row_split ? 3 : c->row_v, c->col_v,
-                               c->d_inst, c->d_rows,
+                               c->row_full, c->col_full, c->d_inst, c->d_rows,
                                c->nrows, c->d_cols, c->ncols, l.sv, st, ev);
     case kUpdateUQ:
       return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st, ev);
@@ -1190,6 +1192,11 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->row_split = c->row_v == 2;
   for (int k = 0; k < n; ++k) c->row_split = c->row_split && cfgs[k].nx % 4 == 0;
   c->col_v = col_form(n, cfgs);
+  c->row_full = c->col_full = true;
+  for (int k = 0; k < n; ++k) {
+    c->row_full = c->row_full && cfgs[k].nx == form_cap(c->row_v);
+    c->col_full = c->col_full && cfgs[k].ny == form_cap(c->col_v);
+  }
   for (int k = 0; k < kNumClasses; ++k) c->shape[k] = 1;
   c->wo = weno_order_of(cfgs[0]);
   c->co = central_order_of(cfgs[0]);

@@ -399,9 +399,9 @@ hipError_t launch_div_u(int co, const Inst *insts, const Work *tiles, int nwork,
 
 // ---------------------------------------------------------------- Helmholtz solve
 
-hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, const Work *rows,
-                             int nrows, const Work *cols, int ncols, const ArgsSolve &a,
-                             hipStream_t st, const Ev &) {
+hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+                             const Inst *insts, const Work *rows, int nrows, const Work *cols,
+                             int ncols, const ArgsSolve &a, hipStream_t st, const Ev &) {
   if (part < 0 || part > 2 || rowv < 0 || rowv > 3 || colv < 0 || colv > 2)
     fail("solve: part %d, forms %d %d", part, rowv, colv);
   hostcheck::enqueue(st, [=] {
@@ -410,11 +410,12 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
     const Work *work = is_rows ? rows : cols;
     const int nwork = is_rows ? nrows : ncols;
     const int v = is_rows ? rowv : colv;
+    const bool full = is_rows ? rowfull : colfull;
     const int cap = v == 0 ? kRowSmallCap : v == 1 ? kColMidCap : kFftCap;  // v 3: halved
-    static std::set<std::tuple<const void *, unsigned long long, int, int, int>> walked;
+    static std::set<std::tuple<const void *, unsigned long long, int, int, int, bool>> walked;
     const bool walk =
         !in_device(work, (size_t)nwork * sizeof(Work)) ||
-        walked.insert({insts, table_hash(work, nwork), nwork, part, v}).second;
+        walked.insert({insts, table_hash(work, nwork), nwork, part, v, full}).second;
     if (walk) check_remap(nwork);
     std::set<int> seen;
     std::map<int, std::vector<char>> cover;
@@ -450,6 +451,20 @@ hipError_t launch_solve_part(int part, int rowv, int colv, const Inst *insts, co
       if (need > have)
         fail("solve part %d: block of instance %d needs %lld LDS values, form holds %lld", part,
              w->inst, need, have);
+      if (full) {
+        // register form: one line per block that fills the form's buffer, and a plan of
+        // length 2^k whose first radix is 8 and whose last is 8, 2 or 4 for k mod 3 = 0, 1, 2
+        const int n_line = is_rows ? I.nx : I.ny;
+        const FftPlan &P = split_cols ? I.fyh : split_rows ? I.fxh : is_rows ? I.fx : I.fy;
+        const int n_plan = split_cols || split_rows ? n_line / 2 : n_line;
+        int k = 0;
+        while ((1 << k) < P.n) ++k;
+        const int last = k % 3 == 0 ? 8 : k % 3 == 1 ? 2 : 4;
+        if (n_line != cap || cnt_lines != 1 || P.n != n_plan || (1 << k) != P.n ||
+            P.npass < 2 || P.radix[0] != 8 || P.radix[P.npass - 1] != last)
+          fail("solve part %d: register form on instance %d (line %d, form %d, %d lines, plan "
+               "%d in %d passes)", part, w->inst, n_line, cap, cnt_lines, P.n, P.npass);
+      }
       auto &cv = cover[w->inst];
       if (cv.empty()) cv.assign(lines, 0);
       for (int l = x0; l < x0 + cnt_lines; ++l) {

@@ -218,6 +218,25 @@ def test_extreme_aspect_ratios_every_fft_form(sides):
         assert max(err.values()) <= TOL, (k, err)
 
 
+@pytest.mark.parametrize("side", [(8192, 8), (8, 8192), (2048, 16), (16, 2048), (1024, 8),
+                                  (8, 1024)])
+def test_lines_filling_their_fft_form(side):
+    """One long thin instance per context, so that every row (column) fills its FFT form
+    (1024, 2048 or 8192 values, the 8192-value rows inverted and columns transformed in the
+    split halves): the FFT kernels run their register forms, which take the first pass from
+    the loaded values and keep the last in registers.  Two steps against the oracle, v and
+    q held against max |u|^2 as for the other thin instances."""
+    nx, ny = side
+    c = wl.make_case("full", wl.random_divfree(nx, ny, kmax=3, rms=0.1, seed=70),
+                     0.05, 0.05, "ars443", cfl=wl.CFL_ARS)
+    _say(f"case lines filling their form {side}")
+    got = _run_gpu([dict(state=c.state, eps=c.eps, tau=c.tau, dt=c.dt)], "ars443", 2)[0]
+    ref = _oracle(c.state, c.eps, c.tau, c.dt, "ars443", 2)
+    err = _relerr(got, ref, kinetic_floor=True)
+    _say(f"  relerr {err}")
+    assert max(err.values()) <= TOL, err
+
+
 @pytest.mark.parametrize("eps", [1.0, 1e-2, 1e-6])
 def test_shear_layer_512_one_step(eps):
     """Full 512^2 size of the third-order shear-layer runs, one step, every cell."""

@@ -7,7 +7,8 @@ slots inside their arenas, no launch writing a plane it reads, FFT blocks fittin
 LDS form and covering every line once).  Scenarios: both precisions, every tableau
 family, WENO3 / second-order operators, ragged and batched instances, and the long thin
 grids that take every FFT form (including the split 8192-value column and inverse-row
-forms, and the whole-row form that rows of nx = 2 mod 4 keep)."""
+forms, and the whole-row form that rows of nx = 2 mod 4 keep), and grids whose rows or
+columns fill their form (the FFT register forms)."""
 
 import os
 import subprocess
@@ -34,6 +35,11 @@ SCENARIOS = [
                                              (6144, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("whole_rows_nx_2mod4", 1, "ars443", [(4374, 8, 0.05, 0.05, -1.0, 0.0, 5, 4),
                                           (8, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    # every row (column) as long as its form holds: the FFT register forms
+    ("full_rows_1024_fp64", 0, "ars443", [(1024, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("full_cols_2048_split", 1, "ars443", [(8, 2048, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("full_rows_8192_split", 1, "ars443", [(8192, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("full_cols_8192_fp64", 0, "ars443", [(8, 8192, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("batch_sizes_split", 1, "ars443",
      [(n, n, 10.0 ** -(k % 7), 0.01 + 0.01 * k, -1.0, 0.0, 5, 4)
       for k, n in enumerate((64, 96, 128, 192, 64, 96, 8, 16, 24, 48))]),
@@ -76,9 +82,9 @@ def test_every_launch_in_bounds_under_asan(checker):
 def test_checks_catch_planted_mistakes(checker):
     """The checks are not vacuous: launches with a duplicated tile, a tile off the grid, a
     slot beyond its arena, an output that is also an input, a float launch on a float64
-    arena and an FFT row block beyond its LDS form are each reported, and the correct
-    launch is not."""
+    arena, an FFT row block beyond its LDS form and the FFT register form on rows shorter
+    than that form are each reported, and the correct launch is not."""
     r = subprocess.run([checker, "--self-test"], capture_output=True, text=True, timeout=120)
     print(r.stdout, r.stderr)
     assert r.returncode == 0, r.stderr
-    assert "7 of 7 planted cases judged correctly" in r.stdout
+    assert "8 of 8 planted cases judged correctly" in r.stdout
