@@ -19,9 +19,12 @@
 //                 spectra by their Hermitian symmetry, each with its own divisor), inverse
 //                 FFT, in place.
 //  rows inverse   Hermitian extension of the half spectra, inverse FFT, two real rows.
-// The largest column form, and the inverse rows of the largest row form when every nx is
-// a multiple of 4, run split: a radix-2 step in registers leaves two half-length
-// transforms, done one after the other in half the LDS, so two workgroups share a CU.
+// The largest column form, the inverse rows of the largest row form when every nx is a
+// multiple of 4, and the forward rows when every nx is that form's length, run split: a
+// radix-2 step in registers leaves two half-length transforms, done one after the other in
+// half the LDS, so two workgroups share a CU.  Where every line of a launch fills its form,
+// each transform takes its first pass from registers and, where its values stay with the
+// thread, leaves its last pass there (fft_one).
 //
 // Every FFT is a mixed-radix (8, 4, 3, 2) Stockham autosort transform in LDS: each pass
 // reads R strided inputs per butterfly, applies twiddles from a float64 table of
@@ -406,6 +409,76 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
                    : make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
     stc(at_byte(S, (unsigned)(k * ny + yl) * 16u), o);
   }
+}
+
+// Forward rows of nx = kFftCap in half the LDS, as the split column kernel does for columns
+// (n = nx, h = n / 2, w = exp(-2 pi i / n)): a radix-2 decimation in frequency in registers,
+//   Z[2m] = FFT_h(z[t] + z[t + h])[m],  Z[2m + 1] = FFT_h((z[t] - z[t + h]) w^t)[m],
+// leaves two length-h transforms, done one after the other with the odd half held in
+// registers.  The Hermitian partner Z[n - k] of a mode has its parity (n is even): Z[2m]
+// pairs with Z[2(h - m)] (Z[0] with Z[h] = Z[2 (h / 2)]), Z[2m + 1] with Z[2(h - 1 - m) + 1],
+// so each half writes its columns of the half spectra (k = 2m, then k = 2m + 1) from LDS
+// as soon as it is transformed.  One row pair per workgroup (the register form of both
+// half transforms' first pass); two workgroups share a CU, so one loads or stores while the
+// other transforms.
+constexpr int kRowFwdSplitThreads = 512;
+
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_forward_split(
+    const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
+  constexpr int CAP = kFftCap / 2;
+  constexpr int E = CAP / NT;  // values of a half per thread
+  __shared__ double2 buf[CAP];
+  __shared__ double2 tws[kTwCap];
+  const Work wk = work[xcd_item_fft(nwork)];
+  const Inst &I = insts[wk.inst];
+  const int n = I.nx, h = n / 2, ny = I.ny;
+  const int p0 = wk.a;
+  const Gp<const double> R = dslot(I, a.r) + 2LL * p0 * n;
+  TwStage<NT> tw;
+  tw.load(I.fx);
+  double2 v[E], x1[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {  // z[t] and z[t + h]: rows 2 p0 (real) and 2 p0 + 1 (imaginary)
+    const unsigned t = threadIdx.x + e * NT;
+    v[e] = make_double2(*at_byte(R, t * 8u), *at_byte(R, (t + (unsigned)n) * 8u));
+    x1[e] = make_double2(*at_byte(R, (t + (unsigned)h) * 8u),
+                         *at_byte(R, (t + (unsigned)(n + h)) * 8u));
+  }
+  tw.store(tws, I.fx);
+  __syncthreads();  // the table is read below
+  // radix-2 step: the even half in v, the odd half (times w^t) in x1, pinned there (left
+  // alone, the compiler sinks the step past the even half's transform and keeps both loaded
+  // halves live through it)
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int t = threadIdx.x + e * NT;
+    const double2 s = cadd(v[e], x1[e]);
+    x1[e] = cmul(csub(v[e], x1[e]), tw_at(tws, I.fx.lb, t));
+    v[e] = s;
+    asm volatile("" : "+v"(x1[e].x), "+v"(x1[e].y));
+  }
+  const Gp<dv2> S = cslot(I, a.spec) + 2LL * p0;
+  // columns k = 2m + par of the two rows from the transformed half in LDS: A = (Z + conj W)
+  // / 2 and B = (Z - conj W) / 2i, W = Z[n - k]; k = 0 packs (A[0], A[n/2]) and (B[0], B[n/2])
+  auto put_columns = [&](int par) {
+    for (int idx = threadIdx.x; idx < h; idx += NT) {  // h / 2 columns of two rows
+      const int m = idx >> 1, yl = idx & 1, k = 2 * m + par;
+      const double2 Z = buf[m];
+      const double2 W = buf[par ? h - 1 - m : (m == 0 ? h / 2 : h - m)];
+      double2 o;
+      if (k == 0)
+        o = yl ? make_double2(Z.y, W.y) : make_double2(Z.x, W.x);
+      else
+        o = yl ? make_double2(0.5 * (Z.y + W.y), -0.5 * (Z.x - W.x))
+               : make_double2(0.5 * (Z.x + W.x), 0.5 * (Z.y - W.y));
+      stc(at_byte(S, (unsigned)(k * ny + yl) * 16u), o);
+    }
+  };
+  fft_one<-1, CAP, NT, 0, true, false>(v, buf, I.fxh, tws, false);
+  put_columns(0);
+  fft_one<-1, CAP, NT, 0, true, false>(x1, buf, I.fxh, tws, true);
+  put_columns(1);
 }
 
 // ------------------------------------------------------------------ columns
@@ -812,10 +885,9 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
 // is a multiple of 4): Z[2m] with Z[2(h - m)] (Z[h] = the even mode h / 2 shares column 0
 // with Z[0]), Z[2m + 1] with Z[2(h - 1 - m) + 1].  A workgroup holds C h <= kFftCap / 2
 // values (C the row pairs of a block, as in the whole-row form), so two workgroups share a
-// CU and one loads or stores while the other transforms.  (The forward rows keep the
-// whole-row form: split the same way, with the odd half held in registers through the
-// even half's transform, that kernel spilled 0.45 GB of registers per 8192^2 launch and
-// measured no faster.)
+// CU and one loads or stores while the other transforms.  (The forward rows split the same
+// way only where every nx is kFftCap, k_rows_forward_split: with the first pass of each half
+// taken from registers and the odd half pinned there, it spills nothing.)
 constexpr int kRowSplitThreads = 512;
 // LDS padding of the split row kernel (lp): none, as the split column kernel (one in 8
 // measured no faster).
@@ -952,7 +1024,13 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
                              const Inst *insts, const Work *rows, int nrows, const Work *cols,
                              int ncols, const ArgsSolve &a, hipStream_t st, const Ev &ev) {
   switch (part) {
-    case 0: APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowfull, k_rows_forward, rows, nrows); break;
+    case 0:
+      if (rowv == 3 && rowfull)  // rows of kFftCap: half the LDS, two workgroups per CU
+        APDVM_LAUNCH(ev, (k_rows_forward_split<kRowFwdSplitThreads>), dim3(nrows),
+                     dim3(kRowFwdSplitThreads), st, insts, rows, nrows, a);
+      else
+        APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowfull, k_rows_forward, rows, nrows);
+      break;
     case 1:
       if (colv == 2) {  // the largest columns: half the LDS, two workgroups per CU
         if (colfull)

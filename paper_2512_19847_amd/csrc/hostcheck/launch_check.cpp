@@ -441,7 +441,8 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
       }
       const int cnt_lines = std::min(per, lines - x0);
       const bool split_cols = !is_rows && v == 2;  // the largest column form halves
-      const bool split_rows = part == 2 && v == 3;  // so do the largest inverse rows
+      // so do the largest inverse rows, and the forward rows that fill the form
+      const bool split_rows = v == 3 && (part == 2 || (part == 0 && full));
       if (split_rows && I.nx % 4)
         fail("solve part %d: split rows of instance %d with nx = %d", part, w->inst, I.nx);
       const long long need = split_cols   ? (long long)cnt_lines * (I.ny / 2)
