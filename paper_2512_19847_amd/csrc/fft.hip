@@ -136,7 +136,8 @@ __device__ __forceinline__ P at_byte(P base, unsigned b) {
 // LDS layout of the FFT buffers: one padding element after every 2^SH (none for SH = 0),
 // so the strided writes of the early Stockham passes (stride R Ns elements of 16 bytes)
 // spread over the banks instead of hitting the same few.  SH = 3 for the whole-row and
-// whole-column kernels; the split column kernel measured fastest without padding.
+// whole-column kernels, SH = 4 for the split kernels (their 4096-value halves, two
+// workgroups per CU).
 template <int SH = 3>
 __device__ __forceinline__ int lp(int i) {
   return SH ? i + (i >> SH) : i;
@@ -422,13 +423,15 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
 // half transforms' first pass); two workgroups share a CU, so one loads or stores while the
 // other transforms.
 constexpr int kRowFwdSplitThreads = 512;
+// LDS padding of the split forward rows (lp): one element in 16, as the other split kernels.
+constexpr int kRowFwdSplitPad = 4;
 
-template <int NT>
+template <int NT, int SH>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rows_forward_split(
     const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
   constexpr int CAP = kFftCap / 2;
   constexpr int E = CAP / NT;  // values of a half per thread
-  __shared__ double2 buf[CAP];
+  __shared__ double2 buf[SH ? CAP + (CAP >> SH) : CAP];
   __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
@@ -464,8 +467,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   auto put_columns = [&](int par) {
     for (int idx = threadIdx.x; idx < h; idx += NT) {  // h / 2 columns of two rows
       const int m = idx >> 1, yl = idx & 1, k = 2 * m + par;
-      const double2 Z = buf[m];
-      const double2 W = buf[par ? h - 1 - m : (m == 0 ? h / 2 : h - m)];
+      const double2 Z = buf[lp<SH>(m)];
+      const double2 W = buf[lp<SH>(par ? h - 1 - m : (m == 0 ? h / 2 : h - m))];
       double2 o;
       if (k == 0)
         o = yl ? make_double2(Z.y, W.y) : make_double2(Z.x, W.x);
@@ -475,9 +478,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       stc(at_byte(S, (unsigned)(k * ny + yl) * 16u), o);
     }
   };
-  fft_one<-1, CAP, NT, 0, true, false>(v, buf, I.fxh, tws, false);
+  fft_one<-1, CAP, NT, SH, true, false>(v, buf, I.fxh, tws, false);
   put_columns(0);
-  fft_one<-1, CAP, NT, 0, true, false>(x1, buf, I.fxh, tws, true);
+  fft_one<-1, CAP, NT, SH, true, false>(x1, buf, I.fxh, tws, true);
   put_columns(1);
 }
 
@@ -624,18 +627,21 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
 // (ya, yb the inverse transforms of the even and odd modes; unnormalised, the divisors
 // carry 1 / (nx ny)).  A workgroup of kColSplitThreads holds C h <= kFftCap / 2 values in
 // LDS, so two workgroups share a CU and one loads or stores while the other transforms.
-// Four waves per SIMD cap the registers at 128 (the two halves in flight spill a little);
-// the buffer is not padded, which measured fastest for this kernel.
+// Four waves per SIMD cap the registers at 128 (the two halves in flight spill a little in
+// the LDS form; the register form spills 8 bytes); the buffer is padded one in 16.
 // Work item (inst, k0) with C = cols_per_block columns.
 constexpr int kColSplitThreads = 512;
+// LDS padding of the split column kernel (lp): one element in 16 (register form, 8192^2:
+// 365-369 us per launch against 403-406 unpadded and 410 with one in 8).
+constexpr int kColSplitPad = 4;
 constexpr int kColSplitCap = kFftCap / 2;
 
-template <int NT, bool DIRECT>
+template <int NT, int SH, bool DIRECT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_cols_split(
     const Inst *__restrict__ insts, const Work *__restrict__ work, int nwork, ArgsSolve a) {
   constexpr int CAP = kColSplitCap;
   constexpr int E = CAP / NT;  // elements of a half per thread
-  __shared__ double2 buf[CAP];
+  __shared__ double2 buf[SH ? CAP + (CAP >> SH) : CAP];
   __shared__ double2 tws[kTwCap];
   const Work wk = work[xcd_item_fft(nwork)];
   const Inst &I = insts[wk.inst];
@@ -677,13 +683,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int ky = 2 * m + par;
         const double lyy = gp(I.lam_y)[ky];
         const double lxx = gp(I.lam_x)[k0 + c];
-        const double2 z = direct ? v[e] : buf[lp<0>(idx)];
+        const double2 z = direct ? v[e] : buf[lp<SH>(idx)];
         if (k0 + c == 0) {
           // Z = F0 + i Fh for the real columns kx = 0 and kx = nx/2: F0 = (Z[ky] +
           // conj Z[-ky]) / 2, Fh = (Z[ky] - conj Z[-ky]) / 2i; -ky has the parity of ky,
           // at position (h - m - par) mod h of the same half
           const int mm = par ? h - 1 - m : (m == 0 ? 0 : h - m);
-          const double2 zm = buf[lp<0>(mm)];
+          const double2 zm = buf[lp<SH>(mm)];
           double2 f0 = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
           double2 fh = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
           const double dhh = mode_div(I, sig, gp(I.lam_x)[hx], lyy);
@@ -717,15 +723,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       asm volatile("" : "+v"(x1[e].x), "+v"(x1[e].y));
     }
     auto half = [&](int par) {
-      fft_one<-1, CAP, NT, 0, true, true>(v, buf, I.fyh, tws, par == 1);
+      fft_one<-1, CAP, NT, SH, true, true>(v, buf, I.fyh, tws, par == 1);
       if (k0 == 0) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) buf[lp<0>(threadIdx.x + e * NT)] = v[e];
+        for (int e = 0; e < E; ++e) buf[lp<SH>(threadIdx.x + e * NT)] = v[e];
         __syncthreads();
       }
       divide_modes(par, v);
-      fft_one<1, CAP, NT, 0, true, true>(v, buf, I.fyh, tws, true);
+      fft_one<1, CAP, NT, SH, true, true>(v, buf, I.fyh, tws, true);
     };
     half(0);
 #pragma unroll
@@ -753,23 +759,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
       const int c = dh.q(idx), y = idx - c * h;
-      buf[lp<0>(idx)] = cadd(x0[e], x1[e]);
+      buf[lp<SH>(idx)] = cadd(x0[e], x1[e]);
       x1[e] = cmul(csub(x0[e], x1[e]), tw_at(tws, I.fy.lb, y));
     }
   }
   __syncthreads();
   auto divide = [&](int par) {
-    fft_lds<-1, CAP, NT, 0>(buf, I.fyh, C, tws);
+    fft_lds<-1, CAP, NT, SH>(buf, I.fyh, C, tws);
     double2 o[E];
     divide_modes(par, o);
     __syncthreads();  // column 0 reads mirrored elements of other threads
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int idx = threadIdx.x + e * NT;
-      if (idx < cnt) buf[lp<0>(idx)] = o[e];
+      if (idx < cnt) buf[lp<SH>(idx)] = o[e];
     }
     __syncthreads();
-    fft_lds<1, CAP, NT, 0>(buf, I.fyh, C, tws);
+    fft_lds<1, CAP, NT, SH>(buf, I.fyh, C, tws);
   };
   divide(0);
   // swap: each thread takes its elements of ya and puts its odd half in their place
@@ -777,8 +783,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int e = 0; e < E; ++e) {
     const int idx = threadIdx.x + e * NT;
     if (idx < cnt) {
-      const double2 ya = buf[lp<0>(idx)];
-      buf[lp<0>(idx)] = x1[e];
+      const double2 ya = buf[lp<SH>(idx)];
+      buf[lp<SH>(idx)] = x1[e];
       x1[e] = ya;
     }
   }
@@ -791,7 +797,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       const int c = dh.q(idx), y = idx - c * h;
       double2 w = tw_at(tws, I.fy.lb, y);
       w.y = -w.y;  // w^-y
-      const double2 yb = cmul(buf[lp<0>(idx)], w);
+      const double2 yb = cmul(buf[lp<SH>(idx)], w);
       const unsigned b = (unsigned)(c * ny + y) * 16u;
       stc(at_byte(S, b), cadd(x1[e], yb));
       stc(at_byte(S, b + (unsigned)h * 16u), csub(x1[e], yb));
@@ -889,9 +895,9 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
 // way only where every nx is kFftCap, k_rows_forward_split: with the first pass of each half
 // taken from registers and the odd half pinned there, it spills nothing.)
 constexpr int kRowSplitThreads = 512;
-// LDS padding of the split row kernel (lp): none, as the split column kernel (one in 8
-// measured no faster).
-constexpr int kRowSplitPad = 0;
+// LDS padding of the split row kernel (lp): one element in 16 (register form, 8192^2:
+// 342 us per launch against 354 unpadded; one in 8 as fast).
+constexpr int kRowSplitPad = 4;
 
 // Even (par 0) or odd (par 1) modes of the Hermitian extensions of C row pairs' half
 // spectra into buf (pair p at p h), from the loaded column-major values A, B of rows 2p and
@@ -1026,7 +1032,7 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
   switch (part) {
     case 0:
       if (rowv == 3 && rowfull)  // rows of kFftCap: half the LDS, two workgroups per CU
-        APDVM_LAUNCH(ev, (k_rows_forward_split<kRowFwdSplitThreads>), dim3(nrows),
+        APDVM_LAUNCH(ev, (k_rows_forward_split<kRowFwdSplitThreads, kRowFwdSplitPad>), dim3(nrows),
                      dim3(kRowFwdSplitThreads), st, insts, rows, nrows, a);
       else
         APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowfull, k_rows_forward, rows, nrows);
@@ -1034,10 +1040,10 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
     case 1:
       if (colv == 2) {  // the largest columns: half the LDS, two workgroups per CU
         if (colfull)
-          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, true>), dim3(ncols),
+          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, kColSplitPad, true>), dim3(ncols),
                        dim3(kColSplitThreads), st, insts, cols, ncols, a);
         else
-          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, false>), dim3(ncols),
+          APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, kColSplitPad, false>), dim3(ncols),
                        dim3(kColSplitThreads), st, insts, cols, ncols, a);
       } else {
         APDVM_FFT_FORM(colv, colfull, k_cols, cols, ncols);
