@@ -261,9 +261,10 @@ __device__ __forceinline__ void fft_lds(double2 *buf, const FftPlan &P, int nb,
 // k = j, twiddle index j) writes its outputs j + r Ns = t + (p + r NPER) NT to registers.
 // The operations are those of fft_lds in the same order; the compiler may still fuse a
 // multiply into an addition differently where values no longer pass through LDS (the
-// forward rows and the columns give the same bits as their LDS forms, the split inverse
-// rows differ in the last bits).  The first pass begins with a barrier when sync_first
-// (buf still being read); the last leaves none (the caller syncs before buf is written).
+// whole-row forward rows and the columns give the same bits as their LDS forms, the split
+// inverse rows differ in the last bits).  The first pass begins with a barrier when
+// sync_first (buf still being read); the last leaves none (the caller syncs before buf is
+// written).
 template <int R, int DIR, int CAP, int NT, int SH>
 __device__ __forceinline__ void pass_first_reg(const double2 *in, double2 *buf, bool sync_first) {
   constexpr int NPER = CAP / (R * NT);
