@@ -1,6 +1,6 @@
 """Parity at the full sizes of the benchmark workloads, in the launch configuration the
-benchmark times (autotuned launch shapes, graph replay, Helmholtz solve on the second
-stream).
+benchmark times (autotuned launch shapes and stream structure, graph replay; at 8192^2 and
+2048^2 the FFT kernels' register forms, every row and column filling its form).
 
 The Helmholtz solve couples every cell, so the oracle cannot produce single cells of a
 large grid one by one.  These tests use a property that holds at any size instead: every
