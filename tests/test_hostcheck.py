@@ -40,6 +40,8 @@ SCENARIOS = [
     ("full_cols_2048_split", 1, "ars443", [(8, 2048, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("full_rows_8192_split", 1, "ars443", [(8192, 8, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("full_cols_8192_fp64", 0, "ars443", [(8, 8192, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("full_rows_two_instances_split", 1, "ars443", [(2048, 16, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                                     (2048, 8, 1e-6, 0.05, -1.0, 0.0, 5, 4)]),
     ("batch_sizes_split", 1, "ars443",
      [(n, n, 10.0 ** -(k % 7), 0.01 + 0.01 * k, -1.0, 0.0, 5, 4)
       for k, n in enumerate((64, 96, 128, 192, 64, 96, 8, 16, 24, 48))]),
