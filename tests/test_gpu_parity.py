@@ -194,14 +194,16 @@ def test_batched_heterogeneous_instances():
 
 @pytest.mark.parametrize("sides", [((2048, 16), (16, 2048)), ((8192, 8), (8, 8192)),
                                    ((3072, 8), (12, 4096), (6144, 8)),
-                                   ((4374, 8), (8, 8))])
+                                   ((4374, 8), (8, 8)), ((2048, 16), (2048, 8))])
 def test_extreme_aspect_ratios_every_fft_form(sides):
     """Long thin instances in one context: rows and columns of up to 2048 (8192) values
     take the 2048-value (8192-value) FFT forms, while the short sides put many rows
     (columns) into one workgroup; two steps against the oracle.  Rows longer than 2048
     are inverted in the split form when every nx is a multiple of 4 (radix-3 halves of 1536
     and 6, and 682 row pairs of 12 values in one workgroup, in the third case) and in the
-    whole-row form otherwise (nx = 4374 = 2 * 3^7 in the fourth).  q is ~1e-4 here, a
+    whole-row form otherwise (nx = 4374 = 2 * 3^7 in the fourth); in the fifth every row of
+    both instances fills the 2048-value form, so the row kernels run their register forms
+    over two instances in one launch.  q is ~1e-4 here, a
     cancellation of O(|u|^2) terms whose rounding the 1/h = 1300 of the long side
     amplifies, so v and q are held against max |u|^2 (kinetic floor)."""
     cases = []
