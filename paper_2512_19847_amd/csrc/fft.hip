@@ -302,6 +302,46 @@ __device__ __forceinline__ void pass_last_reg(const double2 *buf, double2 *out, 
     for (int r = 0; r < R; ++r) out[p + r * NPER] = v[r];
   }
 }
+// Several transforms filling the buffer: nb = CAP / n lines of n = 8^m values (64 <= n <
+// CAP), every pass radix 8, with their values in registers at either end.  With n8 = n / 8,
+// thread t takes butterfly j = t mod n8 of line b = t / n8 in the first pass (elements b n +
+// j + r n8, outputs at b n + 8 j + r) and in the last (Ns = n8, k = j, twiddle index j:
+// elements, and outputs, b n + j + r n8), so both ends hold element (b, j + r n8) in v[r].
+template <int DIR, int CAP, int NT, int SH, bool IN_REGS, bool OUT_REGS>
+__device__ __forceinline__ void fft_lines(double2 *v, double2 *buf, const FftPlan &P, int n,
+                                          int nb, int lg8, const double2 *tws,
+                                          bool sync_first) {
+  static_assert(CAP == 8 * NT, "eight values per thread");
+  const int n8 = 1 << lg8, b = threadIdx.x >> lg8, j = threadIdx.x & (n8 - 1);
+  int Ns = 1, ps = 0;
+  if constexpr (IN_REGS) {
+    double2 w[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) w[r] = v[r];
+    dft<8, DIR>(w);
+    if (sync_first) __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[lp<SH>(b * n + 8 * j + r)] = w[r];
+    __syncthreads();
+    Ns = 8;
+    ps = 1;
+  }
+  const int last = OUT_REGS ? P.npass - 1 : P.npass;
+  for (; ps < last; ++ps) {
+    pass<8, DIR, CAP, NT, SH>(buf, n, nb, Ns, tws, P.lb, P.tsc);
+    Ns *= 8;
+  }
+  if constexpr (OUT_REGS) {
+    double2 w[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) w[r] = buf[lp<SH>(b * n + j + r * n8)];
+    twiddle<8, DIR>(w, tws, P.lb, j * P.tsc);
+    dft<8, DIR>(w);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = w[r];
+  }
+}
+
 // Radix of the last pass of a length-n plan, n = 2^k: the plans take as many radix-8 passes
 // as fit, first, then one of 4 (k mod 3 = 2) or 2 (k mod 3 = 1).
 constexpr int last_radix_pow2(int n) {
@@ -351,7 +391,7 @@ __device__ __forceinline__ Gp<dv2> cslot(const Inst &I, int slot) {
 
 // ------------------------------------------------------------------ rows forward
 
-template <int CAP, int NT, bool DIRECT>
+template <int CAP, int NT, int FORM>
 __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
@@ -368,10 +408,18 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
   const Div dn(n);
   TwStage<NT> tw;
   tw.load(I.fx);
+  // element of slot e: t + e NT, or in the form of several lines (FORM 2) element j + e n8
+  // of line b, t = b n8 + j (the register layout of fft_lines)
+  const int lg8 = FORM == 2 ? __builtin_ctz(n) - 3 : 0;
+  auto elem = [&](int e) {
+    return FORM == 2 ? (int)(threadIdx.x >> lg8) * n + (int)(threadIdx.x & ((1u << lg8) - 1)) +
+                           (e << lg8)
+                     : (int)threadIdx.x + e * NT;
+  };
   double ra[E], rb[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
+    const int idx = elem(e);
     if (idx < cnt) {
       const int o = idx + dn.q(idx) * n;  // row 2p, column x
       ra[e] = *at_byte(R, (unsigned)o * 8u);
@@ -379,11 +427,16 @@ __global__ __launch_bounds__(NT) void k_rows_forward(const Inst *__restrict__ in
     }
   }
   tw.store(tws, I.fx);
-  if constexpr (DIRECT) {  // one row pair fills the buffer: the first pass takes the loads
+  if constexpr (FORM == 1) {  // one row pair fills the buffer: the first pass takes the loads
     double2 z[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) z[e] = make_double2(ra[e], rb[e]);
     fft_one<-1, CAP, NT, 3, true, false>(z, buf, I.fx, tws, false);
+  } else if constexpr (FORM == 2) {  // several row pairs of 8^m values fill it
+    double2 z[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = make_double2(ra[e], rb[e]);
+    fft_lines<-1, CAP, NT, 3, true, false>(z, buf, I.fx, n, np, lg8, tws, false);
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -496,7 +549,7 @@ __device__ __forceinline__ double mode_div(const Inst &I, double sig, double lx,
 // The C = cols_per_block columns kx = k0.. of the column-major spectrum, one contiguous
 // run of C ny complex values: forward FFT along y, symbol divide with the (0,0) rule,
 // inverse FFT, stored in place.  Work item (inst, k0).
-template <int CAP, int NT, bool DIRECT>
+template <int CAP, int NT, int FORM>
 __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
                                              const Work *__restrict__ work, int nwork,
                                              ArgsSolve a) {
@@ -514,6 +567,14 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   const Div dy(ny);
   TwStage<NT> tw;
   tw.load(I.fy);
+  // element of slot e (column c = e / ny, mode y): t + e NT, or in the form of several
+  // columns (FORM 2) mode j + e n8 of column b, t = b n8 + j (the register layout of fft_lines)
+  const int lg8 = FORM == 2 ? __builtin_ctz(ny) - 3 : 0;
+  auto elem = [&](int e) {
+    return FORM == 2 ? (int)(threadIdx.x >> lg8) * ny + (int)(threadIdx.x & ((1u << lg8) - 1)) +
+                           (e << lg8)
+                     : (int)threadIdx.x + e * NT;
+  };
   // PRE: the symbol values of the thread's modes travel with the data loads.  The larger
   // forms have no registers to spare for them (they would lower the waves per SIMD below
   // what the LDS allows) and load them after the transform; they hit the L2, every
@@ -524,7 +585,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   double lxh = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
+    const int idx = elem(e);
     if (idx < cnt) {
       v[e] = ldc(at_byte(S, (unsigned)idx * 16u));
       if constexpr (PRE) {
@@ -538,13 +599,17 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   tw.store(tws, I.fy);
   // one column fills the buffer: both transforms take and leave their values in registers
   // (the column-0 block puts the spectrum in LDS too, for the mirrored modes it pairs)
-  constexpr bool direct = DIRECT;
+  // (several columns of 8^m values filling it: the same with the layout of fft_lines)
+  constexpr bool direct = FORM != 0;
   if constexpr (direct) {
-    fft_one<-1, CAP, NT, 3, true, true>(v, buf, I.fy, tws, false);
+    if constexpr (FORM == 1)
+      fft_one<-1, CAP, NT, 3, true, true>(v, buf, I.fy, tws, false);
+    else
+      fft_lines<-1, CAP, NT, 3, true, true>(v, buf, I.fy, ny, C, lg8, tws, false);
     if (k0 == 0) {
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < E; ++e) buf[lp(threadIdx.x + e * NT)] = v[e];
+      for (int e = 0; e < E; ++e) buf[lp(elem(e))] = v[e];
       __syncthreads();
     }
   } else {
@@ -559,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   double2 o[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int idx = threadIdx.x + e * NT;
+    const int idx = elem(e);
     if (idx < cnt) {
       const int c = dy.q(idx), y = idx - c * ny;
       double lyy, lxx, lxn;
@@ -596,10 +661,12 @@ __global__ __launch_bounds__(NT) void k_cols(const Inst *__restrict__ insts,
   }
   if constexpr (direct) {
     // (the first inverse pass syncs before it writes: column 0 reads mirrored modes)
-    fft_one<1, CAP, NT, 3, true, true>(o, buf, I.fy, tws, true);
+    if constexpr (FORM == 1)
+      fft_one<1, CAP, NT, 3, true, true>(o, buf, I.fy, tws, true);
+    else
+      fft_lines<1, CAP, NT, 3, true, true>(o, buf, I.fy, ny, C, lg8, tws, true);
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      stc(at_byte(S, (unsigned)(threadIdx.x + e * NT) * 16u), o[e]);
+    for (int e = 0; e < E; ++e) stc(at_byte(S, (unsigned)elem(e) * 16u), o[e]);
     return;
   }
   __syncthreads();  // column 0 reads mirrored elements of other threads
@@ -808,7 +875,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ------------------------------------------------------------------ rows inverse
 
-template <int CAP, int NT, bool DIRECT>
+template <int CAP, int NT, int FORM>
 __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ insts,
                                                      const Work *__restrict__ work, int nwork,
                                                      ArgsSolve a) {
@@ -855,7 +922,20 @@ __global__ __launch_bounds__(NT) void k_rows_inverse(const Inst *__restrict__ in
   }
   __syncthreads();
   const Gp<double> T = dslot(I, a.out) + 2LL * p0 * n;
-  if constexpr (DIRECT) {  // one row pair fills the buffer: the last pass leaves it in registers
+  if constexpr (FORM == 2) {  // several row pairs of 8^m values: the layout of fft_lines
+    const int lg8 = __builtin_ctz(n) - 3;
+    double2 z[EO];
+    fft_lines<1, CAP, NT, 3, false, true>(z, buf, I.fx, n, np, lg8, tws, false);
+    const int b = threadIdx.x >> lg8, j = threadIdx.x & ((1 << lg8) - 1);
+#pragma unroll
+    for (int e = 0; e < EO; ++e) {
+      const unsigned o = (unsigned)(2 * b * n + j + (e << lg8)) * 8u;
+      *at_byte(T, o) = z[e].x;
+      *at_byte(T, o + (unsigned)n * 8u) = z[e].y;
+    }
+    return;
+  }
+  if constexpr (FORM == 1) {  // one row pair fills the buffer: the last pass leaves it in registers
     double2 z[EO];
     fft_one<1, CAP, NT, 3, false, true>(z, buf, I.fx, tws, false);
 #pragma unroll
@@ -1000,7 +1080,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // Kernel forms by LDS capacity: 0 kRowSmallCap, 1 kColMidCap, 2 kFftCap complex values;
-// D: the register form (every line of the launch fills the form's buffer) (the launch
+// D: 0 the LDS form, 1 the register form of one line filling the buffer, 2 that of several
+// lines of 8^m values filling it (the launch
 // takes ev, st, insts and a of the calling function).
 #define APDVM_FFT_FORM_D(V, D, KERNEL, WORK, NWORK)                                           \
   do {                                                                                       \
@@ -1014,52 +1095,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       APDVM_LAUNCH(ev, (KERNEL<kRowSmallCap, kRowSmallThreads, D>), dim3(NWORK),             \
                    dim3(kRowSmallThreads), st, insts, WORK, NWORK, a);                       \
   } while (0)
-#define APDVM_FFT_FORM(V, FULL, KERNEL, WORK, NWORK)                 \
+#define APDVM_FFT_FORM(V, REG, KERNEL, WORK, NWORK)                  \
   do {                                                              \
-    if (FULL)                                                       \
-      APDVM_FFT_FORM_D(V, true, KERNEL, WORK, NWORK);               \
+    if ((REG) == 1)                                                 \
+      APDVM_FFT_FORM_D(V, 1, KERNEL, WORK, NWORK);                  \
+    else if ((REG) == 2)                                            \
+      APDVM_FFT_FORM_D(V, 2, KERNEL, WORK, NWORK);                  \
     else                                                            \
-      APDVM_FFT_FORM_D(V, false, KERNEL, WORK, NWORK);              \
+      APDVM_FFT_FORM_D(V, 0, KERNEL, WORK, NWORK);                  \
   } while (0)
 
 // part 0: rows forward, 1: columns, 2: rows inverse; rowv and colv the kernel forms
 // (the smallest that holds a whole row, a whole column; rowv 3: the largest row form,
-// with the inverse rows split in halves); rowfull (colfull): every row (column) of every
+// with the inverse rows split in halves); rowreg (colreg): 1 every row (column) of every
 // instance is as long as its form holds (the largest form: kFftCap), so each workgroup
-// transforms one line with its values in registers at the ends of the transforms.
-hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+// transforms one line with its values in registers at the ends of the transforms; 2 every
+// row (column) is 8^m values, shorter, and fills the blocks of its form (the whole-line
+// kernels transform those lines the same way; the split kernels take their LDS form).
+hipError_t launch_solve_part(int part, int rowv, int colv, int rowreg, int colreg,
                              const Inst *insts, const Work *rows, int nrows, const Work *cols,
                              int ncols, const ArgsSolve &a, hipStream_t st, const Ev &ev) {
   switch (part) {
     case 0:
-      if (rowv == 3 && rowfull)  // rows of kFftCap: half the LDS, two workgroups per CU
+      if (rowv == 3 && rowreg == 1)  // rows of kFftCap: half the LDS, two workgroups per CU
         APDVM_LAUNCH(ev, (k_rows_forward_split<kRowFwdSplitThreads, kRowFwdSplitPad>), dim3(nrows),
                      dim3(kRowFwdSplitThreads), st, insts, rows, nrows, a);
       else
-        APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowfull, k_rows_forward, rows, nrows);
+        APDVM_FFT_FORM(rowv == 3 ? 2 : rowv, rowreg, k_rows_forward, rows, nrows);
       break;
     case 1:
       if (colv == 2) {  // the largest columns: half the LDS, two workgroups per CU
-        if (colfull)
+        if (colreg == 1)
           APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, kColSplitPad, true>), dim3(ncols),
                        dim3(kColSplitThreads), st, insts, cols, ncols, a);
         else
           APDVM_LAUNCH(ev, (k_cols_split<kColSplitThreads, kColSplitPad, false>), dim3(ncols),
                        dim3(kColSplitThreads), st, insts, cols, ncols, a);
       } else {
-        APDVM_FFT_FORM(colv, colfull, k_cols, cols, ncols);
+        APDVM_FFT_FORM(colv, colreg, k_cols, cols, ncols);
       }
       break;
     default:
       if (rowv == 3) {  // the largest rows, nx a multiple of 4: half the LDS, two per CU
-        if (rowfull)
+        if (rowreg == 1)
           APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad, true>),
                        dim3(nrows), dim3(kRowSplitThreads), st, insts, rows, nrows, a);
         else
           APDVM_LAUNCH(ev, (k_rows_inverse_split<kRowSplitThreads, kRowSplitPad, false>),
                        dim3(nrows), dim3(kRowSplitThreads), st, insts, rows, nrows, a);
       } else {
-        APDVM_FFT_FORM(rowv, rowfull, k_rows_inverse, rows, nrows);
+        APDVM_FFT_FORM(rowv, rowreg, k_rows_inverse, rows, nrows);
       }
       break;
   }

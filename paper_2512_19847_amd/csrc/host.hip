@@ -44,7 +44,7 @@ inline int shape_of(int rows, int threads) {
     if (kShapeRows[si] == rows && kShapeThreads[si] == threads) return si;
   return -1;
 }
-hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+hipError_t launch_solve_part(int part, int rowv, int colv, int rowreg, int colreg,
                              const Inst *, const Work *, int, const Work *, int,
                              const ArgsSolve &, hipStream_t, const Ev &);
 hipError_t launch_diagnostics(const Inst *, const Work *, int, int, int, int, int, int, int, int,
@@ -362,6 +362,23 @@ int cpb(const apdvm_config &c, int v) {
 int n_colblocks(const apdvm_config &c, int v) { return (c.nx / 2 + cpb(c, v) - 1) / cpb(c, v); }
 int n_rowblocks(const apdvm_config &c, int v) { return (c.ny / 2 + rpb(c, v) - 1) / rpb(c, v); }
 
+// Register form of the row (rows) or column FFT kernels of form v for these instances: 1 if
+// every line is the form's capacity (one line per workgroup), 2 if every line is 8^m >= 64
+// values, shorter, and the lines of every instance fill whole workgroups of cap / n lines
+// (row pairs, or columns of the half spectrum), 0 otherwise.
+int fft_reg_form(int n, const apdvm_config *cfgs, int v, bool rows) {
+  const int cap = form_cap(v);
+  bool one = true, lines = true;
+  for (int k = 0; k < n; ++k) {
+    const int len = rows ? cfgs[k].nx : cfgs[k].ny;
+    const int cnt = rows ? cfgs[k].ny / 2 : cfgs[k].nx / 2;  // row pairs or columns
+    one = one && len == cap;
+    const bool pow8 = len >= 64 && (len & (len - 1)) == 0 && __builtin_ctz(len) % 3 == 0;
+    lines = lines && pow8 && len < cap && cnt % (cap / len) == 0;
+  }
+  return one ? 1 : lines ? 2 : 0;
+}
+
 size_t inst_bytes(const apdvm_config &c, const Layout &L, size_t tsize) {
   const size_t plane = (size_t)c.nx * c.ny;
   size_t b = align_up(L.ntrans * plane * tsize);
@@ -449,7 +466,9 @@ struct apdvm_ctx {
   int nrows = 0, ncols = 0;
   int row_v = 0, col_v = 0;  // FFT kernel forms of the rows and columns (fft_form)
   bool row_split = false;    // inverse rows split in halves (largest form, every nx % 4 == 0)
-  bool row_full = false, col_full = false;  // every nx (ny) is its form's capacity
+  // FFT register forms of the rows and columns (fft_reg_form): 0 none, 1 every line is its
+  // form's capacity, 2 every line is 8^m values, shorter, filling the blocks of its form
+  int row_reg = 0, col_reg = 0;
   int shape[apdvm::kNumClasses];     // launch shape of each stencil class (kShapeRows...)
   int wo = 5, co = 4;                // WENO and central-difference orders
   std::vector<Work> tiles;  // host copy of the 64 x 16 tiles (diagnostics use per-instance ranges)
@@ -816,7 +835,7 @@ hipError_t run_launch(apdvm_ctx *c, const Launch &l, const Ev &ev = Ev{}) {
     case kCols:
     case kRowsInv:
       return launch_solve_part(l.cls - kRowsFwd, c->row_split ? 3 : c->row_v, c->col_v,
-                               c->row_full, c->col_full, c->d_inst, c->d_rows,
+                               c->row_reg, c->col_reg, c->d_inst, c->d_rows,
                                c->nrows, c->d_cols, c->ncols, l.sv, st, ev);
     case kUpdateUQ:
       return launch_update_uq<T>(si, c->wo, c->co, c->d_inst, tiles, nt, l.uq, st, ev);
@@ -1192,11 +1211,8 @@ apdvm_status apdvm_create(int32_t n, const apdvm_config *cfgs, void *dev_ws, siz
   c->row_split = c->row_v == 2;
   for (int k = 0; k < n; ++k) c->row_split = c->row_split && cfgs[k].nx % 4 == 0;
   c->col_v = col_form(n, cfgs);
-  c->row_full = c->col_full = true;
-  for (int k = 0; k < n; ++k) {
-    c->row_full = c->row_full && cfgs[k].nx == form_cap(c->row_v);
-    c->col_full = c->col_full && cfgs[k].ny == form_cap(c->col_v);
-  }
+  c->row_reg = fft_reg_form(n, cfgs, c->row_v, true);
+  c->col_reg = fft_reg_form(n, cfgs, c->col_v, false);
   for (int k = 0; k < kNumClasses; ++k) c->shape[k] = 1;
   c->wo = weno_order_of(cfgs[0]);
   c->co = central_order_of(cfgs[0]);

@@ -245,7 +245,7 @@ namespace apdvm {
 template <typename T>
 hipError_t launch_update_uq(int, int, int, const Inst *, const Work *, int, const ArgsUQ &,
                             hipStream_t, const Ev &);
-hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+hipError_t launch_solve_part(int part, int rowv, int colv, int rowreg, int colreg,
                              const Inst *, const Work *, int, const Work *, int,
                              const ArgsSolve &, hipStream_t, const Ev &);
 }  // namespace apdvm
@@ -355,14 +355,20 @@ int self_test() {
     Work *r = w + 32;  // one row block in device memory
     r[0] = Work{0, 0, 0, 0};
     ArgsSolve sa{1, 0, 1, 2};
-    launch_solve_part(0, 0, 0, false, false, &I, r, 1, r, 1, sa, nullptr, ev);
+    launch_solve_part(0, 0, 0, 0, 0, &I, r, 1, r, 1, sa, nullptr, ev);
     I.row_pairs_per_block = 1;
   });
   run("FFT register form on rows shorter than the form", true, [&] {
     Work *r = w + 32;
     r[0] = Work{0, 0, 0, 0};
     ArgsSolve sa{1, 0, 1, 2};
-    launch_solve_part(0, 0, 0, true, false, &I, r, 1, r, 1, sa, nullptr, ev);
+    launch_solve_part(0, 0, 0, 1, 0, &I, r, 1, r, 1, sa, nullptr, ev);
+  });
+  run("FFT register form of several lines on blocks they do not fill", true, [&] {
+    Work *r = w + 32;
+    r[0] = Work{0, 0, 0, 0};
+    ArgsSolve sa{1, 0, 1, 2};
+    launch_solve_part(0, 0, 0, 2, 0, &I, r, 1, r, 1, sa, nullptr, ev);
   });
   std::printf("self-test: %d of %d planted cases judged correctly\n", caught, cases);
   for (void *p : {tb, db, tw, lam, ip, wp}) hipFree(p);

@@ -399,7 +399,7 @@ hipError_t launch_div_u(int co, const Inst *insts, const Work *tiles, int nwork,
 
 // ---------------------------------------------------------------- Helmholtz solve
 
-hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool colfull,
+hipError_t launch_solve_part(int part, int rowv, int colv, int rowreg, int colreg,
                              const Inst *insts, const Work *rows, int nrows, const Work *cols,
                              int ncols, const ArgsSolve &a, hipStream_t st, const Ev &) {
   if (part < 0 || part > 2 || rowv < 0 || rowv > 3 || colv < 0 || colv > 2)
@@ -410,12 +410,14 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
     const Work *work = is_rows ? rows : cols;
     const int nwork = is_rows ? nrows : ncols;
     const int v = is_rows ? rowv : colv;
-    const bool full = is_rows ? rowfull : colfull;
+    const int reg = is_rows ? rowreg : colreg;
+    if (reg < 0 || reg > 2) fail("solve: register form %d", reg);
+    const bool full = reg == 1;
     const int cap = v == 0 ? kRowSmallCap : v == 1 ? kColMidCap : kFftCap;  // v 3: halved
-    static std::set<std::tuple<const void *, unsigned long long, int, int, int, bool>> walked;
+    static std::set<std::tuple<const void *, unsigned long long, int, int, int, int>> walked;
     const bool walk =
         !in_device(work, (size_t)nwork * sizeof(Work)) ||
-        walked.insert({insts, table_hash(work, nwork), nwork, part, v, full}).second;
+        walked.insert({insts, table_hash(work, nwork), nwork, part, v, reg}).second;
     if (walk) check_remap(nwork);
     std::set<int> seen;
     std::map<int, std::vector<char>> cover;
@@ -465,6 +467,20 @@ hipError_t launch_solve_part(int part, int rowv, int colv, bool rowfull, bool co
             P.npass < 2 || P.radix[0] != 8 || P.radix[P.npass - 1] != last)
           fail("solve part %d: register form on instance %d (line %d, form %d, %d lines, plan "
                "%d in %d passes)", part, w->inst, n_line, cap, cnt_lines, P.n, P.npass);
+      }
+      if (reg == 2 && !split_cols && !split_rows) {
+        // several lines of 8^m values fill the block, and every pass of their plan is radix 8
+        const int n_line = is_rows ? I.nx : I.ny;
+        const FftPlan &P = is_rows ? I.fx : I.fy;
+        int k = 0;
+        while ((1 << k) < n_line) ++k;
+        bool radix8 = P.npass >= 2 && P.n == n_line;
+        for (int q = 0; q < P.npass && radix8; ++q) radix8 = P.radix[q] == 8;
+        if ((1 << k) != n_line || k % 3 || n_line < 64 || n_line >= cap ||
+            cnt_lines * n_line != cap || !radix8)
+          fail("solve part %d: register form of several lines on instance %d (line %d, form "
+               "%d, %d lines, plan %d in %d passes)", part, w->inst, n_line, cap, cnt_lines,
+               P.n, P.npass);
       }
       auto &cv = cover[w->inst];
       if (cv.empty()) cv.assign(lines, 0);

@@ -42,6 +42,10 @@ SCENARIOS = [
     ("full_cols_8192_fp64", 0, "ars443", [(8, 8192, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("full_rows_two_instances_split", 1, "ars443", [(2048, 16, 0.05, 0.05, -1.0, 0.0, 5, 4),
                                                      (2048, 8, 1e-6, 0.05, -1.0, 0.0, 5, 4)]),
+    # rows (columns) of 8^m values filling the blocks of a larger form: several per workgroup
+    ("lines_512_rows_fp64", 0, "ars443", [(512, 16, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                          (512, 32, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("lines_64_cols_split", 1, "ars443", [(32, 64, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("batch_sizes_split", 1, "ars443",
      [(n, n, 10.0 ** -(k % 7), 0.01 + 0.01 * k, -1.0, 0.0, 5, 4)
       for k, n in enumerate((64, 96, 128, 192, 64, 96, 8, 16, 24, 48))]),
@@ -84,9 +88,10 @@ def test_every_launch_in_bounds_under_asan(checker):
 def test_checks_catch_planted_mistakes(checker):
     """The checks are not vacuous: launches with a duplicated tile, a tile off the grid, a
     slot beyond its arena, an output that is also an input, a float launch on a float64
-    arena, an FFT row block beyond its LDS form and the FFT register form on rows shorter
-    than that form are each reported, and the correct launch is not."""
+    arena, an FFT row block beyond its LDS form, the FFT register form on rows shorter than
+    that form and the register form of several lines on blocks they do not fill are each
+    reported, and the correct launch is not."""
     r = subprocess.run([checker, "--self-test"], capture_output=True, text=True, timeout=120)
     print(r.stdout, r.stderr)
     assert r.returncode == 0, r.stderr
-    assert "8 of 8 planted cases judged correctly" in r.stdout
+    assert "9 of 9 planted cases judged correctly" in r.stdout
