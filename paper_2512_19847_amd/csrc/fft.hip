@@ -387,7 +387,11 @@ __device__ __forceinline__ Gp<dv2> cslot(const Inst &I, int slot) {
 // Each kernel below stages its tile in two phases: every thread first issues all of its
 // global loads (data, twiddle table and, in the small column form, the symbol values of
 // the modes it will scale), then writes them to LDS, so one memory round trip covers the
-// whole tile.
+// whole tile.  The whole-line kernels come in three forms (FORM): 0 in LDS from end to
+// end; 1 one line filling the buffer, its first pass taking the loaded values and its last
+// leaving its outputs in registers (fft_one); 2 the same for several lines of 8^m values
+// filling it (fft_lines).  The host takes 1 or 2 only when every line of the launch
+// qualifies (fft_reg_form).
 
 // ------------------------------------------------------------------ rows forward
 
