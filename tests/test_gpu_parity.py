@@ -194,7 +194,8 @@ def test_batched_heterogeneous_instances():
 
 @pytest.mark.parametrize("sides", [((2048, 16), (16, 2048)), ((8192, 8), (8, 8192)),
                                    ((3072, 8), (12, 4096), (6144, 8)),
-                                   ((4374, 8), (8, 8)), ((2048, 16), (2048, 8))])
+                                   ((4374, 8), (8, 8)), ((2048, 16), (2048, 8)),
+                                   ((512, 16), (64, 32))])
 def test_extreme_aspect_ratios_every_fft_form(sides):
     """Long thin instances in one context: rows and columns of up to 2048 (8192) values
     take the 2048-value (8192-value) FFT forms, while the short sides put many rows
@@ -203,7 +204,9 @@ def test_extreme_aspect_ratios_every_fft_form(sides):
     and 6, and 682 row pairs of 12 values in one workgroup, in the third case) and in the
     whole-row form otherwise (nx = 4374 = 2 * 3^7 in the fourth); in the fifth every row of
     both instances fills the 2048-value form, so the row kernels run their register forms
-    over two instances in one launch.  q is ~1e-4 here, a
+    over two instances in one launch; in the sixth the rows of 512 and of 64 values fill
+    the 1024-value form's workgroups two and sixteen at a time (the register form of several
+    lines, with each instance's own line length).  q is ~1e-4 here, a
     cancellation of O(|u|^2) terms whose rounding the 1/h = 1300 of the long side
     amplifies, so v and q are held against max |u|^2 (kinetic floor)."""
     cases = []

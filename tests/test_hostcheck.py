@@ -46,6 +46,8 @@ SCENARIOS = [
     ("lines_512_rows_fp64", 0, "ars443", [(512, 16, 0.05, 0.05, -1.0, 0.0, 5, 4),
                                           (512, 32, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("lines_64_cols_split", 1, "ars443", [(32, 64, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
+    ("lines_512_and_64_rows_split", 1, "ars443", [(512, 16, 0.05, 0.05, -1.0, 0.0, 5, 4),
+                                                   (64, 32, 0.05, 0.05, -1.0, 0.0, 5, 4)]),
     ("batch_sizes_split", 1, "ars443",
      [(n, n, 10.0 ** -(k % 7), 0.01 + 0.01 * k, -1.0, 0.0, 5, 4)
       for k, n in enumerate((64, 96, 128, 192, 64, 96, 8, 16, 24, 48))]),
